@@ -1,0 +1,115 @@
+"""Plants plausible mistakes in the oracle (on the CPU only) and checks that
+the pins in the other oracle tests catch each of them."""
+import numpy as np
+import pytest
+
+import test_oracle_basis as TB
+import test_oracle_gradient as TG
+import test_oracle_hamiltonian as TH
+import test_oracle_propagation as TP
+from oracle import basis as B
+from oracle import exact as X
+from oracle import hamiltonian as Hm
+from oracle import krylov as K
+from oracle import model as M
+
+_orig_bonds = M.bonds
+_orig_fields = M.fields
+_orig_diagonal = Hm.diagonal
+_orig_hop = Hm.hop_targets
+_orig_evolve = X.evolve
+_orig_amp = X.survival_amplitude
+_orig_nbp = B.next_bit_permutation
+_orig_first = B.first_int
+
+
+def _fails(*checks):
+    """True when at least one of the pin checks raises AssertionError."""
+    for c in checks:
+        try:
+            c()
+        except AssertionError:
+            return True
+    return False
+
+
+def _no_wrap(L, pbc):
+    return _orig_bonds(L, False)
+
+
+def _field_shift(L, h, beta, phi):
+    return _orig_fields(L + 1, h, beta, phi)[1:]
+
+
+def _half_jz(states, L, pbc, jz, h):
+    return _orig_diagonal(states, L, pbc, 0.5 * jz, h)
+
+
+def _field_sign(states, L, pbc, jz, h):
+    zz = _orig_diagonal(states, L, pbc, jz, np.zeros_like(np.asarray(h)))
+    return zz - (_orig_diagonal(states, L, pbc, 0.0, h))
+
+
+def _reversed_time(H, psi0, times, eigsys=None):
+    return _orig_evolve(H, psi0, -np.asarray(times, dtype=float), eigsys)
+
+
+def _transposed_U(H, psi0, times, eigsys=None):
+    w, U = X.eig(H) if eigsys is None else eigsys
+    coef = U @ np.asarray(psi0, dtype=np.complex128)
+    ph = np.exp(-1j * np.outer(np.atleast_1d(times), w))
+    return (ph * coef[None, :]) @ U.T
+
+
+def _bad_nbp(v):
+    t = (v | (v - 1)) + 1
+    return t | ((((t & -t) // (v & -v)) >> 2) - 1)
+
+
+def _bad_first(L, N, start):
+    return _orig_first(L, N, max(start - 1, 0)) if start == 3 else _orig_first(L, N, start)
+
+
+def _hop_full(jxy):
+    return jxy
+
+
+def _hop_negative(jxy):
+    return -0.5 * jxy
+
+
+PLANTS = {
+    "hopping jxy instead of jxy/2": [(Hm, "hop_amplitude", _hop_full)],
+    "hopping sign flipped": [(Hm, "hop_amplitude", _hop_negative)],
+    "dropped wrap bond": [(M, "bonds", _no_wrap)],
+    "field on the wrong site": [(M, "fields", _field_shift)],
+    "zz coupling halved": [(Hm, "diagonal", _half_jz)],
+    "field sign flipped": [(Hm, "diagonal", _field_sign)],
+    "time runs backwards": [(X, "evolve", _reversed_time)],
+    "transposed eigenvectors": [(X, "evolve", _transposed_U)],
+    "wrong refill shift in Algorithm 2": [(B, "next_bit_permutation", _bad_nbp)],
+    "off-by-one section start": [(B, "first_int", _bad_first)],
+}
+
+CHECKS = [
+    TB.test_paper_example_L4_N2, TB.test_alg2_matches_scan, TB.test_first_int_is_kth_state,
+    TB.test_sections_alg1_alg3_rebuild_basis,
+    TH.test_heisenberg_ring_L4_spectrum, TH.test_two_level_amplitude,
+    lambda: TH.test_neel_energy_and_first_lanczos_norm(8, True),
+    TH.test_hopping_sign_on_odd_ring,
+    lambda: TP.test_free_fermion_determinant_matches_dense(8, True),
+    TP.test_norm_energy_conservation_and_time_reversal, TP.test_expm_multiply_matches_dense,
+    TP.test_krylov_converged_matches_exact,
+    lambda: TB.test_fields_special_beta(),
+]
+
+
+@pytest.mark.parametrize("name", sorted(PLANTS))
+def test_planted_mistake_is_caught(name, monkeypatch):
+    for mod, attr, fn in PLANTS[name]:
+        monkeypatch.setattr(mod, attr, fn)
+    assert _fails(*CHECKS), f"no pin caught: {name}"
+
+
+def test_unplanted_oracle_passes_all_checks():
+    assert not _fails(*CHECKS)

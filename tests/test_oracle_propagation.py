@@ -1,0 +1,172 @@
+"""Pins of the oracle's propagators: conservation laws, the free-fermion closed
+form, a library routine, short-time expansion and the paper's Krylov error bound."""
+import numpy as np
+import pytest
+
+from oracle import basis as B
+from oracle import exact as X
+from oracle import freefermion as FF
+from oracle import hamiltonian as Hm
+from oracle import krylov as K
+from oracle import midsize as MS
+from oracle import model as M
+from workloads import BETA_GOLDEN, random_complex, random_fields
+
+
+def _setup(L, pbc, jxy=1.0, jz=1.0, h=None):
+    N = L // 2
+    if h is None:
+        h = M.fields(L, 1.5, BETA_GOLDEN, 0.4)
+    st = B.sector_states(L, N)
+    r0 = int(B.lookup(st, [M.neel_state(L)])[0])
+    return N, h, st, r0, Hm.build_dense(L, N, pbc, jxy, jz, h)
+
+
+def test_norm_energy_conservation_and_time_reversal():
+    L = 10
+    N, h, st, r0, H = _setup(L, True)
+    psi0 = random_complex(len(st), 7)
+    psi0 /= np.linalg.norm(psi0)
+    t = np.array([0.0, 0.3, 2.0, 11.0])
+    psis = X.evolve(H, psi0, t)
+    E0 = np.vdot(psi0, H @ psi0).real
+    for p in psis:
+        assert np.linalg.norm(p) == pytest.approx(1.0, abs=1e-13)
+        assert np.vdot(p, H @ p).real == pytest.approx(E0, abs=1e-12)
+    # F(-t) = F(t) for a real initial state and real H
+    F_p = X.survival_probability(H, r0, t)
+    F_m = X.survival_probability(H, r0, -t)
+    assert np.allclose(F_p, F_m, atol=1e-14)
+    assert F_p[0] == pytest.approx(1.0, abs=1e-14)
+
+
+@pytest.mark.parametrize("pbc", [False, True])
+@pytest.mark.parametrize("L", [6, 8, 10])
+def test_free_fermion_determinant_matches_dense(L, pbc):
+    h = random_fields(L, 11 + L)
+    N, _, st, r0, H = _setup(L, pbc, jxy=1.0, jz=0.0, h=h)
+    t = np.linspace(0, 12, 25)
+    F_dense = X.survival_probability(H, r0, t)
+    F_ff = FF.survival_probability(L, N, pbc, 1.0, h, M.neel_state(L), t)
+    assert np.max(np.abs(F_dense - F_ff)) < 1e-12
+
+
+def test_free_fermion_other_fillings():
+    # odd particle number on a ring flips the boundary sign relative to even
+    for L, N in [(7, 3), (8, 3), (9, 4)]:
+        h = random_fields(L, L)
+        st = B.sector_states(L, N)
+        s = int(st[len(st) // 3])
+        H = Hm.build_dense(L, N, True, 1.0, 0.0, h)
+        r0 = int(B.lookup(st, [s])[0])
+        t = np.linspace(0, 5, 11)
+        assert np.allclose(X.survival_probability(H, r0, t),
+                           FF.survival_probability(L, N, True, 1.0, h, s, t), atol=1e-12)
+
+
+def test_short_time_expansion():
+    # F(t) = 1 - beta0^2 t^2 + O(t^4) with beta0 the first Lanczos norm of e_r0
+    L = 10
+    N, h, st, r0, H = _setup(L, True)
+    e = np.zeros(len(st)); e[r0] = 1
+    E0 = H[r0, r0]
+    beta0sq = np.sum((H @ e - E0 * e) ** 2)
+    for t in [1e-3, 3e-3]:
+        F = X.survival_probability(H, r0, [t])[0]
+        assert (1 - F) / t ** 2 == pytest.approx(beta0sq, rel=1e-4)
+
+
+def test_expm_multiply_matches_dense():
+    L = 12
+    N, h, st, r0, H = _setup(L, False)
+    t = np.array([0.0, 0.5, 1.7, 6.0])
+    Hc = Hm.build_csr(L, N, False, 1.0, 1.0, h)
+    psi0 = np.zeros(len(st), complex); psi0[r0] = 1
+    a = MS.evolve(Hc, psi0, t)
+    b = X.evolve(H, psi0, t)
+    assert np.max(np.abs(a - b)) < 1e-12
+    assert np.allclose(MS.survival_probability(Hc, r0, t), X.survival_probability(H, r0, t), atol=1e-12)
+
+
+def test_autocorrelation_simple_cases():
+    t = np.linspace(0, 4, 401)
+    assert np.allclose(X.autocorrelation(t, np.full_like(t, 0.25)), 0.25)
+    C = X.autocorrelation(t, np.exp(-t))
+    assert C[-1] == pytest.approx((1 - np.exp(-4)) / 4, rel=1e-5)
+
+
+def test_krylov_converged_matches_exact():
+    L = 10
+    N, h, st, r0, H = _setup(L, True)
+    psi0 = np.zeros(len(st), complex); psi0[r0] = 1
+    dt, steps = 0.1, 20
+    psi, F = K.evolve(lambda v: H @ v, psi0, dt, steps, 30, r0=r0)
+    t = dt * np.arange(1, steps + 1)
+    assert np.max(np.abs(F - X.survival_probability(H, r0, t))) < 1e-12
+    assert np.max(np.abs(psi - X.evolve(H, psi0, [dt * steps])[0])) < 1e-11
+
+
+def test_krylov_projection_is_tridiagonal_real():
+    # Hermitian H: the Arnoldi matrix is tridiagonal with real diagonal and
+    # positive real subdiagonal (the Lanczos coefficients), alpha_0 = E0.
+    L = 10
+    N, h, st, r0, H = _setup(L, True)
+    psi0 = np.zeros(len(st), complex); psi0[r0] = 1
+    V, A, beta0, hn, mu = K.arnoldi(lambda v: H @ v, psi0, 12)
+    assert mu == 12
+    assert np.allclose(np.triu(A, 2), 0, atol=1e-12)
+    assert np.allclose(A.imag, 0, atol=1e-13)
+    sub = np.diag(A, -1).real
+    assert np.all(sub > 0)
+    assert np.allclose(np.diag(A, 1), sub, atol=1e-12)
+    assert A[0, 0].real == pytest.approx(H[r0, r0], abs=1e-13)
+    assert sub[0] == pytest.approx(0.5 * np.sqrt(L), abs=1e-13)   # all L ring bonds anti-aligned
+    assert np.allclose(V.conj().T @ V, np.eye(mu), atol=1e-12)
+
+
+def test_krylov_breakdown_cases():
+    # invariant subspace: an eigenvector gives m_used = 1 and F = 1
+    L = 8
+    N, h, st, r0, H = _setup(L, True)
+    w, U = np.linalg.eigh(H)
+    psi, info = K.expm_step(lambda v: H @ v, U[:, 3].astype(complex), 0.7, 30)
+    assert info["m_used"] == 1
+    assert abs(np.vdot(U[:, 3], psi)) ** 2 == pytest.approx(1.0, abs=1e-14)
+    # D < m: the Krylov space is the whole sector and the step is exact
+    N4, h4, st4, r04, H4 = _setup(4, True)
+    psi0 = np.zeros(6, complex); psi0[r04] = 1
+    psi, info = K.expm_step(lambda v: H4 @ v, psi0, 1.3, 30)
+    assert info["m_used"] <= 6
+    assert np.allclose(psi, X.evolve(H4, psi0, [1.3])[0], atol=1e-13)
+
+
+def test_krylov_error_within_paper_bound():
+    # Sec. 2: the Krylov error behaves like e^(m - t||A||) (t||A||/m)^m once m
+    # exceeds t||A||; published forms of this bound carry a constant <= 12.
+    L = 10
+    N, h, st, r0, H = _setup(L, True)
+    normA = np.max(np.abs(np.linalg.eigvalsh(H)))
+    psi0 = np.zeros(len(st), complex); psi0[r0] = 1
+    checked = 0
+    for m in range(4, 24, 2):
+        for t in [0.05, 0.1, 0.2, 0.4]:
+            if m < t * normA:
+                continue
+            psi, _ = K.expm_step(lambda v: H @ v, psi0, t, m)
+            err = np.linalg.norm(psi - X.evolve(H, psi0, [t])[0])
+            assert err <= 12 * K.error_bound(m, t, normA) + 1e-13
+            checked += 1
+    assert checked > 20
+
+
+def test_saad_estimate_tracks_error():
+    L = 10
+    N, h, st, r0, H = _setup(L, True)
+    psi0 = np.zeros(len(st), complex); psi0[r0] = 1
+    # Before roundoff takes over, the estimate bounds the true error from
+    # above, and not by more than two orders of magnitude.
+    for dt in [0.2, 0.5]:
+        for m in [4, 6, 8, 10, 12]:
+            psi, info = K.expm_step(lambda v: H @ v, psi0, dt, m)
+            err = np.linalg.norm(psi - X.evolve(H, psi0, [dt])[0])
+            assert err < info["err_est"] < err * 100
