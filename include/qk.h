@@ -1,0 +1,210 @@
+/*
+ * qk.h -- C ABI of libqkrylov: Krylov-subspace time evolution of a spin-1/2
+ * XXZ chain with on-site fields in a fixed particle-number sector, on one
+ * AMD Instinct MI355X (gfx950).
+ *
+ * Method: Brenes, Varma, Scardicchio, Girotto, "Massively parallel
+ * implementation and approaches to simulate quantum dynamics using Krylov
+ * subspace techniques" (arXiv:1704.02770).  Section / equation / algorithm
+ * references below are to that paper.
+ *
+ * Conventions shared by every entry point
+ *   - Model (Sec. 2, Eq. (1), read in spin language):
+ *       H = sum_b [ (jxy/2)(S+_a S-_c + S-_a S+_c) + jz S^z_a S^z_c ] + sum_i h_i S^z_i
+ *     with S = sigma/2.  Site i (1-based) is bit i-1 of a state integer.  Open
+ *     chains have the bonds (0,1)..(L-2,L-1); periodic chains add (L-1,0)
+ *     (so a 2-site ring carries its pair twice).  The hopping is +jxy/2.
+ *   - Basis (Sec. 2 "Basis representation"; Sec. 3 Algorithm 2): the states
+ *     with n_up set bits out of L, in ascending integer order; row r of every
+ *     vector belongs to the r-th such integer.  D = C(L, n_up).
+ *   - Vectors are device memory holding interleaved complex numbers (real,
+ *     imaginary): QK_C128 = 2 x double per element (16 B, 16-B aligned),
+ *     QK_C64 = 2 x float (8 B, 8-B aligned).  A batch of B problems that
+ *     share one basis is stored row-major [D][B] (batch index fastest).
+ *   - Every call that takes `stream` enqueues its device work on that
+ *     hipStream_t (NULL = the legacy default stream) and returns without
+ *     waiting, unless stated otherwise.  The caller keeps every buffer alive
+ *     until that work has completed.
+ *   - Errors: every function returns qk_status; arguments are checked before
+ *     any device work is enqueued, so an argument error leaves all buffers
+ *     untouched.  qk_last_error() returns a thread-local text for the last
+ *     failing call on the calling thread.  Nothing aborts or throws across
+ *     this boundary.
+ *   - Handles (qk_basis, qk_ham, qk_krylov) are created on the current HIP
+ *     device, own their device memory, and are released only by the matching
+ *     *_destroy (which accepts NULL and synchronises the device first).  A
+ *     handle may be used by one stream at a time; calls on a handle from
+ *     another device return QK_EINVAL.
+ */
+#ifndef QK_H
+#define QK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define QK_ABI_VERSION 1
+#define QK_MAX_L 32          /* states are 32-bit integers */
+#define QK_MAX_M 64          /* Krylov dimension limit (one wavefront per projected problem) */
+#define QK_MAX_BATCH 64      /* problems per batched handle */
+
+typedef enum {
+  QK_OK = 0,
+  QK_EINVAL = 1,        /* bad argument; nothing was enqueued */
+  QK_ENOMEM = 2,        /* device allocation failed */
+  QK_EHIP = 3,          /* a HIP runtime call failed (text in qk_last_error) */
+  QK_EUNSUPPORTED = 4,  /* valid request outside what this build implements */
+  QK_ENUMERIC = 5       /* non-finite Lanczos coefficient detected */
+} qk_status;
+
+typedef enum { QK_C128 = 0, QK_C64 = 1 } qk_dtype;
+typedef enum { QK_MATFREE = 0, QK_CSR = 1 } qk_ham_mode;
+
+/* Version of this header the library was built from (QK_ABI_VERSION). */
+int qk_abi_version(void);
+
+/* Thread-local text of the last error on this thread ("" if none).  The
+ * pointer stays valid until the next qk_* call on the same thread. */
+const char* qk_last_error(void);
+
+/*
+ * Quasiperiodic on-site fields of Eq. (1): h_out[b*L + (i-1)] =
+ * h * cos(2*pi*beta*i + phi[b]) for i = 1..L and b = 0..batch-1.
+ * Host arrays; runs on the host, no device work.  Errors: QK_EINVAL for
+ * L outside [1, QK_MAX_L], batch < 1, NULL pointers or non-finite inputs.
+ */
+qk_status qk_fields_quasiperiodic(int32_t L, double h, double beta, const double* phi,
+                                  int32_t batch, double* h_out);
+
+/* ---------------------------------------------------------------- basis */
+typedef struct qk_basis qk_basis;
+
+/*
+ * Builds the sorted sector basis on the device (Sec. 3, Algorithms 2 and 3:
+ * every chunk of rows starts from the unranked first state of its section
+ * and advances by the next-bit-permutation), plus the binomial rank table.
+ * 2 <= L <= QK_MAX_L, 0 < n_up < L.  *out receives the handle; the build is
+ * enqueued on `stream`.  Errors: QK_EINVAL, QK_ENOMEM, QK_EHIP.
+ */
+qk_status qk_basis_build(int32_t L, int32_t n_up, void* stream, qk_basis** out);
+
+/* Sector dimension D = C(L, n_up) (host value, no device work). */
+qk_status qk_basis_dim(const qk_basis* b, int64_t* D);
+
+/* L and n_up of a basis (host values). */
+qk_status qk_basis_shape(const qk_basis* b, int32_t* L, int32_t* n_up);
+
+/* Copies the D sorted states (uint32) into caller device memory dst_device. */
+qk_status qk_basis_states(const qk_basis* b, uint32_t* dst_device, void* stream);
+
+/*
+ * Row index of each of n host states (Sec. 3: lookup of the row of a state;
+ * computed on the device by the combinatorial number system, which equals the
+ * position in the sorted basis).  idx_host[i] = -1 when states_host[i] does
+ * not have n_up set bits below bit L.  Synchronous (waits for its own work on
+ * the legacy default stream).  n may be 0.
+ */
+qk_status qk_basis_rank(const qk_basis* b, const uint64_t* states_host, int64_t n, int64_t* idx_host);
+
+void qk_basis_destroy(qk_basis* b);
+
+/* ---------------------------------------------------------- Hamiltonian */
+typedef struct {
+  double jxy;      /* hopping: off-diagonal entry jxy/2 (Eq. (1) t = jxy/2) */
+  double jz;       /* zz coupling (Eq. (1) V = jz) */
+  int32_t pbc;     /* 0 open chain, 1 periodic chain */
+  int32_t mode;    /* QK_MATFREE (rows generated on the fly) or QK_CSR */
+} qk_ham_params;
+
+typedef struct qk_ham qk_ham;
+
+/*
+ * Hamiltonian of Eq. (1) on basis `b` (Sec. 3, "Hamiltonian matrix
+ * construction") for `batch` field sets h_host[batch][L] (host doubles,
+ * copied).  QK_MATFREE generates every row on the fly in the apply kernels;
+ * QK_CSR additionally stores the column indices of the off-diagonal entries
+ * after an exact counting pass (the exact preallocation of Sec. 3); allowed
+ * for D <= 2^24.  The basis must outlive the Hamiltonian.
+ * Errors: QK_EINVAL (NULL, batch outside [1, QK_MAX_BATCH], non-finite
+ * parameters, CSR too large), QK_ENOMEM, QK_EHIP.
+ */
+qk_status qk_ham_create(const qk_basis* b, const qk_ham_params* p, const double* h_host,
+                        int32_t batch, void* stream, qk_ham** out);
+
+/* Replaces the field sets (same batch count).  Enqueued on `stream`. */
+qk_status qk_ham_set_fields(qk_ham* H, const double* h_host, int32_t batch, void* stream);
+
+/* D, batch and mode of a Hamiltonian (host values). */
+qk_status qk_ham_shape(const qk_ham* H, int64_t* D, int32_t* batch, int32_t* mode);
+
+/*
+ * y = H x for every batch item (problem k uses field set k): x, y are [D][B]
+ * device arrays of `dtype`; x and y must not overlap (QK_EINVAL).  QK_C128
+ * accumulates in double, QK_C64 in float.
+ */
+qk_status qk_ham_apply(const qk_ham* H, const void* x, void* y, int32_t dtype, void* stream);
+
+void qk_ham_destroy(qk_ham* H);
+
+/* --------------------------------------------------------------- Krylov */
+typedef struct {
+  int32_t m_used;   /* Krylov dimension actually used (< m after an invariant subspace) */
+  int32_t status;   /* QK_OK or QK_ENUMERIC for this problem */
+  double err_est;   /* a-posteriori estimate ||psi|| beta_m |[exp(-i dt T)]_{m,1}| */
+  double beta0;     /* ||psi|| at the start of the step */
+} qk_step_info;
+
+typedef struct qk_krylov qk_krylov;
+
+/*
+ * Workspace for Krylov steps of dimension m (1 <= m <= QK_MAX_M) on
+ * Hamiltonian H (Sec. 2 "Krylov subspace methods"): m device vectors of
+ * D x batch elements of `dtype`, the Lanczos coefficients and the reduction
+ * scratch.  reorth: 0 = none (plain three-term recurrence), 1 = local (the
+ * new vector is also orthogonalised against the previous one).  The
+ * Hamiltonian must outlive the workspace.
+ */
+qk_status qk_krylov_create(const qk_ham* H, int32_t m, int32_t dtype, int32_t reorth, qk_krylov** out);
+
+/*
+ * One step psi <- exp(-i dt H) psi for every batch item (Sec. 2: psi(t) ~
+ * ||psi|| V_m exp(-i dt A_m) e_1 with A_m the projection of H on the Krylov
+ * space of psi, built here by the Lanczos recurrence since H is Hermitian).
+ * psi is a [D][B] device array of the workspace dtype, updated in place.
+ * When the recurrence reaches an invariant subspace it stops early
+ * (m_used < m; the result is then exact up to rounding) -- not an error.
+ * info_host (NULL or an array of B entries) is filled after the step has
+ * completed, which makes the call synchronous; with info_host == NULL the
+ * call returns after enqueueing.  Errors: QK_EINVAL (dt not finite, NULL
+ * psi), QK_ENUMERIC (only reported when info_host != NULL), QK_EHIP.
+ */
+qk_status qk_krylov_expm_step(qk_krylov* k, void* psi, double dt, void* stream, qk_step_info* info_host);
+
+/*
+ * Lanczos coefficients of the last completed step for batch item `item`
+ * (synchronous): alpha[0..m_used-1], beta[0..m_used-1] (beta[j] = norm of
+ * the (j+1)-th residual), *m_used.  Arrays hold at least m entries.
+ */
+qk_status qk_krylov_coefficients(const qk_krylov* k, int32_t item, double* alpha, double* beta,
+                                 int32_t* m_used);
+
+void qk_krylov_destroy(qk_krylov* k);
+
+/* ----------------------------------------------------------- observable */
+/*
+ * Survival (return) probability of Sec. 4, F = |<psi0|psi>|^2, for every
+ * batch item: P_device[k] (device double array of B entries).  With
+ * psi0 == NULL the initial state is the basis state of row r0 and
+ * F = |psi[r0]|^2; otherwise psi0 is a [D][B] array of `dtype` and the
+ * overlap is reduced in double precision.  Asynchronous.
+ */
+qk_status qk_return_prob(const qk_basis* b, int64_t r0, const void* psi0, const void* psi,
+                         int32_t dtype, int32_t batch, double* P_device, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* QK_H */

@@ -1,0 +1,235 @@
+"""Python binding of libqkrylov (include/qk.h): Krylov time evolution of a
+spin-1/2 XXZ chain with on-site fields on an MI355X (arXiv:1704.02770).
+
+Every function here has the name of the C entry point it calls and only
+marshals arguments: torch tensors supply device memory (their data pointers)
+and streams (torch's current HIP stream); all computation runs in the HIP
+kernels of the library.  Failures raise QkError with the library's message.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+import torch
+
+from . import _native
+from ._native import HamParams, StepInfo, lib
+
+QK_OK, QK_EINVAL, QK_ENOMEM, QK_EHIP, QK_EUNSUPPORTED, QK_ENUMERIC = range(6)
+QK_C128, QK_C64 = 0, 1
+QK_MATFREE, QK_CSR = 0, 1
+
+_DTYPE = {torch.complex128: QK_C128, torch.complex64: QK_C64}
+TORCH_DTYPE = {QK_C128: torch.complex128, QK_C64: torch.complex64}
+
+
+class QkError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        msg = lib.qk_last_error().decode(errors="replace")
+        super().__init__(f"{where} failed with status {status}: {msg}")
+
+
+def _check(status: int, where: str) -> None:
+    if status != QK_OK:
+        raise QkError(status, where)
+
+
+def _stream(stream) -> C.c_void_p:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+
+
+def _dptr(t: torch.Tensor) -> C.c_void_p:
+    if not t.is_cuda:
+        raise ValueError("expected a device tensor")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    return C.c_void_p(t.data_ptr())
+
+
+def dtype_code(t: torch.Tensor) -> int:
+    try:
+        return _DTYPE[t.dtype]
+    except KeyError:
+        raise ValueError(f"unsupported dtype {t.dtype}") from None
+
+
+class _Handle:
+    """Owns one library handle; released by the matching *_destroy."""
+    _destroy = None
+
+    def __init__(self, ptr: C.c_void_p, keep=()):
+        self.ptr = ptr
+        self._keep = keep   # objects that must outlive this handle
+
+    def close(self):
+        if self.ptr is not None and self.ptr.value:
+            type(self)._destroy(self.ptr)
+        self.ptr = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Basis(_Handle):
+    _destroy = staticmethod(lib.qk_basis_destroy)
+
+
+class Ham(_Handle):
+    _destroy = staticmethod(lib.qk_ham_destroy)
+
+
+class Krylov(_Handle):
+    _destroy = staticmethod(lib.qk_krylov_destroy)
+
+
+def qk_abi_version() -> int:
+    return int(lib.qk_abi_version())
+
+
+def qk_fields_quasiperiodic(L: int, h: float, beta: float, phi) -> np.ndarray:
+    """Fields h*cos(2*pi*beta*i + phi_b), i = 1..L, for every phase: shape (batch, L)."""
+    phi = np.ascontiguousarray(np.atleast_1d(phi), dtype=np.float64)
+    out = np.empty((len(phi), L), dtype=np.float64)
+    _check(lib.qk_fields_quasiperiodic(L, h, beta, phi.ctypes.data_as(C.POINTER(C.c_double)), len(phi),
+                                       out.ctypes.data_as(C.POINTER(C.c_double))), "qk_fields_quasiperiodic")
+    return out
+
+
+def qk_basis_build(L: int, n_up: int, stream=None) -> Basis:
+    out = C.c_void_p()
+    _check(lib.qk_basis_build(L, n_up, _stream(stream), C.byref(out)), "qk_basis_build")
+    return Basis(out)
+
+
+def qk_basis_dim(b: Basis) -> int:
+    D = C.c_int64()
+    _check(lib.qk_basis_dim(b.ptr, C.byref(D)), "qk_basis_dim")
+    return D.value
+
+
+def qk_basis_shape(b: Basis) -> tuple[int, int]:
+    L, N = C.c_int32(), C.c_int32()
+    _check(lib.qk_basis_shape(b.ptr, C.byref(L), C.byref(N)), "qk_basis_shape")
+    return L.value, N.value
+
+
+def qk_basis_states(b: Basis, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """The sorted states as a device int32 tensor holding the uint32 bit patterns."""
+    D = qk_basis_dim(b)
+    if out is None:
+        out = torch.empty(D, dtype=torch.int32, device="cuda")
+    if out.numel() != D or out.element_size() != 4:
+        raise ValueError("out must hold D 32-bit integers")
+    _check(lib.qk_basis_states(b.ptr, _dptr(out), _stream(stream)), "qk_basis_states")
+    return out
+
+
+def qk_basis_rank(b: Basis, states) -> np.ndarray:
+    st = np.ascontiguousarray(np.atleast_1d(states), dtype=np.uint64)
+    idx = np.empty(len(st), dtype=np.int64)
+    _check(lib.qk_basis_rank(b.ptr, st.ctypes.data_as(C.POINTER(C.c_uint64)), len(st),
+                             idx.ctypes.data_as(C.POINTER(C.c_int64))), "qk_basis_rank")
+    return idx
+
+
+def qk_ham_create(b: Basis, jxy: float, jz: float, pbc: bool, fields, mode: int = QK_MATFREE,
+                  stream=None) -> Ham:
+    """fields: (L,) or (batch, L) host array of on-site fields."""
+    f = np.ascontiguousarray(np.atleast_2d(np.asarray(fields, dtype=np.float64)))
+    p = HamParams(float(jxy), float(jz), int(bool(pbc)), int(mode))
+    out = C.c_void_p()
+    _check(lib.qk_ham_create(b.ptr, C.byref(p), f.ctypes.data_as(C.POINTER(C.c_double)), f.shape[0],
+                             _stream(stream), C.byref(out)), "qk_ham_create")
+    return Ham(out, keep=(b,))
+
+
+def qk_ham_set_fields(H: Ham, fields, stream=None) -> None:
+    f = np.ascontiguousarray(np.atleast_2d(np.asarray(fields, dtype=np.float64)))
+    _check(lib.qk_ham_set_fields(H.ptr, f.ctypes.data_as(C.POINTER(C.c_double)), f.shape[0], _stream(stream)),
+           "qk_ham_set_fields")
+
+
+def qk_ham_shape(H: Ham) -> tuple[int, int, int]:
+    D, Bn, mode = C.c_int64(), C.c_int32(), C.c_int32()
+    _check(lib.qk_ham_shape(H.ptr, C.byref(D), C.byref(Bn), C.byref(mode)), "qk_ham_shape")
+    return D.value, Bn.value, mode.value
+
+
+def _check_vec(H_or_D, t: torch.Tensor, batch: int, name: str):
+    D = H_or_D
+    if t.numel() != D * batch:
+        raise ValueError(f"{name} must hold D*batch = {D * batch} elements, got {t.numel()}")
+
+
+def qk_ham_apply(H: Ham, x: torch.Tensor, y: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """y = H x; x is (D,) or (D, batch) complex128/complex64 on the device."""
+    D, Bn, _ = qk_ham_shape(H)
+    _check_vec(D, x, Bn, "x")
+    if y is None:
+        y = torch.empty_like(x)
+    if y.dtype != x.dtype:
+        raise ValueError("x and y dtypes differ")
+    _check_vec(D, y, Bn, "y")
+    _check(lib.qk_ham_apply(H.ptr, _dptr(x), _dptr(y), dtype_code(x), _stream(stream)), "qk_ham_apply")
+    return y
+
+
+def qk_krylov_create(H: Ham, m: int, dtype=torch.complex128, reorth: int = 0) -> Krylov:
+    out = C.c_void_p()
+    code = _DTYPE[dtype] if isinstance(dtype, torch.dtype) else int(dtype)
+    _check(lib.qk_krylov_create(H.ptr, m, code, reorth, C.byref(out)), "qk_krylov_create")
+    k = Krylov(out, keep=(H,))
+    k.m, k.dtype, k.H = m, code, H
+    return k
+
+
+def qk_krylov_expm_step(k: Krylov, psi: torch.Tensor, dt: float, stream=None, info: bool = False):
+    """psi <- exp(-i dt H) psi in place.  With info=True waits and returns a
+    list of dicts (m_used, status, err_est, beta0), one per batch item."""
+    D, Bn, _ = qk_ham_shape(k.H)
+    _check_vec(D, psi, Bn, "psi")
+    if dtype_code(psi) != k.dtype:
+        raise ValueError("psi dtype differs from the workspace dtype")
+    if not info:
+        _check(lib.qk_krylov_expm_step(k.ptr, _dptr(psi), float(dt), _stream(stream), None), "qk_krylov_expm_step")
+        return None
+    arr = (StepInfo * Bn)()
+    st = lib.qk_krylov_expm_step(k.ptr, _dptr(psi), float(dt), _stream(stream), arr)
+    res = [dict(m_used=a.m_used, status=a.status, err_est=a.err_est, beta0=a.beta0) for a in arr]
+    if st not in (QK_OK, QK_ENUMERIC):
+        _check(st, "qk_krylov_expm_step")
+    return res
+
+
+def qk_krylov_coefficients(k: Krylov, item: int = 0):
+    """(alpha, beta, m_used) of the last completed step for one batch item."""
+    a = np.zeros(k.m)
+    b = np.zeros(k.m)
+    mu = C.c_int32()
+    _check(lib.qk_krylov_coefficients(k.ptr, item, a.ctypes.data_as(C.POINTER(C.c_double)),
+                                      b.ctypes.data_as(C.POINTER(C.c_double)), C.byref(mu)),
+           "qk_krylov_coefficients")
+    return a[: mu.value], b[: mu.value], mu.value
+
+
+def qk_return_prob(b: Basis, psi: torch.Tensor, r0: int = -1, psi0: torch.Tensor | None = None,
+                   batch: int = 1, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """|<psi0|psi>|^2 per batch item into a device float64 tensor (asynchronous)."""
+    if out is None:
+        out = torch.empty(batch, dtype=torch.float64, device=psi.device)
+    p0 = None if psi0 is None else _dptr(psi0)
+    if psi0 is not None and psi0.dtype != psi.dtype:
+        raise ValueError("psi0 and psi dtypes differ")
+    _check(lib.qk_return_prob(b.ptr, int(r0), p0, _dptr(psi), dtype_code(psi), batch, _dptr(out),
+                              _stream(stream)), "qk_return_prob")
+    return out
+
+
+__all__ = [n for n in dir() if n.startswith("qk_")] + ["QkError", "Basis", "Ham", "Krylov"]

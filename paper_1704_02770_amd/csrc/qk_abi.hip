@@ -1,0 +1,384 @@
+// C ABI of libqkrylov: argument validation, handle management and error
+// reporting around the launchers in qk_kernels.hip.  Every entry point
+// validates its arguments before touching the device and converts HIP
+// failures into QK_EHIP with the runtime's message in qk_last_error().
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "qk_internal.h"
+
+namespace qk {
+
+static thread_local std::string g_err;
+
+void set_error(const std::string& msg) { g_err = msg; }
+
+qk_status hip_fail(hipError_t e, const char* what) {
+  g_err = std::string(what) + ": " + hipGetErrorString(e);
+  return e == hipErrorOutOfMemory ? QK_ENOMEM : QK_EHIP;
+}
+
+static qk_status inval(const std::string& msg) {
+  g_err = msg;
+  return QK_EINVAL;
+}
+
+static qk_status check_device(int dev) {
+  int cur = -1;
+  QK_HIP(hipGetDevice(&cur));
+  if (cur != dev) return inval("handle belongs to another device");
+  return QK_OK;
+}
+
+static size_t elem_bytes(int dtype) { return dtype == QK_C128 ? 16 : 8; }
+
+static bool ranges_overlap(const void* a, const void* b, size_t n) {
+  const char* x = (const char*)a;
+  const char* y = (const char*)b;
+  return x < y + n && y < x + n;
+}
+
+int krylov_grid(uint64_t D, int B);
+
+}  // namespace qk
+
+using namespace qk;
+
+#define QK_API extern "C" __attribute__((visibility("default")))
+
+QK_API int qk_abi_version(void) { return QK_ABI_VERSION; }
+
+QK_API const char* qk_last_error(void) { return g_err.c_str(); }
+
+QK_API qk_status qk_fields_quasiperiodic(int32_t L, double h, double beta, const double* phi, int32_t batch,
+                                         double* h_out) {
+  g_err.clear();
+  if (L < 1 || L > QK_MAX_L) return inval("L out of range");
+  if (batch < 1) return inval("batch < 1");
+  if (!phi || !h_out) return inval("NULL pointer");
+  if (!std::isfinite(h) || !std::isfinite(beta)) return inval("non-finite h or beta");
+  for (int b = 0; b < batch; ++b) {
+    if (!std::isfinite(phi[b])) return inval("non-finite phase");
+    for (int i = 1; i <= L; ++i) h_out[(size_t)b * L + (i - 1)] = h * std::cos(2.0 * M_PI * beta * i + phi[b]);
+  }
+  return QK_OK;
+}
+
+// ------------------------------------------------------------------- basis
+static int64_t binom64(int n, int k) {
+  if (k < 0 || k > n) return 0;
+  int64_t r = 1;
+  for (int i = 1; i <= k; ++i) r = r * (n - k + i) / i;
+  return r;
+}
+
+QK_API qk_status qk_basis_build(int32_t L, int32_t n_up, void* stream, qk_basis** out) {
+  g_err.clear();
+  if (!out) return inval("NULL out");
+  *out = nullptr;
+  if (L < 2 || L > QK_MAX_L) return inval("L must be in [2, 32]");
+  if (n_up <= 0 || n_up >= L) return inval("n_up must be in (0, L)");
+  qk_basis* b = new (std::nothrow) qk_basis;
+  if (!b) return QK_ENOMEM;
+  b->L = L;
+  b->N = n_up;
+  b->D = binom64(L, n_up);
+  hipError_t e = hipGetDevice(&b->device);
+  if (e == hipSuccess) e = hipMalloc((void**)&b->d_binom, sizeof(uint32_t) * kBinomStride * kBinomStride);
+  if (e == hipSuccess) e = hipMalloc((void**)&b->d_states, sizeof(uint32_t) * (size_t)b->D);
+  if (e != hipSuccess) {
+    qk_status st = hip_fail(e, "qk_basis_build allocation");
+    qk_basis_destroy(b);
+    return st;
+  }
+  qk_status st = launch_basis_build(b, (hipStream_t)stream);
+  if (st != QK_OK) {
+    qk_basis_destroy(b);
+    return st;
+  }
+  *out = b;
+  return QK_OK;
+}
+
+QK_API qk_status qk_basis_dim(const qk_basis* b, int64_t* D) {
+  g_err.clear();
+  if (!b || !D) return inval("NULL pointer");
+  *D = b->D;
+  return QK_OK;
+}
+
+QK_API qk_status qk_basis_shape(const qk_basis* b, int32_t* L, int32_t* n_up) {
+  g_err.clear();
+  if (!b || !L || !n_up) return inval("NULL pointer");
+  *L = b->L;
+  *n_up = b->N;
+  return QK_OK;
+}
+
+QK_API qk_status qk_basis_states(const qk_basis* b, uint32_t* dst, void* stream) {
+  g_err.clear();
+  if (!b || !dst) return inval("NULL pointer");
+  qk_status st = check_device(b->device);
+  if (st != QK_OK) return st;
+  QK_HIP(hipMemcpyAsync(dst, b->d_states, sizeof(uint32_t) * (size_t)b->D, hipMemcpyDeviceToDevice,
+                        (hipStream_t)stream));
+  return QK_OK;
+}
+
+QK_API qk_status qk_basis_rank(const qk_basis* b, const uint64_t* states_host, int64_t n, int64_t* idx_host) {
+  g_err.clear();
+  if (!b) return inval("NULL basis");
+  if (n < 0) return inval("n < 0");
+  if (n == 0) return QK_OK;
+  if (!states_host || !idx_host) return inval("NULL pointer");
+  qk_status st = check_device(b->device);
+  if (st != QK_OK) return st;
+  uint64_t* d_in = nullptr;
+  int64_t* d_out = nullptr;
+  hipError_t e = hipMalloc((void**)&d_in, sizeof(uint64_t) * (size_t)n);
+  if (e == hipSuccess) e = hipMalloc((void**)&d_out, sizeof(int64_t) * (size_t)n);
+  if (e == hipSuccess) e = hipMemcpy(d_in, states_host, sizeof(uint64_t) * (size_t)n, hipMemcpyHostToDevice);
+  if (e == hipSuccess) {
+    st = launch_rank(b, d_in, n, d_out, nullptr);
+    if (st == QK_OK) e = hipMemcpy(idx_host, d_out, sizeof(int64_t) * (size_t)n, hipMemcpyDeviceToHost);
+  }
+  hipFree(d_in);
+  hipFree(d_out);
+  if (e != hipSuccess) return hip_fail(e, "qk_basis_rank");
+  return st;
+}
+
+QK_API void qk_basis_destroy(qk_basis* b) {
+  if (!b) return;
+  hipDeviceSynchronize();
+  if (b->d_states) hipFree(b->d_states);
+  if (b->d_binom) hipFree(b->d_binom);
+  delete b;
+}
+
+// ------------------------------------------------------------- Hamiltonian
+static qk_status check_fields(const double* h, int32_t L, int32_t batch) {
+  if (!h) return inval("NULL fields");
+  for (int64_t i = 0; i < (int64_t)L * batch; ++i)
+    if (!std::isfinite(h[i])) return inval("non-finite field");
+  return QK_OK;
+}
+
+QK_API qk_status qk_ham_create(const qk_basis* b, const qk_ham_params* p, const double* h_host, int32_t batch,
+                               void* stream, qk_ham** out) {
+  g_err.clear();
+  if (!out) return inval("NULL out");
+  *out = nullptr;
+  if (!b || !p) return inval("NULL pointer");
+  if (batch < 1 || batch > QK_MAX_BATCH) return inval("batch must be in [1, 64]");
+  if (!std::isfinite(p->jxy) || !std::isfinite(p->jz)) return inval("non-finite coupling");
+  if (p->pbc != 0 && p->pbc != 1) return inval("pbc must be 0 or 1");
+  if (p->mode != QK_MATFREE && p->mode != QK_CSR) return inval("unknown mode");
+  if (p->mode == QK_CSR && b->D > (1 << 24)) return inval("CSR form limited to D <= 2^24");
+  qk_status st = check_fields(h_host, b->L, batch);
+  if (st != QK_OK) return st;
+  st = check_device(b->device);
+  if (st != QK_OK) return st;
+  qk_ham* H = new (std::nothrow) qk_ham;
+  if (!H) return QK_ENOMEM;
+  H->basis = b;
+  H->p = *p;
+  H->batch = batch;
+  H->device = b->device;
+  hipStream_t s = (hipStream_t)stream;
+  const size_t fbytes = sizeof(double) * (size_t)b->L * batch;
+  hipError_t e = hipMalloc((void**)&H->d_fields, fbytes);
+  if (e == hipSuccess) e = hipMemcpyAsync(H->d_fields, h_host, fbytes, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);   // h_host may be freed by the caller after return
+  if (e != hipSuccess) {
+    st = hip_fail(e, "qk_ham_create");
+    qk_ham_destroy(H);
+    return st;
+  }
+  if (p->mode == QK_CSR) {
+    e = hipMalloc((void**)&H->d_rowptr, sizeof(uint32_t) * ((size_t)b->D + 1));
+    if (e == hipSuccess) e = hipMalloc((void**)&H->d_diag, sizeof(double) * (size_t)b->D * batch);
+    if (e != hipSuccess) {
+      st = hip_fail(e, "qk_ham_create CSR allocation");
+      qk_ham_destroy(H);
+      return st;
+    }
+    st = launch_csr_build(H, s);
+    if (st != QK_OK) {
+      qk_ham_destroy(H);
+      return st;
+    }
+  }
+  *out = H;
+  return QK_OK;
+}
+
+QK_API qk_status qk_ham_set_fields(qk_ham* H, const double* h_host, int32_t batch, void* stream) {
+  g_err.clear();
+  if (!H) return inval("NULL Hamiltonian");
+  if (batch != H->batch) return inval("batch differs from the Hamiltonian's");
+  qk_status st = check_fields(h_host, H->basis->L, batch);
+  if (st != QK_OK) return st;
+  st = check_device(H->device);
+  if (st != QK_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  const size_t fbytes = sizeof(double) * (size_t)H->basis->L * batch;
+  QK_HIP(hipMemcpyAsync(H->d_fields, h_host, fbytes, hipMemcpyHostToDevice, s));
+  QK_HIP(hipStreamSynchronize(s));
+  if (H->p.mode == QK_CSR) return launch_csr_diag(H, s);
+  return QK_OK;
+}
+
+QK_API qk_status qk_ham_shape(const qk_ham* H, int64_t* D, int32_t* batch, int32_t* mode) {
+  g_err.clear();
+  if (!H || !D || !batch || !mode) return inval("NULL pointer");
+  *D = H->basis->D;
+  *batch = H->batch;
+  *mode = H->p.mode;
+  return QK_OK;
+}
+
+QK_API qk_status qk_ham_apply(const qk_ham* H, const void* x, void* y, int32_t dtype, void* stream) {
+  g_err.clear();
+  if (!H || !x || !y) return inval("NULL pointer");
+  if (dtype != QK_C128 && dtype != QK_C64) return inval("unknown dtype");
+  const size_t bytes = elem_bytes(dtype) * (size_t)H->basis->D * H->batch;
+  if (ranges_overlap(x, y, bytes)) return inval("x and y overlap");
+  if (((uintptr_t)x | (uintptr_t)y) % elem_bytes(dtype)) return inval("misaligned vector");
+  qk_status st = check_device(H->device);
+  if (st != QK_OK) return st;
+  return launch_ham_apply(H, x, y, dtype, (hipStream_t)stream);
+}
+
+QK_API void qk_ham_destroy(qk_ham* H) {
+  if (!H) return;
+  hipDeviceSynchronize();
+  if (H->d_fields) hipFree(H->d_fields);
+  if (H->d_rowptr) hipFree(H->d_rowptr);
+  if (H->d_cols) hipFree(H->d_cols);
+  if (H->d_diag) hipFree(H->d_diag);
+  delete H;
+}
+
+// ------------------------------------------------------------------ Krylov
+QK_API qk_status qk_krylov_create(const qk_ham* H, int32_t m, int32_t dtype, int32_t reorth, qk_krylov** out) {
+  g_err.clear();
+  if (!out) return inval("NULL out");
+  *out = nullptr;
+  if (!H) return inval("NULL Hamiltonian");
+  if (m < 1 || m > QK_MAX_M) return inval("m must be in [1, 64]");
+  if (dtype != QK_C128 && dtype != QK_C64) return inval("unknown dtype");
+  if (reorth != 0) {
+    set_error("only reorth = 0 is implemented");
+    return QK_EUNSUPPORTED;
+  }
+  qk_status st = check_device(H->device);
+  if (st != QK_OK) return st;
+  qk_krylov* k = new (std::nothrow) qk_krylov;
+  if (!k) return QK_ENOMEM;
+  k->H = H;
+  k->m = m;
+  k->dtype = dtype;
+  k->reorth = reorth;
+  k->batch = H->batch;
+  k->D = H->basis->D;
+  k->device = H->device;
+  k->grid = krylov_grid((uint64_t)k->D, k->batch);
+  const size_t vec = elem_bytes(dtype) * (size_t)k->D * k->batch;
+  hipError_t e = hipMalloc(&k->d_U, vec * (size_t)m);
+  if (e == hipSuccess) e = hipMalloc((void**)&k->d_partA, sizeof(double) * (size_t)k->grid * 2 * k->batch);
+  if (e == hipSuccess) e = hipMalloc((void**)&k->d_partB, sizeof(double) * (size_t)k->grid * k->batch);
+  if (e == hipSuccess) e = hipMalloc((void**)&k->d_coef, sizeof(double) * kstate_doubles(m, k->batch));
+  if (e == hipSuccess) e = hipMalloc((void**)&k->d_int, sizeof(int32_t) * 2 * k->batch);
+  if (e == hipSuccess) e = hipMemset(k->d_coef, 0, sizeof(double) * kstate_doubles(m, k->batch));
+  if (e == hipSuccess) e = hipMemset(k->d_int, 0, sizeof(int32_t) * 2 * k->batch);
+  if (e != hipSuccess) {
+    st = hip_fail(e, "qk_krylov_create allocation");
+    qk_krylov_destroy(k);
+    return st;
+  }
+  *out = k;
+  return QK_OK;
+}
+
+QK_API qk_status qk_krylov_expm_step(qk_krylov* k, void* psi, double dt, void* stream, qk_step_info* info) {
+  g_err.clear();
+  if (!k || !psi) return inval("NULL pointer");
+  if (!std::isfinite(dt)) return inval("dt not finite");
+  if ((uintptr_t)psi % elem_bytes(k->dtype)) return inval("misaligned psi");
+  qk_status st = check_device(k->device);
+  if (st != QK_OK) return st;
+  const size_t vec = elem_bytes(k->dtype) * (size_t)k->D * k->batch;
+  if (ranges_overlap(psi, k->d_U, vec * (size_t)k->m)) return inval("psi overlaps the Krylov workspace");
+  hipStream_t s = (hipStream_t)stream;
+  st = launch_krylov_step(k, psi, dt, s);
+  if (st != QK_OK || !info) return st;
+  const int B = k->batch;
+  std::vector<int32_t> iv(2 * B);
+  std::vector<double> err(B), n0(B);
+  const KState ks = make_kstate(k);
+  QK_HIP(hipMemcpyAsync(iv.data(), k->d_int, sizeof(int32_t) * 2 * B, hipMemcpyDeviceToHost, s));
+  QK_HIP(hipMemcpyAsync(err.data(), ks.err, sizeof(double) * B, hipMemcpyDeviceToHost, s));
+  QK_HIP(hipMemcpyAsync(n0.data(), ks.n0, sizeof(double) * B, hipMemcpyDeviceToHost, s));
+  QK_HIP(hipStreamSynchronize(s));
+  qk_status worst = QK_OK;
+  for (int b = 0; b < B; ++b) {
+    info[b].m_used = iv[b];
+    info[b].status = iv[B + b];
+    info[b].err_est = err[b];
+    info[b].beta0 = n0[b];
+    if (iv[B + b] != QK_OK) worst = QK_ENUMERIC;
+  }
+  if (worst != QK_OK) set_error("non-finite Lanczos coefficient");
+  return worst;
+}
+
+QK_API qk_status qk_krylov_coefficients(const qk_krylov* k, int32_t item, double* alpha, double* beta,
+                                        int32_t* m_used) {
+  g_err.clear();
+  if (!k || !alpha || !beta || !m_used) return inval("NULL pointer");
+  if (item < 0 || item >= k->batch) return inval("item out of range");
+  qk_status st = check_device(k->device);
+  if (st != QK_OK) return st;
+  const int B = k->batch, m = k->m;
+  std::vector<double> a((size_t)m * B), bb((size_t)m * B);
+  std::vector<int32_t> iv(2 * B);
+  const KState ks = make_kstate(k);
+  QK_HIP(hipDeviceSynchronize());
+  QK_HIP(hipMemcpy(a.data(), ks.alpha, sizeof(double) * m * B, hipMemcpyDeviceToHost));
+  QK_HIP(hipMemcpy(bb.data(), ks.beta, sizeof(double) * m * B, hipMemcpyDeviceToHost));
+  QK_HIP(hipMemcpy(iv.data(), k->d_int, sizeof(int32_t) * 2 * B, hipMemcpyDeviceToHost));
+  *m_used = iv[item];
+  for (int j = 0; j < m; ++j) {
+    alpha[j] = a[(size_t)j * B + item];
+    beta[j] = bb[(size_t)j * B + item];
+  }
+  return QK_OK;
+}
+
+QK_API void qk_krylov_destroy(qk_krylov* k) {
+  if (!k) return;
+  hipDeviceSynchronize();
+  if (k->d_U) hipFree(k->d_U);
+  if (k->d_partA) hipFree(k->d_partA);
+  if (k->d_partB) hipFree(k->d_partB);
+  if (k->d_coef) hipFree(k->d_coef);
+  if (k->d_int) hipFree(k->d_int);
+  delete k;
+}
+
+// -------------------------------------------------------------- observable
+QK_API qk_status qk_return_prob(const qk_basis* b, int64_t r0, const void* psi0, const void* psi, int32_t dtype,
+                                int32_t batch, double* P_device, void* stream) {
+  g_err.clear();
+  if (!b || !psi || !P_device) return inval("NULL pointer");
+  if (dtype != QK_C128 && dtype != QK_C64) return inval("unknown dtype");
+  if (batch < 1 || batch > QK_MAX_BATCH) return inval("batch must be in [1, 64]");
+  if (!psi0 && (r0 < 0 || r0 >= b->D)) return inval("r0 out of range");
+  qk_status st = check_device(b->device);
+  if (st != QK_OK) return st;
+  return launch_return_prob(b, r0, psi0, psi, dtype, batch, P_device, (hipStream_t)stream);
+}

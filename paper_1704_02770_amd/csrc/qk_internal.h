@@ -1,0 +1,108 @@
+// Internal declarations of libqkrylov: handle layouts, device-side argument
+// blocks and the host launchers that the C ABI layer calls.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+
+#include "qk.h"
+
+namespace qk {
+
+constexpr int kBinomStride = 33;        // binom[n * 33 + k] = C(n, k), n, k <= 32
+constexpr int kNumXcd = 8;              // MI355X: 8 accelerator complex dies, WGs dealt round-robin
+constexpr int kMaxBlock = 256;
+
+void set_error(const std::string& msg);
+qk_status hip_fail(hipError_t e, const char* what);
+
+#define QK_HIP(call)                                          \
+  do {                                                        \
+    hipError_t e_ = (call);                                   \
+    if (e_ != hipSuccess) return ::qk::hip_fail(e_, #call);   \
+  } while (0)
+
+// Threads per block for a batch of B problems: B x 2^k <= 256, so that a
+// grid-stride loop keeps each thread on one batch column and per-column
+// tree reductions halve evenly.
+inline int block_threads(int B) {
+  int t = B;
+  while (t * 2 <= kMaxBlock) t *= 2;
+  return t;
+}
+
+}  // namespace qk
+
+struct qk_basis {
+  int32_t L = 0, N = 0;
+  int64_t D = 0;
+  int device = 0;
+  uint32_t* d_states = nullptr;   // [D] sorted sector states
+  uint32_t* d_binom = nullptr;    // [33 * 33] C(n, k)
+};
+
+struct qk_ham {
+  const qk_basis* basis = nullptr;
+  qk_ham_params p{};
+  int32_t batch = 1;
+  int device = 0;
+  double* d_fields = nullptr;     // [batch][L]
+  // CSR form (mode == QK_CSR): off-diagonal columns, row pointers, diagonal [D][batch]
+  uint32_t* d_rowptr = nullptr;   // [D + 1]
+  uint32_t* d_cols = nullptr;     // [nnz]
+  double* d_diag = nullptr;       // [D][batch]
+  int64_t nnz = 0;
+};
+
+struct qk_krylov {
+  const qk_ham* H = nullptr;
+  int32_t m = 0, dtype = 0, reorth = 0, batch = 1;
+  int64_t D = 0;
+  int device = 0;
+  int grid = 0;                   // blocks of the streaming kernels (multiple of 8)
+  void* d_U = nullptr;            // m slots of [D][batch] vectors: u_1..u_m
+  double* d_partA = nullptr;      // [grid][2][batch] partial sums of the H-pass
+  double* d_partB = nullptr;      // [grid][1][batch] partial sums of the update pass
+  double* d_coef = nullptr;       // coefficient block, see qk::KState
+  int32_t* d_int = nullptr;       // [2][batch]: m_used, status
+};
+
+namespace qk {
+
+// Device view of the Lanczos coefficient block of one workspace.
+struct KState {
+  double* alpha;   // [m][B]
+  double* beta;    // [m][B]
+  double* sigma;   // [m + 1][B]  1 / norm of stored vector u_j
+  double* n0;      // [B]         norm of psi at step start
+  double* gre;     // [m][B]      combination coefficients (real)
+  double* gim;     // [m][B]      (imaginary)
+  double* err;     // [B]
+  int32_t* mused;  // [B]
+  int32_t* status; // [B]
+};
+
+inline size_t kstate_doubles(int m, int B) { return (size_t)B * (5 * m + 1 + 2 + 1); }
+KState make_kstate(const qk_krylov* k);
+
+// Model arguments of the matrix-free rows.
+struct ModelArgs {
+  int32_t L, N, pbc, B;
+  double half_jxy, jz;
+  uint32_t lmask;        // low L bits
+};
+ModelArgs model_args(const qk_ham* H);
+
+// Launchers (all asynchronous on `s`).
+qk_status launch_basis_build(qk_basis* b, hipStream_t s);
+qk_status launch_rank(const qk_basis* b, const uint64_t* d_in, int64_t n, int64_t* d_out, hipStream_t s);
+qk_status launch_csr_build(qk_ham* H, hipStream_t s);
+qk_status launch_csr_diag(qk_ham* H, hipStream_t s);
+qk_status launch_ham_apply(const qk_ham* H, const void* x, void* y, int dtype, hipStream_t s);
+qk_status launch_krylov_step(qk_krylov* k, void* psi, double dt, hipStream_t s);
+qk_status launch_return_prob(const qk_basis* b, int64_t r0, const void* psi0, const void* psi, int dtype,
+                             int B, double* P, hipStream_t s);
+
+}  // namespace qk

@@ -1,0 +1,898 @@
+// HIP kernels of libqkrylov for gfx950 (MI355X).
+//
+// Method: arXiv:1704.02770.  Basis (Sec. 2 "Basis representation", Sec. 3
+// Algorithms 2 and 3), Hamiltonian rows (Sec. 3 "Hamiltonian matrix
+// construction", Eq. (1)), Krylov propagation (Sec. 2 "Krylov subspace
+// methods") and the survival probability (Sec. 4).
+//
+// Memory layout: vectors are interleaved complex [D][B] (batch fastest), so a
+// row's B values are contiguous and a wavefront of consecutive (row, batch)
+// threads streams contiguous memory.  All reductions are deterministic: each
+// block writes its partial sums, and the next kernel in the chain reduces all
+// partials in a fixed order in every block (no atomics, no cross-XCD fences).
+#include <hipcub/hipcub.hpp>
+
+#include <cmath>
+#include <type_traits>
+
+#include "qk_internal.h"
+
+namespace qk {
+
+template <typename T> struct Cx;
+template <> struct Cx<double> { using V = double2; };
+template <> struct Cx<float> { using V = float2; };
+
+// ------------------------------------------------------------------ ranking
+// Position of a state in the sorted basis: with set bits at p_1 < ... < p_N,
+// the number of sector states below it is sum_k C(p_k, k) (the counting that
+// the sorted order of Sec. 2 implies; the paper finds it by binary lookup).
+__device__ __forceinline__ uint32_t cns_rank(uint32_t s, const uint32_t* tab) {
+  uint32_t r = 0;
+  int k = 1;
+  while (s) {
+    int p = __builtin_ctz(s);
+    r += tab[p * kBinomStride + k];
+    ++k;
+    s &= s - 1u;
+  }
+  return r;
+}
+
+// The r-th state of the sorted basis (Algorithm 3's first_int()).
+__device__ __forceinline__ uint32_t cns_unrank(uint32_t r, int L, int N, const uint32_t* tab) {
+  uint32_t s = 0;
+  int k = N;
+  for (int p = L - 1; p >= 0 && k > 0; --p) {
+    uint32_t c = tab[p * kBinomStride + k];
+    if (r >= c) {
+      s |= 1u << p;
+      r -= c;
+      --k;
+    }
+  }
+  return s;
+}
+
+// Next larger integer with the same popcount (Algorithm 2).  The paper's
+// exact division of two powers of two is a right shift by ctz(v).
+__device__ __forceinline__ uint32_t next_perm(uint32_t v) {
+  uint32_t t = (v | (v - 1u)) + 1u;
+  return t | ((((t & (0u - t)) >> __builtin_ctz(v)) >> 1) - 1u);
+}
+
+__global__ void k_binom_table(uint32_t* tab) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  for (int n = 0; n < kBinomStride; ++n)
+    for (int k = 0; k < kBinomStride; ++k) {
+      uint32_t v;
+      if (k > n) v = 0;
+      else if (k == 0 || k == n) v = 1;
+      else v = tab[(n - 1) * kBinomStride + k - 1] + tab[(n - 1) * kBinomStride + k];
+      tab[n * kBinomStride + k] = v;
+    }
+}
+
+constexpr int kBasisChunk = 8;
+constexpr int kBasisThreads = 256;
+
+// Every thread unranks the first state of its chunk and advances with the
+// next bit permutation; the block stages its 2048 states in LDS and writes
+// them out coalesced.
+__global__ void __launch_bounds__(kBasisThreads)
+k_basis_build(uint32_t* __restrict__ states, uint32_t D, int L, int N, const uint32_t* __restrict__ gtab) {
+  __shared__ uint32_t tab[kBinomStride * kBinomStride];
+  __shared__ uint32_t stage[kBasisThreads * kBasisChunk];
+  for (int i = threadIdx.x; i < kBinomStride * kBinomStride; i += kBasisThreads) tab[i] = gtab[i];
+  __syncthreads();
+  const uint64_t base = (uint64_t)blockIdx.x * kBasisThreads * kBasisChunk;
+  const uint64_t start = base + (uint64_t)threadIdx.x * kBasisChunk;
+  if (start < D) {
+    uint32_t s = cns_unrank((uint32_t)start, L, N, tab);
+    for (int i = 0; i < kBasisChunk; ++i) {
+      stage[threadIdx.x * kBasisChunk + i] = s;
+      s = next_perm(s);
+    }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < kBasisThreads * kBasisChunk; i += kBasisThreads) {
+    uint64_t r = base + i;
+    if (r < D) states[r] = stage[i];
+  }
+}
+
+__global__ void k_rank(const uint64_t* __restrict__ in, int64_t n, int64_t* __restrict__ out, int L, int N,
+                       const uint32_t* __restrict__ tab) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  uint64_t s = in[i];
+  if ((L < 64 && (s >> L) != 0) || __popcll(s) != N) {
+    out[i] = -1;
+    return;
+  }
+  out[i] = (int64_t)cns_rank((uint32_t)s, tab);
+}
+
+// ------------------------------------------------------------- model rows
+__device__ __forceinline__ int anti_bonds(uint32_t s, const ModelArgs& a) {
+  if (a.pbc) {
+    uint32_t rot = ((s >> 1) | (s << (a.L - 1))) & a.lmask;
+    return __popc((s ^ rot) & a.lmask);
+  }
+  return __popc((s ^ (s >> 1)) & (a.lmask >> 1));
+}
+
+// Diagonal of Eq. (1): jz/4 * (aligned - anti-aligned bonds) + sum_i h_i (bit_i - 1/2).
+__device__ __forceinline__ double diag_value(uint32_t s, const ModelArgs& a, const double* f, double hhalf) {
+  const int nb = a.pbc ? a.L : a.L - 1;
+  double d = 0.25 * a.jz * (double)(nb - 2 * anti_bonds(s, a)) - hhalf;
+  uint32_t t = s;
+  while (t) {
+    d += f[__builtin_ctz(t)];
+    t &= t - 1u;
+  }
+  return d;
+}
+
+// Calls f(column) for every bond whose bits differ.  A particle hopping
+// p -> p+1 raises the rank by C(p, #set bits below p); p+1 -> p lowers it by
+// the same amount.  The ring bond (L-1, 0) renumbers every particle and is
+// ranked in full.
+template <class F>
+__device__ __forceinline__ void for_each_hop(uint32_t s, uint32_t r, const ModelArgs& a, const uint32_t* tab, F&& f) {
+  int pc = 0;
+  for (int p = 0; p < a.L - 1; ++p) {
+    const uint32_t b0 = (s >> p) & 1u;
+    const uint32_t b1 = (s >> (p + 1)) & 1u;
+    if (b0 != b1) {
+      const uint32_t c = tab[p * kBinomStride + pc];
+      f(b0 ? r + c : r - c);
+    }
+    pc += (int)b0;
+  }
+  if (a.pbc) {
+    const uint32_t b0 = s & 1u, b1 = (s >> (a.L - 1)) & 1u;
+    if (b0 != b1) f(cns_rank(s ^ (1u | (1u << (a.L - 1))), tab));
+  }
+}
+
+// Per-block LDS copies of the small tables every row kernel needs.
+struct RowShared {
+  uint32_t tab[kBinomStride * kBinomStride];
+  double fld[QK_MAX_BATCH * QK_MAX_L];
+  double hhalf[QK_MAX_BATCH];
+};
+
+__device__ __forceinline__ void load_row_shared(RowShared& sh, const ModelArgs& a, const uint32_t* gtab,
+                                                const double* gfields) {
+  for (int i = threadIdx.x; i < kBinomStride * kBinomStride; i += blockDim.x) sh.tab[i] = gtab[i];
+  for (int i = threadIdx.x; i < a.B * a.L; i += blockDim.x) sh.fld[i] = gfields[i];
+  __syncthreads();
+  for (int b = threadIdx.x; b < a.B; b += blockDim.x) {
+    double t = 0.0;
+    for (int i = 0; i < a.L; ++i) t += sh.fld[b * a.L + i];
+    sh.hhalf[b] = 0.5 * t;
+  }
+  __syncthreads();
+}
+
+struct HamView {
+  const uint32_t* states;
+  const uint32_t* rowptr;
+  const uint32_t* cols;
+  const double* diag;
+  uint32_t D;
+};
+
+// (H x)[r, b] and x[r, b].
+template <typename T, bool CSR>
+__device__ __forceinline__ typename Cx<T>::V h_row(uint32_t r, int b, const ModelArgs& a, const RowShared& sh,
+                                                   const HamView& hv, const typename Cx<T>::V* __restrict__ x,
+                                                   typename Cx<T>::V& xr) {
+  using V = typename Cx<T>::V;
+  const int B = a.B;
+  xr = x[(size_t)r * B + b];
+  const T g = (T)a.half_jxy;
+  V acc;
+  if (CSR) {
+    const T d = (T)hv.diag[(size_t)r * B + b];
+    acc.x = d * xr.x;
+    acc.y = d * xr.y;
+    V hs = {0, 0};
+    for (uint32_t k = hv.rowptr[r]; k < hv.rowptr[r + 1]; ++k) {
+      const V xc = x[(size_t)hv.cols[k] * B + b];
+      hs.x += xc.x;
+      hs.y += xc.y;
+    }
+    acc.x += g * hs.x;
+    acc.y += g * hs.y;
+  } else {
+    const uint32_t s = hv.states[r];
+    const T d = (T)diag_value(s, a, sh.fld + b * a.L, sh.hhalf[b]);
+    acc.x = d * xr.x;
+    acc.y = d * xr.y;
+    V hs = {0, 0};
+    for_each_hop(s, r, a, sh.tab, [&](uint32_t c) {
+      const V xc = x[(size_t)c * B + b];
+      hs.x += xc.x;
+      hs.y += xc.y;
+    });
+    acc.x += g * hs.x;
+    acc.y += g * hs.y;
+  }
+  return acc;
+}
+
+// XCD-aware tile walk: work-groups are dealt round-robin to the 8 XCDs, so
+// block i runs on XCD i % 8.  Each XCD gets one contiguous eighth of the row
+// tiles, and its blocks stride through that eighth together, which keeps the
+// rows being read on one XCD close together in that XCD's L2.
+struct TileWalk {
+  uint32_t t, t_end, step;
+  __device__ TileWalk(uint32_t ntiles) {
+    const uint32_t x = blockIdx.x % kNumXcd, k = blockIdx.x / kNumXcd, per = gridDim.x / kNumXcd;
+    const uint32_t t0 = (uint32_t)(((uint64_t)ntiles * x) / kNumXcd);
+    t_end = (uint32_t)(((uint64_t)ntiles * (x + 1)) / kNumXcd);
+    t = t0 + k;
+    step = per;
+  }
+};
+
+// ----------------------------------------------------------- H x kernels
+template <typename T, bool CSR>
+__global__ void __launch_bounds__(kMaxBlock)
+k_apply(const typename Cx<T>::V* __restrict__ x, typename Cx<T>::V* __restrict__ y, ModelArgs a, HamView hv,
+        const uint32_t* __restrict__ gtab, const double* __restrict__ gfields) {
+  __shared__ RowShared sh;
+  load_row_shared(sh, a, gtab, gfields);
+  const int B = a.B, b = threadIdx.x % B;
+  const uint32_t R = blockDim.x / B, rl = threadIdx.x / B;
+  const uint32_t ntiles = (hv.D + R - 1) / R;
+  for (TileWalk w(ntiles); w.t < w.t_end; w.t += w.step) {
+    const uint32_t r = w.t * R + rl;
+    if (r >= hv.D) continue;
+    typename Cx<T>::V xr;
+    y[(size_t)r * B + b] = h_row<T, CSR>(r, b, a, sh, hv, x, xr);
+  }
+}
+
+// ------------------------------------------------------ block reductions
+// Sums each of Q values over the threads of the block that share a batch
+// column (threadIdx % B; blockDim = B * 2^k) by a fixed tree in LDS and
+// writes the Q * B column sums to out_block.
+template <int Q>
+__device__ __forceinline__ void block_partials(const double (&v)[Q], int B, double* red, double* out_block) {
+  // red: LDS scratch of Q * blockDim doubles
+  for (int q = 0; q < Q; ++q) red[q * blockDim.x + threadIdx.x] = v[q];
+  __syncthreads();
+  for (int s = blockDim.x / 2; s >= B; s >>= 1) {
+    if (threadIdx.x < (unsigned)s)
+      for (int q = 0; q < Q; ++q) red[q * blockDim.x + threadIdx.x] += red[q * blockDim.x + threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x < (unsigned)B)
+    for (int q = 0; q < Q; ++q) out_block[q * B + threadIdx.x] = red[q * blockDim.x + threadIdx.x];
+}
+
+// Reduces partials part[g][q][b] over g < G in a fixed order; every block
+// computes identical totals.  out[q * B + b] in LDS, valid after return.
+__device__ __forceinline__ void reduce_partials(const double* __restrict__ part, int G, int Q, int B, double* red,
+                                                double* out) {
+  const int cols = Q * B;
+  const int lanes_per_col = blockDim.x / cols > 0 ? blockDim.x / cols : 1;
+  const int c = threadIdx.x % cols;
+  const int g0 = threadIdx.x / cols;
+  double acc = 0.0;
+  if ((int)threadIdx.x < cols * lanes_per_col)
+    for (int g = g0; g < G; g += lanes_per_col) acc += part[(size_t)g * cols + c];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  if ((int)threadIdx.x < cols) {
+    double t = 0.0;
+    for (int l = 0; l < lanes_per_col; ++l) t += red[l * cols + threadIdx.x];
+    out[threadIdx.x] = t;
+  }
+  // columns beyond blockDim (Q * B > blockDim) are reduced serially
+  for (int cc = blockDim.x + threadIdx.x; cc < cols; cc += blockDim.x) {
+    double t = 0.0;
+    for (int g = 0; g < G; ++g) t += part[(size_t)g * cols + cc];
+    out[cc] = t;
+  }
+  __syncthreads();
+}
+
+// ------------------------------------------------------- Lanczos passes
+// Stored vectors u_j are unnormalised: v_j = sigma_j u_j.  Iteration j:
+//   pass A:  w = a_j H u_j - b_j u_{j-1}      (= H v_j - beta_{j-1} v_{j-1}, or H u_0 at j = 0)
+//            partials  Re<u_j, w>, |u_j|^2
+//   pass B:  u_{j+1} = c_j (w - d_j u_j)       (= w - alpha_j v_j in v-units)
+//            partial   |u_{j+1}|^2  -> beta_j
+// The scalars come from the previous pass's partials, reduced in each block.
+struct LanczosArgs {
+  int j, m;
+  double breakdown_rtol;
+};
+
+template <typename T, bool CSR>
+__global__ void __launch_bounds__(kMaxBlock)
+k_lanczos_A(const typename Cx<T>::V* __restrict__ uj, const typename Cx<T>::V* __restrict__ ujm1,
+            typename Cx<T>::V* __restrict__ w, ModelArgs a, HamView hv, const uint32_t* __restrict__ gtab,
+            const double* __restrict__ gfields, KState st, LanczosArgs la, const double* __restrict__ partB, int Gp,
+            double* __restrict__ partA) {
+  using V = typename Cx<T>::V;
+  __shared__ RowShared sh;
+  __shared__ double red[2 * kMaxBlock];
+  __shared__ double tot[QK_MAX_BATCH];
+  __shared__ double sa[QK_MAX_BATCH], sb[QK_MAX_BATCH];
+  __shared__ int act[QK_MAX_BATCH];
+  load_row_shared(sh, a, gtab, gfields);
+  const int B = a.B, j = la.j;
+  if (j == 0) {
+    for (int b = threadIdx.x; b < B; b += blockDim.x) {
+      sa[b] = 1.0;
+      sb[b] = 0.0;
+      act[b] = 1;
+      if (blockIdx.x == 0) {
+        st.mused[b] = la.m;
+        st.status[b] = QK_OK;
+      }
+    }
+    __syncthreads();
+  } else {
+    reduce_partials(partB, Gp, 1, B, red, tot);
+    for (int b = threadIdx.x; b < B; b += blockDim.x) {
+      int active = st.mused[b] > j;
+      const double beta = sqrt(tot[b]);
+      if (active) {
+        double scale = beta;
+        for (int i = 0; i < j; ++i) scale = fmax(scale, fabs(st.alpha[i * B + b]));
+        for (int i = 0; i + 1 < j; ++i) scale = fmax(scale, st.beta[i * B + b]);
+        if (!isfinite(beta)) {
+          active = 0;
+          if (blockIdx.x == 0) {
+            st.status[b] = QK_ENUMERIC;
+            st.mused[b] = j;
+          }
+        } else if (beta <= la.breakdown_rtol * scale) {
+          active = 0;  // invariant subspace: the Krylov space stops at dimension j
+          if (blockIdx.x == 0) st.mused[b] = j;
+        }
+        if (blockIdx.x == 0) st.beta[(j - 1) * B + b] = beta;
+      }
+      if (active) {
+        sa[b] = 1.0 / beta;
+        sb[b] = beta * st.sigma[(j - 1) * B + b];
+        if (blockIdx.x == 0) st.sigma[j * B + b] = 1.0 / beta;
+      }
+      act[b] = active;
+    }
+    __syncthreads();
+  }
+
+  const int b = threadIdx.x % B;
+  const uint32_t R = blockDim.x / B, rl = threadIdx.x / B;
+  const uint32_t ntiles = (hv.D + R - 1) / R;
+  double s1 = 0.0, s2 = 0.0;
+  if (act[b]) {
+    const T ca = (T)sa[b], cb = (T)sb[b];
+    for (TileWalk tw(ntiles); tw.t < tw.t_end; tw.t += tw.step) {
+      const uint32_t r = tw.t * R + rl;
+      if (r >= hv.D) continue;
+      V xr;
+      const V hx = h_row<T, CSR>(r, b, a, sh, hv, uj, xr);
+      V wv;
+      wv.x = ca * hx.x;
+      wv.y = ca * hx.y;
+      if (j > 0) {
+        const V um = ujm1[(size_t)r * B + b];
+        wv.x -= cb * um.x;
+        wv.y -= cb * um.y;
+      }
+      w[(size_t)r * B + b] = wv;
+      s1 += (double)xr.x * (double)wv.x + (double)xr.y * (double)wv.y;
+      s2 += (double)xr.x * (double)xr.x + (double)xr.y * (double)xr.y;
+    }
+  }
+  double v[2] = {s1, s2};
+  block_partials<2>(v, B, red, partA + (size_t)blockIdx.x * 2 * B);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kMaxBlock)
+k_lanczos_B(const typename Cx<T>::V* __restrict__ uj, typename Cx<T>::V* __restrict__ w, uint32_t D, int B, KState st,
+            LanczosArgs la, const double* __restrict__ partA, int Gp, double* __restrict__ partB, int store) {
+  using V = typename Cx<T>::V;
+  __shared__ double red[2 * kMaxBlock];
+  __shared__ double tot[2 * QK_MAX_BATCH];
+  __shared__ double sc[QK_MAX_BATCH], sd[QK_MAX_BATCH];
+  __shared__ int act[QK_MAX_BATCH];
+  const int j = la.j;
+  reduce_partials(partA, Gp, 2, B, red, tot);
+  for (int b = threadIdx.x; b < B; b += blockDim.x) {
+    int active = st.mused[b] > j;
+    if (active) {
+      const double S1 = tot[b], S2 = tot[B + b];
+      double alpha, c, d;
+      if (j == 0) {
+        const double n0 = sqrt(S2);
+        alpha = S1 / S2;
+        c = 1.0 / n0;
+        d = alpha;
+        if (blockIdx.x == 0) {
+          st.n0[b] = n0;
+          st.sigma[b] = 1.0 / n0;
+        }
+        if (!(n0 > 0.0)) {
+          active = 0;   // zero vector: nothing to propagate
+          if (blockIdx.x == 0) {
+            st.mused[b] = 0;
+            if (!isfinite(S2)) st.status[b] = QK_ENUMERIC;
+          }
+        }
+      } else {
+        const double sj = st.sigma[j * B + b];
+        alpha = sj * S1;
+        c = 1.0;
+        d = alpha * sj;
+      }
+      if (active && !isfinite(alpha)) {
+        active = 0;
+        if (blockIdx.x == 0) {
+          st.status[b] = QK_ENUMERIC;
+          st.mused[b] = j;
+        }
+      }
+      if (active && blockIdx.x == 0) st.alpha[j * B + b] = alpha;
+      sc[b] = c;
+      sd[b] = d;
+    }
+    act[b] = active;
+  }
+  __syncthreads();
+
+  const int b = threadIdx.x % B;
+  const uint32_t R = blockDim.x / B, rl = threadIdx.x / B;
+  const uint32_t ntiles = (D + R - 1) / R;
+  double s = 0.0;
+  if (act[b]) {
+    const double c = sc[b], d = sd[b];
+    for (TileWalk tw(ntiles); tw.t < tw.t_end; tw.t += tw.step) {
+      const uint32_t r = tw.t * R + rl;
+      if (r >= D) continue;
+      const size_t i = (size_t)r * B + b;
+      const V wv = w[i], u = uj[i];
+      const double nx = c * ((double)wv.x - d * (double)u.x);
+      const double ny = c * ((double)wv.y - d * (double)u.y);
+      V o;
+      o.x = (T)nx;
+      o.y = (T)ny;
+      if (store) w[i] = o;
+      s += (double)o.x * (double)o.x + (double)o.y * (double)o.y;
+    }
+  }
+  double v[1] = {s};
+  block_partials<1>(v, B, red, partB + (size_t)blockIdx.x * B);
+}
+
+// ------------------------------------------ projected exponential (1 wave)
+// c = exp(-i tau T) e_1 for the real symmetric tridiagonal T = tridiag(beta,
+// alpha, beta) of the Lanczos recurrence.  Lane i owns component i.  T is
+// shifted by the centre of its Gershgorin interval, the step is cut into
+// substeps with ||tau_s (T - mu)|| <= 1/2, and each substep sums the Taylor
+// series of the exponential applied to the vector until the terms fall below
+// 1e-18 of the sum.
+__global__ void __launch_bounds__(64)
+k_small_expm(KState st, int m, int B, double tau, const double* __restrict__ partB, int Gp) {
+  const int b = blockIdx.x;
+  const int i = threadIdx.x;
+  __shared__ double red[64];
+  // ||u_m||^2 of the last pass (only meaningful when the recurrence ran m steps)
+  double acc = 0.0;
+  for (int g = i; g < Gp; g += 64) acc += partB[(size_t)g * B + b];
+  red[i] = acc;
+  __syncthreads();
+  for (int s = 32; s > 0; s >>= 1) {
+    if (i < s) red[i] += red[i + s];
+    __syncthreads();
+  }
+  const double beta_last = sqrt(red[0]);
+  const int mu = st.mused[b];
+  if (st.status[b] != QK_OK || mu <= 0) {
+    if (i < m) {
+      st.gre[i * B + b] = 0.0;
+      st.gim[i * B + b] = 0.0;
+    }
+    if (i == 0) st.err[b] = 0.0;
+    return;
+  }
+  if (mu == m && i == 0) st.beta[(m - 1) * B + b] = beta_last;
+  const bool on = i < mu;
+  const double al = on ? st.alpha[i * B + b] : 0.0;
+  const double be = (i + 1 < mu) ? st.beta[i * B + b] : 0.0;     // couples i and i+1
+  const double bl = (on && i > 0) ? st.beta[(i - 1) * B + b] : 0.0;
+  // Gershgorin interval of T
+  double lo = on ? al - be - bl : INFINITY, hi = on ? al + be + bl : -INFINITY;
+  for (int s = 32; s > 0; s >>= 1) {
+    lo = fmin(lo, __shfl_xor(lo, s));
+    hi = fmax(hi, __shfl_xor(hi, s));
+  }
+  const double mu_shift = 0.5 * (lo + hi);
+  const double radius = 0.5 * (hi - lo);
+  const double ad = on ? al - mu_shift : 0.0;
+  // bounded substep count (a non-finite or huge norm cannot stall the wave)
+  const double nsd = ceil(fabs(tau) * radius / 0.5);
+  const int nsub = (nsd >= 1.0 && nsd <= 100000.0) ? (int)nsd : (nsd > 100000.0 ? 100000 : 1);
+  const double ts = tau / nsub;
+  double vr = (i == 0) ? 1.0 : 0.0, vi = 0.0;
+  for (int sub = 0; sub < nsub; ++sub) {
+    double sr = vr, si = vi, tr = vr, ti = vi;
+    for (int k = 1; k <= 40; ++k) {
+      // t <- (-i ts / k) (T - mu) t
+      const double up_r = __shfl_up(tr, 1), up_i = __shfl_up(ti, 1);
+      const double dn_r = __shfl_down(tr, 1), dn_i = __shfl_down(ti, 1);
+      double yr = ad * tr + (i > 0 ? bl * up_r : 0.0) + (i < 63 ? be * dn_r : 0.0);
+      double yi = ad * ti + (i > 0 ? bl * up_i : 0.0) + (i < 63 ? be * dn_i : 0.0);
+      if (!on) yr = yi = 0.0;
+      const double f = ts / k;
+      tr = f * yi;    // (-i f) (yr + i yi) = f yi - i f yr
+      ti = -f * yr;
+      sr += tr;
+      si += ti;
+      double tn = fabs(tr) + fabs(ti), sn = fabs(sr) + fabs(si);
+      for (int s = 32; s > 0; s >>= 1) {
+        tn = fmax(tn, __shfl_xor(tn, s));
+        sn = fmax(sn, __shfl_xor(sn, s));
+      }
+      if (tn <= 1e-18 * sn) break;
+    }
+    vr = sr;
+    vi = si;
+  }
+  // overall phase exp(-i tau mu)
+  const double cr = cos(tau * mu_shift), ci = -sin(tau * mu_shift);
+  const double er = vr * cr - vi * ci, ei = vr * ci + vi * cr;
+  const double n0 = st.n0[b];
+  if (i < m) {
+    const double g = on ? n0 * st.sigma[i * B + b] : 0.0;
+    st.gre[i * B + b] = g * er;
+    st.gim[i * B + b] = g * ei;
+  }
+  const double last = __shfl(sqrt(er * er + ei * ei), mu - 1);
+  if (i == 0) st.err[b] = (mu == m) ? n0 * beta_last * last : 0.0;
+}
+
+// ------------------------------------------------ Krylov combination
+// psi[r, b] = sum_{j < m_used} gamma_j u_j[r, b], u_0 = psi, accumulated in
+// double and rounded once.
+template <typename T>
+__global__ void __launch_bounds__(kMaxBlock)
+k_combine(typename Cx<T>::V* __restrict__ psi, const typename Cx<T>::V* __restrict__ U, uint32_t D, int B, int m,
+          KState st) {
+  using V = typename Cx<T>::V;
+  const int b = threadIdx.x % B;
+  const uint32_t R = blockDim.x / B, rl = threadIdx.x / B;
+  const int mu = st.mused[b];
+  if (st.status[b] != QK_OK || mu <= 0) return;
+  const uint32_t ntiles = (D + R - 1) / R;
+  const size_t stride = (size_t)D * B;
+  for (TileWalk tw(ntiles); tw.t < tw.t_end; tw.t += tw.step) {
+    const uint32_t r = tw.t * R + rl;
+    if (r >= D) continue;
+    const size_t i = (size_t)r * B + b;
+    const V p = psi[i];
+    double gr = st.gre[b], gi = st.gim[b];
+    double ar = gr * (double)p.x - gi * (double)p.y;
+    double ai = gr * (double)p.y + gi * (double)p.x;
+    for (int jj = 1; jj < mu; ++jj) {
+      const V u = U[(size_t)(jj - 1) * stride + i];
+      gr = st.gre[jj * B + b];
+      gi = st.gim[jj * B + b];
+      ar += gr * (double)u.x - gi * (double)u.y;
+      ai += gr * (double)u.y + gi * (double)u.x;
+    }
+    V o;
+    o.x = (T)ar;
+    o.y = (T)ai;
+    psi[i] = o;
+  }
+}
+
+// ------------------------------------------------ survival probability
+template <typename T>
+__global__ void k_prob_basis_state(const typename Cx<T>::V* __restrict__ psi, uint32_t r0, int B, double* P) {
+  const int b = threadIdx.x;
+  if (b >= B) return;
+  const typename Cx<T>::V v = psi[(size_t)r0 * B + b];
+  P[b] = (double)v.x * (double)v.x + (double)v.y * (double)v.y;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kMaxBlock)
+k_overlap_partial(const typename Cx<T>::V* __restrict__ psi0, const typename Cx<T>::V* __restrict__ psi, uint32_t D,
+                  int B, double* __restrict__ part) {
+  __shared__ double red[2 * kMaxBlock];
+  const int b = threadIdx.x % B;
+  const uint32_t R = blockDim.x / B, rl = threadIdx.x / B;
+  const uint32_t ntiles = (D + R - 1) / R;
+  double sr = 0.0, si = 0.0;
+  for (TileWalk tw(ntiles); tw.t < tw.t_end; tw.t += tw.step) {
+    const uint32_t r = tw.t * R + rl;
+    if (r >= D) continue;
+    const size_t i = (size_t)r * B + b;
+    const typename Cx<T>::V a = psi0[i], c = psi[i];
+    sr += (double)a.x * (double)c.x + (double)a.y * (double)c.y;   // conj(a) c
+    si += (double)a.x * (double)c.y - (double)a.y * (double)c.x;
+  }
+  double v[2] = {sr, si};
+  block_partials<2>(v, B, red, part + (size_t)blockIdx.x * 2 * B);
+}
+
+__global__ void __launch_bounds__(kMaxBlock) k_overlap_final(const double* __restrict__ part, int G, int B, double* P) {
+  __shared__ double red[kMaxBlock];
+  __shared__ double tot[2 * QK_MAX_BATCH];
+  reduce_partials(part, G, 2, B, red, tot);
+  for (int b = threadIdx.x; b < B; b += blockDim.x) P[b] = tot[b] * tot[b] + tot[B + b] * tot[B + b];
+}
+
+// ------------------------------------------------------------- CSR form
+// Counting pass = the exact preallocation of Sec. 3.
+__global__ void __launch_bounds__(kMaxBlock)
+k_csr_count(const uint32_t* __restrict__ states, uint32_t D, ModelArgs a, uint32_t* __restrict__ cnt) {
+  const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= D) return;
+  const uint32_t s = states[r];
+  uint32_t n = (uint32_t)__popc((s ^ (s >> 1)) & (a.lmask >> 1));
+  if (a.pbc) n += ((s ^ (s >> (a.L - 1))) & 1u);
+  cnt[r] = n;
+}
+
+__global__ void __launch_bounds__(kMaxBlock)
+k_csr_fill(const uint32_t* __restrict__ states, uint32_t D, ModelArgs a, const uint32_t* __restrict__ gtab,
+           const uint32_t* __restrict__ rowptr, uint32_t* __restrict__ cols) {
+  __shared__ uint32_t tab[kBinomStride * kBinomStride];
+  for (int i = threadIdx.x; i < kBinomStride * kBinomStride; i += blockDim.x) tab[i] = gtab[i];
+  __syncthreads();
+  const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= D) return;
+  uint32_t k = rowptr[r];
+  for_each_hop(states[r], r, a, tab, [&](uint32_t c) { cols[k++] = c; });
+}
+
+__global__ void __launch_bounds__(kMaxBlock)
+k_csr_diag(const uint32_t* __restrict__ states, uint32_t D, ModelArgs a, const double* __restrict__ gfields,
+           double* __restrict__ diag) {
+  __shared__ double fld[QK_MAX_BATCH * QK_MAX_L];
+  __shared__ double hh[QK_MAX_BATCH];
+  for (int i = threadIdx.x; i < a.B * a.L; i += blockDim.x) fld[i] = gfields[i];
+  __syncthreads();
+  for (int b = threadIdx.x; b < a.B; b += blockDim.x) {
+    double t = 0.0;
+    for (int i = 0; i < a.L; ++i) t += fld[b * a.L + i];
+    hh[b] = 0.5 * t;
+  }
+  __syncthreads();
+  const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= D) return;
+  const uint32_t s = states[r];
+  for (int b = 0; b < a.B; ++b) diag[(size_t)r * a.B + b] = diag_value(s, a, fld + b * a.L, hh[b]);
+}
+
+// ================================================================ launchers
+static int num_cus() {
+  static int n = 0;
+  if (n == 0) {
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+      n = prop.multiProcessorCount;
+    if (n <= 0) n = 256;
+  }
+  return n;
+}
+
+// Blocks of a streaming kernel: enough for 8 blocks per CU, at most one per
+// tile, rounded to a multiple of the XCD count.
+static int stream_grid(uint64_t rows, int B) {
+  const int threads = block_threads(B);
+  const uint64_t R = threads / B;
+  uint64_t tiles = (rows + R - 1) / R;
+  uint64_t g = (uint64_t)num_cus() * 8;
+  if (g > tiles) g = tiles;
+  g = ((g + kNumXcd - 1) / kNumXcd) * kNumXcd;
+  if (g < kNumXcd) g = kNumXcd;
+  return (int)g;
+}
+
+static HamView ham_view(const qk_ham* H) {
+  HamView v;
+  v.states = H->basis->d_states;
+  v.rowptr = H->d_rowptr;
+  v.cols = H->d_cols;
+  v.diag = H->d_diag;
+  v.D = (uint32_t)H->basis->D;
+  return v;
+}
+
+ModelArgs model_args(const qk_ham* H) {
+  ModelArgs a;
+  a.L = H->basis->L;
+  a.N = H->basis->N;
+  a.pbc = H->p.pbc;
+  a.B = H->batch;
+  a.half_jxy = 0.5 * H->p.jxy;
+  a.jz = H->p.jz;
+  a.lmask = a.L >= 32 ? 0xffffffffu : ((1u << a.L) - 1u);
+  return a;
+}
+
+KState make_kstate(const qk_krylov* k) {
+  const int m = k->m, B = k->batch;
+  double* p = k->d_coef;
+  KState s;
+  s.alpha = p;
+  s.beta = p + (size_t)m * B;
+  s.sigma = p + (size_t)2 * m * B;
+  s.n0 = p + (size_t)(3 * m + 1) * B;
+  s.gre = p + (size_t)(3 * m + 2) * B;
+  s.gim = p + (size_t)(4 * m + 2) * B;
+  s.err = p + (size_t)(5 * m + 2) * B;
+  s.mused = k->d_int;
+  s.status = k->d_int + B;
+  return s;
+}
+
+qk_status launch_basis_build(qk_basis* b, hipStream_t s) {
+  hipLaunchKernelGGL(k_binom_table, dim3(1), dim3(1), 0, s, b->d_binom);
+  QK_HIP(hipGetLastError());
+  const uint64_t per = (uint64_t)kBasisThreads * kBasisChunk;
+  const uint64_t blocks = ((uint64_t)b->D + per - 1) / per;
+  hipLaunchKernelGGL(k_basis_build, dim3((unsigned)blocks), dim3(kBasisThreads), 0, s, b->d_states,
+                     (uint32_t)b->D, b->L, b->N, b->d_binom);
+  QK_HIP(hipGetLastError());
+  return QK_OK;
+}
+
+qk_status launch_rank(const qk_basis* b, const uint64_t* d_in, int64_t n, int64_t* d_out, hipStream_t s) {
+  if (n == 0) return QK_OK;
+  const int64_t blocks = (n + 255) / 256;
+  hipLaunchKernelGGL(k_rank, dim3((unsigned)blocks), dim3(256), 0, s, d_in, n, d_out, b->L, b->N, b->d_binom);
+  QK_HIP(hipGetLastError());
+  return QK_OK;
+}
+
+qk_status launch_csr_diag(qk_ham* H, hipStream_t s) {
+  const ModelArgs a = model_args(H);
+  const uint32_t D = (uint32_t)H->basis->D;
+  hipLaunchKernelGGL(k_csr_diag, dim3((D + 255) / 256), dim3(256), 0, s, H->basis->d_states, D, a, H->d_fields,
+                     H->d_diag);
+  QK_HIP(hipGetLastError());
+  return QK_OK;
+}
+
+qk_status launch_csr_build(qk_ham* H, hipStream_t s) {
+  const ModelArgs a = model_args(H);
+  const uint32_t D = (uint32_t)H->basis->D;
+  // count into rowptr[1..D], then an inclusive scan in place gives the row pointers
+  QK_HIP(hipMemsetAsync(H->d_rowptr, 0, sizeof(uint32_t), s));
+  hipLaunchKernelGGL(k_csr_count, dim3((D + 255) / 256), dim3(256), 0, s, H->basis->d_states, D, a, H->d_rowptr + 1);
+  QK_HIP(hipGetLastError());
+  size_t tmp_bytes = 0;
+  QK_HIP(hipcub::DeviceScan::InclusiveSum(nullptr, tmp_bytes, H->d_rowptr + 1, H->d_rowptr + 1, (int)D, s));
+  void* tmp = nullptr;
+  QK_HIP(hipMallocAsync(&tmp, tmp_bytes + 16, s));
+  hipError_t e = hipcub::DeviceScan::InclusiveSum(tmp, tmp_bytes, H->d_rowptr + 1, H->d_rowptr + 1, (int)D, s);
+  QK_HIP(hipFreeAsync(tmp, s));
+  QK_HIP(e);
+  uint32_t nnz = 0;
+  QK_HIP(hipMemcpyAsync(&nnz, H->d_rowptr + D, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+  QK_HIP(hipStreamSynchronize(s));
+  H->nnz = nnz;
+  QK_HIP(hipMalloc(&H->d_cols, sizeof(uint32_t) * (size_t)(nnz > 0 ? nnz : 1)));
+  hipLaunchKernelGGL(k_csr_fill, dim3((D + 255) / 256), dim3(256), 0, s, H->basis->d_states, D, a, H->basis->d_binom,
+                     H->d_rowptr, H->d_cols);
+  QK_HIP(hipGetLastError());
+  return launch_csr_diag(H, s);
+}
+
+qk_status launch_ham_apply(const qk_ham* H, const void* x, void* y, int dtype, hipStream_t s) {
+  const ModelArgs a = model_args(H);
+  const HamView hv = ham_view(H);
+  const int threads = block_threads(a.B);
+  const int grid = stream_grid(hv.D, a.B);
+  const bool csr = H->p.mode == QK_CSR;
+  if (dtype == QK_C128) {
+    if (csr)
+      hipLaunchKernelGGL((k_apply<double, true>), dim3(grid), dim3(threads), 0, s, (const double2*)x, (double2*)y, a,
+                         hv, H->basis->d_binom, H->d_fields);
+    else
+      hipLaunchKernelGGL((k_apply<double, false>), dim3(grid), dim3(threads), 0, s, (const double2*)x, (double2*)y,
+                         a, hv, H->basis->d_binom, H->d_fields);
+  } else {
+    if (csr)
+      hipLaunchKernelGGL((k_apply<float, true>), dim3(grid), dim3(threads), 0, s, (const float2*)x, (float2*)y, a,
+                         hv, H->basis->d_binom, H->d_fields);
+    else
+      hipLaunchKernelGGL((k_apply<float, false>), dim3(grid), dim3(threads), 0, s, (const float2*)x, (float2*)y, a,
+                         hv, H->basis->d_binom, H->d_fields);
+  }
+  QK_HIP(hipGetLastError());
+  return QK_OK;
+}
+
+template <typename T>
+static qk_status krylov_step_t(qk_krylov* k, void* psi_v, double dt, hipStream_t s) {
+  using V = typename Cx<T>::V;
+  const qk_ham* H = k->H;
+  const ModelArgs a = model_args(H);
+  const HamView hv = ham_view(H);
+  const int B = a.B, threads = block_threads(B), G = k->grid, m = k->m;
+  const uint32_t D = hv.D;
+  const size_t stride = (size_t)D * B;
+  V* psi = (V*)psi_v;
+  V* U = (V*)k->d_U;
+  const KState st = make_kstate(k);
+  const bool csr = H->p.mode == QK_CSR;
+  // breakdown threshold relative to the largest coefficient so far
+  const double rtol = std::is_same<T, double>::value ? 1e-12 : 1e-5;
+  for (int j = 0; j < m; ++j) {
+    LanczosArgs la{j, m, rtol};
+    const V* uj = j == 0 ? psi : U + (size_t)(j - 1) * stride;
+    const V* ujm1 = j == 0 ? nullptr : (j == 1 ? psi : U + (size_t)(j - 2) * stride);
+    V* w = U + (size_t)j * stride;
+    if (csr)
+      hipLaunchKernelGGL((k_lanczos_A<T, true>), dim3(G), dim3(threads), 0, s, uj, ujm1, w, a, hv,
+                         H->basis->d_binom, H->d_fields, st, la, k->d_partB, G, k->d_partA);
+    else
+      hipLaunchKernelGGL((k_lanczos_A<T, false>), dim3(G), dim3(threads), 0, s, uj, ujm1, w, a, hv,
+                         H->basis->d_binom, H->d_fields, st, la, k->d_partB, G, k->d_partA);
+    QK_HIP(hipGetLastError());
+    hipLaunchKernelGGL((k_lanczos_B<T>), dim3(G), dim3(threads), 0, s, uj, w, D, B, st, la, k->d_partA, G,
+                       k->d_partB, j + 1 < m ? 1 : 0);
+    QK_HIP(hipGetLastError());
+  }
+  hipLaunchKernelGGL(k_small_expm, dim3(B), dim3(64), 0, s, st, m, B, dt, k->d_partB, G);
+  QK_HIP(hipGetLastError());
+  hipLaunchKernelGGL((k_combine<T>), dim3(G), dim3(threads), 0, s, psi, U, D, B, m, st);
+  QK_HIP(hipGetLastError());
+  return QK_OK;
+}
+
+qk_status launch_krylov_step(qk_krylov* k, void* psi, double dt, hipStream_t s) {
+  if (k->dtype == QK_C128) return krylov_step_t<double>(k, psi, dt, s);
+  return krylov_step_t<float>(k, psi, dt, s);
+}
+
+qk_status launch_return_prob(const qk_basis* b, int64_t r0, const void* psi0, const void* psi, int dtype, int B,
+                             double* P, hipStream_t s) {
+  const uint32_t D = (uint32_t)b->D;
+  if (psi0 == nullptr) {
+    if (dtype == QK_C128)
+      hipLaunchKernelGGL(k_prob_basis_state<double>, dim3(1), dim3(64), 0, s, (const double2*)psi, (uint32_t)r0, B, P);
+    else
+      hipLaunchKernelGGL(k_prob_basis_state<float>, dim3(1), dim3(64), 0, s, (const float2*)psi, (uint32_t)r0, B, P);
+    QK_HIP(hipGetLastError());
+    return QK_OK;
+  }
+  const int threads = block_threads(B);
+  const int G = stream_grid(D, B);
+  double* part = nullptr;
+  QK_HIP(hipMallocAsync((void**)&part, sizeof(double) * (size_t)G * 2 * B, s));
+  if (dtype == QK_C128)
+    hipLaunchKernelGGL(k_overlap_partial<double>, dim3(G), dim3(threads), 0, s, (const double2*)psi0,
+                       (const double2*)psi, D, B, part);
+  else
+    hipLaunchKernelGGL(k_overlap_partial<float>, dim3(G), dim3(threads), 0, s, (const float2*)psi0,
+                       (const float2*)psi, D, B, part);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(k_overlap_final, dim3(1), dim3(kMaxBlock), 0, s, part, G, B, P);
+    e = hipGetLastError();
+  }
+  QK_HIP(hipFreeAsync(part, s));
+  QK_HIP(e);
+  return QK_OK;
+}
+
+int krylov_grid(uint64_t D, int B) { return stream_grid(D, B); }
+
+}  // namespace qk

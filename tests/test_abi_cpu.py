@@ -1,0 +1,83 @@
+"""The C ABI without a GPU: the library loads, exports every symbol that
+include/qk.h declares, and rejects bad arguments before any device work."""
+import ctypes as C
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "qk.h")
+LIB = os.path.join(ROOT, "paper_1704_02770_amd", "libqkrylov.so")
+
+pytestmark = pytest.mark.skipif(not os.path.exists(LIB), reason="libqkrylov.so not built (run __graft_entry__.build())")
+
+
+def header_symbols():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(qk_[a-z0-9_]+)\s*\(", txt)))
+
+
+def test_header_declares_north_star_calls():
+    syms = header_symbols()
+    for name in ["qk_basis_build", "qk_ham_apply", "qk_krylov_expm_step", "qk_return_prob"]:
+        assert name in syms
+
+
+def test_library_exports_every_header_symbol():
+    out = subprocess.run(["nm", "-D", "--defined-only", LIB], capture_output=True, text=True, check=True).stdout
+    exported = set(re.findall(r"\bT (qk_[a-z0-9_]+)\b", out))
+    missing = [s for s in header_symbols() if s not in exported]
+    assert not missing, missing
+    # nothing beyond the header is exported under the qk_ prefix
+    assert exported <= set(header_symbols())
+
+
+def test_binding_covers_every_symbol():
+    import paper_1704_02770_amd as qk
+    from paper_1704_02770_amd import _native
+    assert set(_native.SIGNATURES) == set(header_symbols())
+    for s in header_symbols():
+        if s.endswith("_destroy") or s == "qk_last_error":
+            continue
+        assert hasattr(qk, s), s
+
+
+def test_version_and_validation_without_device():
+    import paper_1704_02770_amd as qk
+    from paper_1704_02770_amd._native import lib
+    assert qk.qk_abi_version() == 1
+    out = C.c_void_p()
+    assert lib.qk_basis_build(40, 20, None, C.byref(out)) == qk.QK_EINVAL
+    assert b"L must be" in lib.qk_last_error()
+    assert lib.qk_basis_build(1, 1, None, C.byref(out)) == qk.QK_EINVAL
+    assert lib.qk_basis_build(8, 0, None, C.byref(out)) == qk.QK_EINVAL
+    assert lib.qk_basis_build(8, 8, None, C.byref(out)) == qk.QK_EINVAL
+    assert lib.qk_basis_build(8, 4, None, None) == qk.QK_EINVAL
+    assert lib.qk_ham_apply(None, None, None, 0, None) == qk.QK_EINVAL
+    assert lib.qk_krylov_create(None, 30, 0, 0, C.byref(out)) == qk.QK_EINVAL
+    assert lib.qk_krylov_expm_step(None, None, 0.1, None, None) == qk.QK_EINVAL
+    assert lib.qk_return_prob(None, 0, None, None, 0, 1, None, None) == qk.QK_EINVAL
+    D = C.c_int64()
+    assert lib.qk_basis_dim(None, C.byref(D)) == qk.QK_EINVAL
+    lib.qk_basis_destroy(None)
+    lib.qk_ham_destroy(None)
+    lib.qk_krylov_destroy(None)
+
+
+def test_fields_host_function():
+    # host-side field generation of Eq. (1); checked against the definition
+    import paper_1704_02770_amd as qk
+    from oracle import model
+    from workloads import BETA_GOLDEN, phases
+    phi = phases(3, 0)
+    got = qk.qk_fields_quasiperiodic(28, 1.5, BETA_GOLDEN, phi)
+    for b in range(3):
+        assert np.allclose(got[b], model.fields(28, 1.5, BETA_GOLDEN, phi[b]), rtol=0, atol=1e-14)
+    with pytest.raises(qk.QkError):
+        qk.qk_fields_quasiperiodic(0, 1.0, 0.5, [0.0])
+    with pytest.raises(qk.QkError):
+        qk.qk_fields_quasiperiodic(8, float("nan"), 0.5, [0.0])

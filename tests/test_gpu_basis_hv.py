@@ -1,0 +1,136 @@
+"""GPU parity of the basis (bit-exact) and of y = H x (matrix-free and CSR,
+complex128 and complex64, single and batched) against the oracle."""
+import numpy as np
+import pytest
+import torch
+
+import paper_1704_02770_amd as qk
+from gpu_util import max_rel, say, to_dev, to_host
+from oracle import basis as OB
+from oracle import hamiltonian as OH
+from oracle import model as OM
+from workloads import BETA_GOLDEN, phases, random_complex, random_fields
+
+pytestmark = pytest.mark.gpu
+
+TOL = {torch.complex128: 1e-13, torch.complex64: 2e-6}
+
+
+@pytest.mark.parametrize("L,N", [(2, 1), (3, 1), (4, 2), (5, 2), (8, 4), (9, 7), (10, 3), (12, 6), (16, 8),
+                                 (17, 5), (20, 10), (22, 11)])
+def test_basis_bitwise(L, N):
+    say("basis", L, N)
+    b = qk.qk_basis_build(L, N)
+    assert qk.qk_basis_dim(b) == OB.sector_dim(L, N)
+    st = to_host(qk.qk_basis_states(b)).view(np.uint32).astype(np.int64)
+    assert np.array_equal(st, OB.sector_states(L, N))
+
+
+def test_rank_lookup():
+    L, N = 14, 7
+    b = qk.qk_basis_build(L, N)
+    st = OB.sector_states(L, N)
+    say("rank", L, N)
+    assert np.array_equal(qk.qk_basis_rank(b, st), np.arange(len(st)))
+    bad = np.array([0, (1 << 15) | 0x3F, 0x3F, 1 << 40], dtype=np.uint64)   # bit above L, or popcount != N
+    assert np.all(qk.qk_basis_rank(b, bad) == -1)
+    assert qk.qk_basis_rank(b, [OM.neel_state(L)])[0] == OB.lookup(st, [OM.neel_state(L)])[0]
+
+
+CASES = [(2, 1, False), (2, 1, True), (3, 1, True), (4, 2, True), (6, 3, False), (8, 4, True), (9, 4, True),
+         (10, 5, False), (12, 6, True), (14, 7, True), (16, 8, False), (16, 8, True), (18, 9, True)]
+
+
+@pytest.mark.parametrize("dtype", [torch.complex128, torch.complex64])
+@pytest.mark.parametrize("mode", [qk.QK_MATFREE, qk.QK_CSR])
+@pytest.mark.parametrize("L,N,pbc", CASES)
+def test_hv_single(L, N, pbc, mode, dtype):
+    h = random_fields(L, 100 + L)
+    jxy, jz = 1.0, 0.8
+    b = qk.qk_basis_build(L, N)
+    say("hv", L, N, pbc, mode, dtype)
+    H = qk.qk_ham_create(b, jxy, jz, pbc, h, mode)
+    D = qk.qk_basis_dim(b)
+    x = random_complex(D, 7 + L)
+    xd = to_dev(x, dtype)
+    y = to_host(qk.qk_ham_apply(H, xd))
+    xr = to_host(xd).astype(np.complex128)
+    ref = OH.build_csr(L, N, pbc, jxy, jz, h) @ xr
+    assert max_rel(y, ref) < TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype", [torch.complex128, torch.complex64])
+@pytest.mark.parametrize("mode", [qk.QK_MATFREE, qk.QK_CSR])
+@pytest.mark.parametrize("Bn", [2, 3, 8])
+def test_hv_batched(Bn, mode, dtype):
+    L, N, pbc = 12, 6, True
+    phi = phases(Bn, 3)
+    hs = np.stack([OM.fields(L, 2.0, BETA_GOLDEN, p) for p in phi])
+    b = qk.qk_basis_build(L, N)
+    say("hv batched", Bn, mode, dtype)
+    H = qk.qk_ham_create(b, 1.0, 1.0, pbc, hs, mode)
+    D = qk.qk_basis_dim(b)
+    x = random_complex(D * Bn, 11).reshape(D, Bn)
+    xd = to_dev(x, dtype)
+    y = to_host(qk.qk_ham_apply(H, xd))
+    ref = OH.apply_rows(L, N, pbc, 1.0, 1.0, hs, to_host(xd).astype(np.complex128), np.arange(D))
+    assert max_rel(y, ref) < TOL[dtype]
+
+
+def test_hv_hermitian_and_set_fields():
+    L, N, pbc = 16, 8, True
+    b = qk.qk_basis_build(L, N)
+    D = qk.qk_basis_dim(b)
+    say("hermitian", L)
+    H = qk.qk_ham_create(b, 1.0, 1.0, pbc, random_fields(L, 1))
+    u = to_dev(random_complex(D, 1))
+    v = to_dev(random_complex(D, 2))
+    Hu = qk.qk_ham_apply(H, u)
+    Hv = qk.qk_ham_apply(H, v)
+    a = torch.vdot(u, Hv).item()
+    c = torch.vdot(v, Hu).item()
+    assert abs(a - np.conj(c)) < 1e-11 * abs(a)
+    # replacing the fields changes only the diagonal
+    h2 = random_fields(L, 9)
+    qk.qk_ham_set_fields(H, h2)
+    y = to_host(qk.qk_ham_apply(H, u))
+    ref = OH.build_csr(L, N, pbc, 1.0, 1.0, h2) @ to_host(u)
+    assert max_rel(y, ref) < 1e-13
+
+
+def test_hv_errors():
+    b = qk.qk_basis_build(8, 4)
+    H = qk.qk_ham_create(b, 1.0, 1.0, True, np.zeros(8))
+    x = torch.zeros(70, dtype=torch.complex128, device="cuda")
+    with pytest.raises(qk.QkError):
+        qk.qk_ham_apply(H, x, x)            # aliasing
+    with pytest.raises(qk.QkError):
+        qk.qk_ham_create(b, 1.0, float("inf"), True, np.zeros(8))
+    with pytest.raises(qk.QkError):
+        qk.qk_ham_create(b, 1.0, 1.0, True, np.zeros((65, 8)))
+    bb = qk.qk_basis_build(27, 13)     # D = 20,058,300 > 2^24
+    with pytest.raises(qk.QkError):
+        qk.qk_ham_create(bb, 1.0, 1.0, True, np.zeros(27), qk.QK_CSR)
+
+
+@pytest.mark.parametrize("L,pbc", [(24, False), (28, True)])
+def test_hv_full_size_sampled_rows(L, pbc):
+    # large sectors in the launch configuration of the benchmark: every row
+    # of a seeded sample is recomputed by the oracle one by one
+    N = L // 2
+    say("hv full size", L, pbc)
+    b = qk.qk_basis_build(L, N)
+    D = qk.qk_basis_dim(b)
+    h = OM.fields(L, 1.5, BETA_GOLDEN, phases(1, 0)[0])
+    H = qk.qk_ham_create(b, 1.0, 1.0, pbc, h)
+    xh = random_complex(D, 5)
+    x = to_dev(xh)
+    y = qk.qk_ham_apply(H, x)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(1)
+    rows = np.unique(np.concatenate([rng.integers(0, D, 3000), [0, 1, D - 2, D - 1]]))
+    basis = OB.sector_states(L, N)
+    st_dev = to_host(qk.qk_basis_states(b)).view(np.uint32).astype(np.int64)
+    assert np.array_equal(st_dev, basis)
+    ref = OH.apply_rows(L, N, pbc, 1.0, 1.0, h, xh, rows, basis=basis)
+    assert max_rel(to_host(y)[rows], ref) < 1e-13

@@ -1,0 +1,247 @@
+"""GPU parity of the Krylov step and the survival probability against the
+oracle: dense propagation at small L, Lanczos coefficients, breakdown and
+error cases, the complex64 storage path, batching and determinism."""
+import numpy as np
+import pytest
+import torch
+
+import paper_1704_02770_amd as qk
+from gpu_util import max_rel, neel_row, say, to_dev, to_host
+from oracle import basis as OB
+from oracle import exact as OX
+from oracle import hamiltonian as OH
+from oracle import krylov as OK
+from oracle import model as OM
+from workloads import BETA_GOLDEN, WORKLOADS, phases, random_complex, random_fields
+
+pytestmark = pytest.mark.gpu
+
+
+def _problem(L, pbc, h=1.5, jz=1.0, phi=0.4, mode=qk.QK_MATFREE, Bn=1):
+    N = L // 2
+    b = qk.qk_basis_build(L, N)
+    if Bn == 1:
+        hf = OM.fields(L, h, BETA_GOLDEN, phi)
+    else:
+        hf = np.stack([OM.fields(L, h, BETA_GOLDEN, p) for p in phases(Bn, 2)])
+    H = qk.qk_ham_create(b, 1.0, jz, pbc, hf, mode)
+    return b, H, hf
+
+
+def _neel_psi(b, L, dtype=torch.complex128, Bn=1):
+    D = qk.qk_basis_dim(b)
+    r0 = int(qk.qk_basis_rank(b, [OM.neel_state(L)])[0])
+    psi = torch.zeros((D, Bn) if Bn > 1 else D, dtype=dtype, device="cuda")
+    psi[r0] = 1.0
+    return psi, r0
+
+
+@pytest.mark.parametrize("mode", [qk.QK_MATFREE, qk.QK_CSR])
+@pytest.mark.parametrize("L,pbc", [(6, True), (8, False), (10, True), (12, True), (14, False)])
+def test_steps_vs_dense(L, pbc, mode):
+    b, H, hf = _problem(L, pbc, mode=mode)
+    psi, r0 = _neel_psi(b, L)
+    assert r0 == neel_row(L)
+    k = qk.qk_krylov_create(H, 30)
+    Hd = OH.build_dense(L, L // 2, pbc, 1.0, 1.0, hf)
+    eig = OX.eig(Hd)
+    dt, steps = 0.1, 25
+    P = torch.empty(steps, dtype=torch.float64, device="cuda")
+    say("krylov dense", L, pbc, mode)
+    for s in range(steps):
+        qk.qk_krylov_expm_step(k, psi, dt)
+        qk.qk_return_prob(b, psi, r0=r0, out=P[s:s + 1])
+    t = dt * np.arange(1, steps + 1)
+    F = OX.survival_probability(Hd, r0, t, eig)
+    assert np.max(np.abs(to_host(P) - F)) < 1e-10
+    e0 = np.zeros(len(Hd), complex)
+    e0[r0] = 1
+    assert np.linalg.norm(to_host(psi) - OX.evolve(Hd, e0, [t[-1]], eig)[0]) < 1e-9
+
+
+def test_workload_L16_to_t10():
+    # the small periodic chain: L=16, h=1.5, phi from seed 0, m=30, dt=0.1 to t=10
+    w = WORKLOADS["xxz_L16_pbc"]
+    phi = w.phis()[0]
+    b, H, hf = _problem(w.L, w.pbc, h=w.h, phi=phi)
+    psi, r0 = _neel_psi(b, w.L)
+    k = qk.qk_krylov_create(H, w.m)
+    n = int(round(w.t_end / w.dt))
+    P = torch.empty(n, dtype=torch.float64, device="cuda")
+    say("workload L16", n)
+    for s in range(n):
+        qk.qk_krylov_expm_step(k, psi, w.dt)
+        qk.qk_return_prob(b, psi, r0=r0, out=P[s:s + 1])
+    Hd = OH.build_dense(w.L, w.n_up, w.pbc, w.jxy, w.jz, hf)
+    F = OX.survival_probability(Hd, r0, w.dt * np.arange(1, n + 1))
+    assert np.max(np.abs(to_host(P) - F)) < 1e-10
+    assert abs(torch.linalg.vector_norm(psi).item() - 1.0) < 1e-12
+
+
+def test_lanczos_coefficients_match_arnoldi():
+    L = 12
+    b, H, hf = _problem(L, True)
+    psi, r0 = _neel_psi(b, L)
+    m = 12
+    k = qk.qk_krylov_create(H, m)
+    info = qk.qk_krylov_expm_step(k, psi, 0.05, info=True)
+    assert info[0]["m_used"] == m and info[0]["status"] == 0
+    a, be, mu = qk.qk_krylov_coefficients(k)
+    Hd = OH.build_dense(L, L // 2, True, 1.0, 1.0, hf)
+    e0 = np.zeros(len(Hd), complex)
+    e0[r0] = 1
+    V, A, beta0, hn, mo = OK.arnoldi(lambda v: Hd @ v, e0, m)
+    assert np.allclose(a, np.diag(A).real, rtol=0, atol=1e-12)
+    assert np.allclose(be[:-1], np.diag(A, -1).real, rtol=0, atol=1e-12)
+    assert be[-1] == pytest.approx(hn, abs=1e-12)
+    # closed forms of the first coefficients for the Neel state
+    assert a[0] == pytest.approx(Hd[r0, r0], abs=1e-13)
+    assert be[0] == pytest.approx(0.5 * np.sqrt(L), abs=1e-13)
+    assert info[0]["beta0"] == pytest.approx(1.0, abs=1e-15)
+    _, inf_o = OK.expm_step(lambda v: Hd @ v, e0, 0.05, m)
+    assert info[0]["err_est"] == pytest.approx(inf_o["err_est"], rel=1e-6)
+
+
+def test_small_m_matches_krylov_oracle():
+    # with m = 6 the truncation error is visible; the GPU must reproduce the
+    # Krylov approximation itself, not the exact exponential
+    L = 10
+    b, H, hf = _problem(L, True)
+    psi, r0 = _neel_psi(b, L)
+    Hd = OH.build_dense(L, L // 2, True, 1.0, 1.0, hf)
+    e0 = np.zeros(len(Hd), complex)
+    e0[r0] = 1
+    k = qk.qk_krylov_create(H, 6)
+    ref = e0
+    say("small m")
+    for _ in range(5):
+        qk.qk_krylov_expm_step(k, psi, 0.3)
+        ref, _ = OK.expm_step(lambda v: Hd @ v, ref, 0.3, 6)
+    exact = OX.evolve(Hd, e0, [1.5])[0]
+    got = to_host(psi)
+    assert np.linalg.norm(got - ref) < 1e-11
+    assert np.linalg.norm(ref - exact) > 1e-6
+
+
+def test_breakdown_eigenvector_and_small_sector():
+    L = 8
+    b, H, hf = _problem(L, True)
+    Hd = OH.build_dense(L, L // 2, True, 1.0, 1.0, hf)
+    w, U = np.linalg.eigh(Hd)
+    psi = to_dev(U[:, 5].astype(complex))
+    k = qk.qk_krylov_create(H, 30)
+    say("breakdown eigenvector")
+    info = qk.qk_krylov_expm_step(k, psi, 0.7, info=True)
+    assert info[0]["m_used"] == 1
+    assert abs(np.vdot(U[:, 5], to_host(psi))) ** 2 == pytest.approx(1.0, abs=1e-13)
+    # D = 6 < m: the recurrence stops at the sector dimension and is exact
+    b4, H4, hf4 = _problem(4, True)
+    psi4, r04 = _neel_psi(b4, 4)
+    k4 = qk.qk_krylov_create(H4, 30)
+    info = qk.qk_krylov_expm_step(k4, psi4, 1.3, info=True)
+    assert 1 <= info[0]["m_used"] <= 6
+    H4d = OH.build_dense(4, 2, True, 1.0, 1.0, hf4)
+    e0 = np.zeros(6, complex)
+    e0[r04] = 1
+    assert np.linalg.norm(to_host(psi4) - OX.evolve(H4d, e0, [1.3])[0]) < 1e-12
+
+
+@pytest.mark.parametrize("pbc", [False, True])
+def test_two_site_chain(pbc):
+    b = qk.qk_basis_build(2, 1)
+    h = np.array([0.9, -0.4])
+    H = qk.qk_ham_create(b, 0.8, 0.6, pbc, h)
+    psi = torch.tensor([1.0, 0.0], dtype=torch.complex128, device="cuda")
+    k = qk.qk_krylov_create(H, 4)
+    say("two site", pbc)
+    qk.qk_krylov_expm_step(k, psi, 1.1)
+    Hd = OH.build_dense(2, 1, pbc, 0.8, 0.6, h)
+    assert np.allclose(to_host(psi), OX.evolve(Hd, np.array([1, 0], complex), [1.1])[0], atol=1e-13)
+
+
+def test_zero_and_nonfinite_vectors():
+    L = 8
+    b, H, hf = _problem(L, True)
+    D = qk.qk_basis_dim(b)
+    k = qk.qk_krylov_create(H, 10)
+    z = torch.zeros(D, dtype=torch.complex128, device="cuda")
+    info = qk.qk_krylov_expm_step(k, z, 0.1, info=True)
+    assert info[0]["m_used"] == 0 and info[0]["status"] == 0
+    assert torch.count_nonzero(z).item() == 0
+    bad = to_dev(random_complex(D, 3))
+    bad[7] = complex(float("nan"), 0.0)
+    say("nan vector")
+    info = qk.qk_krylov_expm_step(k, bad, 0.1, info=True)
+    assert info[0]["status"] == qk.QK_ENUMERIC
+    with pytest.raises(qk.QkError):
+        qk.qk_krylov_expm_step(k, z, float("inf"))
+    with pytest.raises(qk.QkError):
+        qk.qk_krylov_create(H, 0)
+    with pytest.raises(qk.QkError):
+        qk.qk_krylov_create(H, 65)
+
+
+def test_complex64_storage_path():
+    L = 16
+    b, H, hf = _problem(L, True)
+    psi, r0 = _neel_psi(b, L, torch.complex64)
+    k = qk.qk_krylov_create(H, 30, torch.complex64)
+    steps, dt = 50, 0.1
+    P = torch.empty(steps, dtype=torch.float64, device="cuda")
+    say("complex64 path")
+    for s in range(steps):
+        qk.qk_krylov_expm_step(k, psi, dt)
+        qk.qk_return_prob(b, psi, r0=r0, out=P[s:s + 1])
+    Hd = OH.build_dense(L, L // 2, True, 1.0, 1.0, hf)
+    F = OX.survival_probability(Hd, r0, dt * np.arange(1, steps + 1))
+    err = np.max(np.abs(to_host(P) - F))
+    say("complex64 max |dP| =", err)
+    assert err < 1e-5
+
+
+@pytest.mark.parametrize("dtype", [torch.complex128, torch.complex64])
+def test_batched_equals_single(dtype):
+    L, Bn = 12, 3
+    b, Hb, hs = _problem(L, True, h=2.0, Bn=Bn)
+    D = qk.qk_basis_dim(b)
+    r0 = neel_row(L)
+    psib = torch.zeros((D, Bn), dtype=dtype, device="cuda")
+    psib[r0] = 1.0
+    kb = qk.qk_krylov_create(Hb, 30, dtype)
+    say("batched", dtype)
+    for _ in range(10):
+        qk.qk_krylov_expm_step(kb, psib, 0.1)
+    Pb = to_host(qk.qk_return_prob(b, psib, r0=r0, batch=Bn))
+    for i in range(Bn):
+        H1 = qk.qk_ham_create(b, 1.0, 1.0, True, hs[i])
+        p1 = torch.zeros(D, dtype=dtype, device="cuda")
+        p1[r0] = 1.0
+        k1 = qk.qk_krylov_create(H1, 30, dtype)
+        for _ in range(10):
+            qk.qk_krylov_expm_step(k1, p1, 0.1)
+        tol = 1e-12 if dtype == torch.complex128 else 2e-5
+        assert max_rel(to_host(psib[:, i].contiguous()), to_host(p1)) < tol
+        assert abs(Pb[i] - to_host(qk.qk_return_prob(b, p1, r0=r0))[0]) < tol
+
+
+def test_return_prob_general_state_and_determinism():
+    L = 14
+    b, H, hf = _problem(L, True)
+    D = qk.qk_basis_dim(b)
+    p0 = random_complex(D, 4)
+    p0 /= np.linalg.norm(p0)
+    psi0 = to_dev(p0)
+    runs = []
+    say("determinism")
+    for _ in range(2):
+        psi = psi0.clone()
+        k = qk.qk_krylov_create(H, 30)
+        for _ in range(5):
+            qk.qk_krylov_expm_step(k, psi, 0.1)
+        runs.append(to_host(psi))
+    assert np.array_equal(runs[0], runs[1])
+    P = to_host(qk.qk_return_prob(b, to_dev(runs[0]), psi0=psi0))[0]
+    Hd = OH.build_dense(L, L // 2, True, 1.0, 1.0, hf)
+    ref = OX.evolve(Hd, p0, [0.5])[0]
+    assert P == pytest.approx(OX.overlap_probability(p0, ref), abs=1e-12)
+    assert np.linalg.norm(runs[0] - ref) < 1e-10
