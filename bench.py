@@ -1,0 +1,292 @@
+#!/usr/bin/env python3
+"""Krylov time-evolution benchmark on one MI355X.
+
+Workload: spin-1/2 XXZ ring L=28 in the Sz=0 sector (D = 40,116,600; the
+strong-scaling system of the paper's Sec. 5), J = Delta = 1, quasiperiodic
+fields h_i = 1.5 cos(2 pi beta i + phi) with beta the inverse golden ratio and
+phi from numpy's default_rng(0), Neel initial state, Krylov dimension m = 30,
+dt = 0.1.  A step is one Krylov step psi <- exp(-i dt H) psi (m Lanczos
+iterations, the projected exponential, the combination) followed by the
+survival probability.  Inputs are synthetic and resident in HBM before the
+timed region starts.
+
+Forms: plain complex128 (the headline `value`), complex64 storage, and a
+batch of 8 phases in complex64 ([D][8] layout).  Also reported: standalone
+y = H x throughput (algorithmic bytes 2 s D per call), a device-copy ceiling,
+the roofline of the dominant kernel from HIP events recorded on the step's
+stream, and the CPU oracle timed on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Krylov steps/sec + achieved HBM GB/s of H·v at L=28 Sz=0, plain FP64 vs batched/FP32"
+PEAK_HBM_GBS = 8000.0          # MI355X HBM3E, published
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_lanczos_h_L28.json")
+KERNEL_SRC = os.path.join(ROOT, "paper_1704_02770_amd", "csrc", "qk_kernels.hip")
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--L", type=int, default=28)
+    ap.add_argument("--m", type=int, default=30)
+    ap.add_argument("--dt", type=float, default=0.1)
+    ap.add_argument("--h", type=float, default=1.5)
+    ap.add_argument("--batch", type=int, default=8)
+    ap.add_argument("--forms", default="fp64,fp32,batched")
+    ap.add_argument("--hv-reps", type=int, default=20)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU time of the oracle sample")
+    return ap.parse_args()
+
+
+def source_sha():
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def run_form(qk, torch, b, fields, m, dt, dtype, steps, warmup, r0):
+    """Times `steps` Krylov steps (+ survival probability) after `warmup`."""
+    D = qk.qk_basis_dim(b)
+    B = fields.shape[0]
+    H = qk.qk_ham_create(b, 1.0, 1.0, True, fields)
+    k = qk.qk_krylov_create(H, m, dtype)
+    psi = torch.zeros((D, B) if B > 1 else D, dtype=dtype, device="cuda")
+    psi[r0] = 1.0
+    P = torch.empty((steps + warmup, B), dtype=torch.float64, device="cuda")
+    for s in range(warmup):
+        qk.qk_krylov_expm_step(k, psi, dt)
+        qk.qk_return_prob(b, psi, r0=r0, batch=B, out=P[s])
+    torch.cuda.synchronize()
+    # timed region; HIP events bracket every kernel launch on the same stream
+    qk.qk_krylov_profile(k, True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(steps):
+        qk.qk_krylov_expm_step(k, psi, dt)
+        qk.qk_return_prob(b, psi, r0=r0, batch=B, out=P[warmup + s])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = qk.qk_krylov_profile_read(k)
+    qk.qk_krylov_profile(k, False)
+    # same number of steps without events, to show their cost
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    for s in range(steps):
+        qk.qk_krylov_expm_step(k, psi, dt)
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    info = qk.qk_krylov_expm_step(k, psi, dt, info=True)
+    norm = torch.linalg.vector_norm(psi.reshape(D, B).to(torch.complex128), dim=0).cpu().tolist()
+    out = dict(sec=t1 - t0, sec_no_events=t3 - t2, prof=prof, m_used=[i["m_used"] for i in info],
+               err_est=max(i["err_est"] for i in info), P_last=P[warmup + steps - 1].cpu().tolist(),
+               norm_drift=max(abs(x - 1.0) for x in norm))
+    del k, H, psi
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    return out
+
+
+def hv_throughput(qk, torch, b, fields, dtype, reps):
+    D = qk.qk_basis_dim(b)
+    H = qk.qk_ham_create(b, 1.0, 1.0, True, fields)
+    g = torch.Generator(device="cuda").manual_seed(0)
+    x = torch.randn(D, dtype=dtype, device="cuda", generator=g)
+    y = torch.empty_like(x)
+    qk.qk_ham_apply(H, x, y)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        qk.qk_ham_apply(H, x, y)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    s = x.element_size()
+    # copy ceiling on the same vector size
+    y.copy_(x)
+    torch.cuda.synchronize()
+    c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    c0.record()
+    for _ in range(reps):
+        y.copy_(x)
+    c1.record()
+    torch.cuda.synchronize()
+    cms = c0.elapsed_time(c1) / reps
+    del H, x, y
+    torch.cuda.empty_cache()
+    return dict(ms=ms, GBps=2 * s * D / ms / 1e6, copy_GBps=2 * s * D / cms / 1e6)
+
+
+def cpu_baseline(L, m, fields, pbc, target_s):
+    """The oracle's Krylov step (Arnoldi with modified Gram-Schmidt, scipy CSR
+    matvec) timed on the host on a bounded sample of the same L=28 workload:
+    the CSR matvec on a seeded sample of rows (scaled to all D rows) and the
+    oracle's vector operations on full-length vectors."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    from oracle import basis as OB
+    from oracle import hamiltonian as OH
+
+    N = L // 2
+    with threadpool_limits(limits=1):
+        t_b0 = time.perf_counter()
+        basis = OB.sector_states(L, N)
+        t_basis = time.perf_counter() - t_b0
+        D = len(basis)
+        rng = np.random.default_rng(0)
+        R = 20000
+        Hs = OH.build_csr(L, N, pbc, 1.0, 1.0, fields, rows=np.sort(rng.choice(D, R, replace=False)))
+        x = (rng.standard_normal(D) + 1j * rng.standard_normal(D)).astype(np.complex128)
+        Hc = Hs.astype(np.complex128)
+        t0 = time.perf_counter()
+        reps = 0
+        while time.perf_counter() - t0 < 0.35 * target_s:
+            Hc @ x
+            reps += 1
+        t_rows = (time.perf_counter() - t0) / reps
+        t_hv = t_rows * D / R
+        y = x.copy()
+        def timeit(fn, n=2):
+            fn()
+            a = time.perf_counter()
+            for _ in range(n):
+                fn()
+            return (time.perf_counter() - a) / n
+        t_dot = timeit(lambda: np.vdot(x, y))
+        t_axpy = timeit(lambda: np.subtract(y, 0.5 * x, out=y))
+        t_norm = timeit(lambda: np.linalg.norm(y))
+    # one oracle step: m matvecs; at iteration j, j+1 (vdot + axpy) pairs, a
+    # norm and a scaling; the final combination V @ c costs about m axpys
+    t_step = m * t_hv + sum((j + 1) * (t_dot + t_axpy) for j in range(m)) + m * (t_norm + t_axpy) + m * t_axpy
+    return dict(value=1.0 / t_step, unit="steps/s", cores=1, kind="oracle",
+                sample=(f"oracle Krylov step at L={L} (D={D}), m={m}: scipy CSR matvec of the oracle's H "
+                        f"timed on {R} seeded rows and scaled by D/{R} ({t_hv:.2f} s per full H*x); numpy "
+                        f"vdot/axpy/norm timed on full-length complex128 vectors; one host thread; "
+                        f"basis build {t_basis:.1f} s not counted"),
+                t_hv_s=t_hv, t_vec_s=dict(dot=t_dot, axpy=t_axpy, norm=t_norm))
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus > 1 or world > 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(see DESIGN.md for how the Krylov step would shard).", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import paper_1704_02770_amd as qk
+    from workloads import BETA_GOLDEN, phases
+
+    L, N, m, dt = args.L, args.L // 2, args.m, args.dt
+    log(f"L={L} m={m} dt={dt} steps={args.steps} warmup={args.warmup}")
+    phi = phases(1, 0)
+    fields1 = qk.qk_fields_quasiperiodic(L, args.h, BETA_GOLDEN, phi)
+    b = qk.qk_basis_build(L, N)
+    D = qk.qk_basis_dim(b)
+    neel = sum(1 << i for i in range(0, L, 2))
+    r0 = int(qk.qk_basis_rank(b, [neel])[0])
+    forms = [f.strip() for f in args.forms.split(",") if f.strip()]
+
+    res = {}
+    hv = {}
+    log("H*x throughput")
+    hv["fp64"] = hv_throughput(qk, torch, b, fields1, torch.complex128, args.hv_reps)
+    hv["fp32"] = hv_throughput(qk, torch, b, fields1, torch.complex64, args.hv_reps)
+    for f in forms:
+        log("form", f)
+        if f == "fp64":
+            res[f] = run_form(qk, torch, b, fields1, m, dt, torch.complex128, args.steps, args.warmup, r0)
+        elif f == "fp32":
+            res[f] = run_form(qk, torch, b, fields1, m, dt, torch.complex64, args.steps, args.warmup, r0)
+        elif f == "batched":
+            fb = qk.qk_fields_quasiperiodic(L, args.h, BETA_GOLDEN, phases(args.batch, 0))
+            res[f] = run_form(qk, torch, b, fb, m, dt, torch.complex64, args.steps, args.warmup, r0)
+        else:
+            raise SystemExit(f"unknown form {f}")
+
+    head = res.get("fp64") or next(iter(res.values()))
+    steps = args.steps
+    value = steps / head["sec"]
+    s_bytes = 16
+    # dominant kernel: the H-pass of each Lanczos iteration.  Algorithmic
+    # bytes per step: iteration 0 reads u_0 and writes w (2 vectors), later
+    # iterations also read u_{j-1} (3 vectors).
+    ms_h, n_h = head["prof"]["lanczos_h"]
+    bytes_h_step = (3 * m - 1) * s_bytes * D
+    achieved = bytes_h_step * steps / (ms_h / 1e3) / 1e9
+    traffic = None
+    if os.path.exists(TRAFFIC_FILE):
+        tr = json.load(open(TRAFFIC_FILE))
+        if tr.get("kernel_source_sha256") == source_sha() and tr.get("m") == m and tr.get("L") == L:
+            traffic = tr.get("bytes_per_launch")
+    roof = dict(bound="hbm", achieved=round(achieved, 1), peak=PEAK_HBM_GBS, unit="GB/s",
+                frac=round(achieved / PEAK_HBM_GBS, 4), traffic=traffic,
+                kernel="k_lanczos_A<double,false> (H-pass: y = H u_j fused with the three-term update and dots)",
+                bytes_per_launch_avg=bytes_h_step / m, ms_per_launch_avg=ms_h / max(n_h, 1))
+
+    def form_summary(r, B, s):
+        sec = r["sec"]
+        kernels = {kname: dict(ms_per_launch=ms / max(n, 1), launches=n) for kname, (ms, n) in r["prof"].items()}
+        step_bytes = (7 * m - 1) * s * D * B
+        return dict(steps_per_s=round(steps / sec, 3), phase_steps_per_s=round(B * steps / sec, 3),
+                    ms_per_step=round(1e3 * sec / steps, 3), ms_per_step_no_events=round(1e3 * r["sec_no_events"] / steps, 3),
+                    step_algorithmic_GBps=round(step_bytes * steps / sec / 1e9, 1), kernels=kernels,
+                    m_used=r["m_used"], err_est=r["err_est"], norm_drift=r["norm_drift"], P_last=r["P_last"])
+
+    out = {
+        "metric": METRIC,
+        "value": round(value, 3),
+        "unit": "steps/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1e3 * head["sec"] / steps, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"XXZ ring L={L} Sz=0 (D={D}), J=Delta=1, h=1.5 quasiperiodic, phi=default_rng(0), "
+                               f"Neel initial state, Lanczos m={m}, dt={dt}, complex128",
+                   "L": L, "D": D, "m": m, "dt": dt, "h": args.h, "pbc": True, "phi": float(phi[0]),
+                   "parallelism": "single GPU"},
+        "roofline": roof,
+        "hv": {k: {kk: round(vv, 4) for kk, vv in v.items()} for k, v in hv.items()},
+        "hv_fp64_GBps": round(hv["fp64"]["GBps"], 1),
+        "hv_fp32_GBps": round(hv["fp32"]["GBps"], 1),
+        "forms": {},
+    }
+    for f, r in res.items():
+        B = args.batch if f == "batched" else 1
+        s = 16 if f == "fp64" else 8
+        out["forms"][f] = form_summary(r, B, s)
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle)")
+        cb = cpu_baseline(L, m, fields1[0], True, args.cpu_seconds)
+        out["cpu_baseline"] = {k: (round(v, 6) if isinstance(v, float) else v) for k, v in cb.items()
+                               if k in ("value", "unit", "cores", "kind", "sample")}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -193,6 +193,27 @@ qk_status qk_krylov_coefficients(const qk_krylov* k, int32_t item, double* alpha
 
 void qk_krylov_destroy(qk_krylov* k);
 
+/*
+ * Per-kernel timing of Krylov steps for benchmarks.  With enable = 1 every
+ * later qk_krylov_expm_step records a pair of HIP events on its stream around
+ * each kernel launch and the running totals restart from zero; enable = 0
+ * stops recording.  qk_krylov_profile_read waits for the recorded events and
+ * writes, for each kernel kind below, the summed elapsed milliseconds and the
+ * number of launches since profiling was enabled (out has QK_NUM_KERNELS
+ * entries).  Kernel kinds: the H-pass of a Lanczos iteration (y = H u fused
+ * with the three-term update and its dot products), the update pass (new
+ * vector and its norm), the projected exponential, the Krylov combination.
+ */
+enum { QK_KERNEL_LANCZOS_H = 0, QK_KERNEL_LANCZOS_UPDATE = 1, QK_KERNEL_SMALL_EXPM = 2, QK_KERNEL_COMBINE = 3,
+       QK_NUM_KERNELS = 4 };
+typedef struct {
+  double ms_total;
+  int64_t launches;
+} qk_kernel_time;
+
+qk_status qk_krylov_profile(qk_krylov* k, int32_t enable);
+qk_status qk_krylov_profile_read(qk_krylov* k, qk_kernel_time* out);
+
 /* ----------------------------------------------------------- observable */
 /*
  * Survival (return) probability of Sec. 4, F = |<psi0|psi>|^2, for every

@@ -14,7 +14,7 @@ import numpy as np
 import torch
 
 from . import _native
-from ._native import HamParams, StepInfo, lib
+from ._native import HamParams, KernelTime, StepInfo, lib
 
 QK_OK, QK_EINVAL, QK_ENOMEM, QK_EHIP, QK_EUNSUPPORTED, QK_ENUMERIC = range(6)
 QK_C128, QK_C64 = 0, 1
@@ -217,6 +217,21 @@ def qk_krylov_coefficients(k: Krylov, item: int = 0):
                                       b.ctypes.data_as(C.POINTER(C.c_double)), C.byref(mu)),
            "qk_krylov_coefficients")
     return a[: mu.value], b[: mu.value], mu.value
+
+
+KERNEL_KINDS = ("lanczos_h", "lanczos_update", "small_expm", "combine")
+
+
+def qk_krylov_profile(k: Krylov, enable: bool = True) -> None:
+    """Start (totals reset) or stop HIP-event timing of every kernel of later steps."""
+    _check(lib.qk_krylov_profile(k.ptr, int(bool(enable))), "qk_krylov_profile")
+
+
+def qk_krylov_profile_read(k: Krylov) -> dict:
+    """{kind: (milliseconds summed, launches)} since profiling was enabled (waits)."""
+    arr = (KernelTime * len(KERNEL_KINDS))()
+    _check(lib.qk_krylov_profile_read(k.ptr, arr), "qk_krylov_profile_read")
+    return {name: (arr[i].ms_total, arr[i].launches) for i, name in enumerate(KERNEL_KINDS)}
 
 
 def qk_return_prob(b: Basis, psi: torch.Tensor, r0: int = -1, psi0: torch.Tensor | None = None,

@@ -28,6 +28,10 @@ class HamParams(C.Structure):
     _fields_ = [("jxy", f64), ("jz", f64), ("pbc", i32), ("mode", i32)]
 
 
+class KernelTime(C.Structure):
+    _fields_ = [("ms_total", f64), ("launches", i64)]
+
+
 class StepInfo(C.Structure):
     _fields_ = [("m_used", i32), ("status", i32), ("err_est", f64), ("beta0", f64)]
 
@@ -52,6 +56,8 @@ SIGNATURES = {
     "qk_krylov_expm_step": (i32, [vp, vp, f64, vp, P(StepInfo)]),
     "qk_krylov_coefficients": (i32, [vp, i32, P(f64), P(f64), P(i32)]),
     "qk_krylov_destroy": (None, [vp]),
+    "qk_krylov_profile": (i32, [vp, i32]),
+    "qk_krylov_profile_read": (i32, [vp, P(KernelTime)]),
     "qk_return_prob": (i32, [vp, i64, vp, vp, i32, i32, vp, vp]),
 }
 

@@ -1,6 +1,8 @@
 """Builds libqkrylov.so in-tree for gfx950 with hipcc.
 
-Usage: python -m paper_1704_02770_amd.build   (or call build()).
+Usage: python paper_1704_02770_amd/build.py   (or call build()).
+Run it by path, not as a module of the package: importing the package loads
+the library this script produces.
 """
 from __future__ import annotations
 

@@ -35,10 +35,11 @@ static qk_status check_device(int dev) {
 
 static size_t elem_bytes(int dtype) { return dtype == QK_C128 ? 16 : 8; }
 
-static bool ranges_overlap(const void* a, const void* b, size_t n) {
+// [a, a + na) and [b, b + nb) intersect
+static bool ranges_overlap(const void* a, size_t na, const void* b, size_t nb) {
   const char* x = (const char*)a;
   const char* y = (const char*)b;
-  return x < y + n && y < x + n;
+  return x < y + nb && y < x + na;
 }
 
 int krylov_grid(uint64_t D, int B);
@@ -246,7 +247,7 @@ QK_API qk_status qk_ham_apply(const qk_ham* H, const void* x, void* y, int32_t d
   if (!H || !x || !y) return inval("NULL pointer");
   if (dtype != QK_C128 && dtype != QK_C64) return inval("unknown dtype");
   const size_t bytes = elem_bytes(dtype) * (size_t)H->basis->D * H->batch;
-  if (ranges_overlap(x, y, bytes)) return inval("x and y overlap");
+  if (ranges_overlap(x, bytes, y, bytes)) return inval("x and y overlap");
   if (((uintptr_t)x | (uintptr_t)y) % elem_bytes(dtype)) return inval("misaligned vector");
   qk_status st = check_device(H->device);
   if (st != QK_OK) return st;
@@ -312,7 +313,7 @@ QK_API qk_status qk_krylov_expm_step(qk_krylov* k, void* psi, double dt, void* s
   qk_status st = check_device(k->device);
   if (st != QK_OK) return st;
   const size_t vec = elem_bytes(k->dtype) * (size_t)k->D * k->batch;
-  if (ranges_overlap(psi, k->d_U, vec * (size_t)k->m)) return inval("psi overlaps the Krylov workspace");
+  if (ranges_overlap(psi, vec, k->d_U, vec * (size_t)k->m)) return inval("psi overlaps the Krylov workspace");
   hipStream_t s = (hipStream_t)stream;
   st = launch_krylov_step(k, psi, dt, s);
   if (st != QK_OK || !info) return st;
@@ -359,9 +360,46 @@ QK_API qk_status qk_krylov_coefficients(const qk_krylov* k, int32_t item, double
   return QK_OK;
 }
 
+QK_API qk_status qk_krylov_profile(qk_krylov* k, int32_t enable) {
+  g_err.clear();
+  if (!k) return inval("NULL workspace");
+  if (enable != 0 && enable != 1) return inval("enable must be 0 or 1");
+  qk_status st = check_device(k->device);
+  if (st != QK_OK) return st;
+  if (enable) {
+    st = profile_collect(k);
+    if (st != QK_OK) return st;
+    for (int i = 0; i < QK_NUM_KERNELS; ++i) {
+      k->ms_total[i] = 0.0;
+      k->launches[i] = 0;
+    }
+  }
+  k->profiling = enable != 0;
+  return QK_OK;
+}
+
+QK_API qk_status qk_krylov_profile_read(qk_krylov* k, qk_kernel_time* out) {
+  g_err.clear();
+  if (!k || !out) return inval("NULL pointer");
+  qk_status st = check_device(k->device);
+  if (st != QK_OK) return st;
+  st = profile_collect(k);
+  if (st != QK_OK) return st;
+  for (int i = 0; i < QK_NUM_KERNELS; ++i) {
+    out[i].ms_total = k->ms_total[i];
+    out[i].launches = k->launches[i];
+  }
+  return QK_OK;
+}
+
 QK_API void qk_krylov_destroy(qk_krylov* k) {
   if (!k) return;
   hipDeviceSynchronize();
+  for (auto& p : k->pending) {
+    if (p.start) hipEventDestroy(p.start);
+    if (p.end) hipEventDestroy(p.end);
+  }
+  for (auto e : k->spare) hipEventDestroy(e);
   if (k->d_U) hipFree(k->d_U);
   if (k->d_partA) hipFree(k->d_partA);
   if (k->d_partB) hipFree(k->d_partB);

@@ -6,6 +6,7 @@
 
 #include <cstdint>
 #include <string>
+#include <vector>
 
 #include "qk.h"
 
@@ -67,6 +68,13 @@ struct qk_krylov {
   double* d_partB = nullptr;      // [grid][1][batch] partial sums of the update pass
   double* d_coef = nullptr;       // coefficient block, see qk::KState
   int32_t* d_int = nullptr;       // [2][batch]: m_used, status
+  // event timing (qk_krylov_profile)
+  bool profiling = false;
+  struct Pending { int kind; hipEvent_t start, end; };
+  std::vector<Pending> pending;
+  std::vector<hipEvent_t> spare;
+  double ms_total[QK_NUM_KERNELS] = {0, 0, 0, 0};
+  int64_t launches[QK_NUM_KERNELS] = {0, 0, 0, 0};
 };
 
 namespace qk {
@@ -102,6 +110,8 @@ qk_status launch_csr_build(qk_ham* H, hipStream_t s);
 qk_status launch_csr_diag(qk_ham* H, hipStream_t s);
 qk_status launch_ham_apply(const qk_ham* H, const void* x, void* y, int dtype, hipStream_t s);
 qk_status launch_krylov_step(qk_krylov* k, void* psi, double dt, hipStream_t s);
+qk_status profile_mark(qk_krylov* k, int kind, bool begin, hipStream_t s);
+qk_status profile_collect(qk_krylov* k);
 qk_status launch_return_prob(const qk_basis* b, int64_t r0, const void* psi0, const void* psi, int dtype,
                              int B, double* P, hipStream_t s);
 

@@ -834,11 +834,19 @@ static qk_status krylov_step_t(qk_krylov* k, void* psi_v, double dt, hipStream_t
   const bool csr = H->p.mode == QK_CSR;
   // breakdown threshold relative to the largest coefficient so far
   const double rtol = std::is_same<T, double>::value ? 1e-12 : 1e-5;
+#define QK_MARK(kind, begin)                                   \
+  do {                                                         \
+    if (k->profiling) {                                        \
+      qk_status ps_ = profile_mark(k, kind, begin, s);         \
+      if (ps_ != QK_OK) return ps_;                            \
+    }                                                          \
+  } while (0)
   for (int j = 0; j < m; ++j) {
     LanczosArgs la{j, m, rtol};
     const V* uj = j == 0 ? psi : U + (size_t)(j - 1) * stride;
     const V* ujm1 = j == 0 ? nullptr : (j == 1 ? psi : U + (size_t)(j - 2) * stride);
     V* w = U + (size_t)j * stride;
+    QK_MARK(QK_KERNEL_LANCZOS_H, true);
     if (csr)
       hipLaunchKernelGGL((k_lanczos_A<T, true>), dim3(G), dim3(threads), 0, s, uj, ujm1, w, a, hv,
                          H->basis->d_binom, H->d_fields, st, la, k->d_partB, G, k->d_partA);
@@ -846,14 +854,56 @@ static qk_status krylov_step_t(qk_krylov* k, void* psi_v, double dt, hipStream_t
       hipLaunchKernelGGL((k_lanczos_A<T, false>), dim3(G), dim3(threads), 0, s, uj, ujm1, w, a, hv,
                          H->basis->d_binom, H->d_fields, st, la, k->d_partB, G, k->d_partA);
     QK_HIP(hipGetLastError());
+    QK_MARK(QK_KERNEL_LANCZOS_H, false);
+    QK_MARK(QK_KERNEL_LANCZOS_UPDATE, true);
     hipLaunchKernelGGL((k_lanczos_B<T>), dim3(G), dim3(threads), 0, s, uj, w, D, B, st, la, k->d_partA, G,
                        k->d_partB, j + 1 < m ? 1 : 0);
     QK_HIP(hipGetLastError());
+    QK_MARK(QK_KERNEL_LANCZOS_UPDATE, false);
   }
+  QK_MARK(QK_KERNEL_SMALL_EXPM, true);
   hipLaunchKernelGGL(k_small_expm, dim3(B), dim3(64), 0, s, st, m, B, dt, k->d_partB, G);
   QK_HIP(hipGetLastError());
+  QK_MARK(QK_KERNEL_SMALL_EXPM, false);
+  QK_MARK(QK_KERNEL_COMBINE, true);
   hipLaunchKernelGGL((k_combine<T>), dim3(G), dim3(threads), 0, s, psi, U, D, B, m, st);
   QK_HIP(hipGetLastError());
+  QK_MARK(QK_KERNEL_COMBINE, false);
+#undef QK_MARK
+  return QK_OK;
+}
+
+// Event pair around one launch: `begin` records the start event, the
+// matching call after the launch records the end event.
+qk_status profile_mark(qk_krylov* k, int kind, bool begin, hipStream_t s) {
+  hipEvent_t ev;
+  if (!k->spare.empty()) {
+    ev = k->spare.back();
+    k->spare.pop_back();
+  } else {
+    QK_HIP(hipEventCreate(&ev));
+  }
+  if (begin) {
+    k->pending.push_back({kind, ev, nullptr});
+  } else {
+    k->pending.back().end = ev;
+  }
+  QK_HIP(hipEventRecord(ev, s));
+  return QK_OK;
+}
+
+qk_status profile_collect(qk_krylov* k) {
+  for (auto& p : k->pending) {
+    if (!p.end) continue;
+    QK_HIP(hipEventSynchronize(p.end));
+    float ms = 0.f;
+    QK_HIP(hipEventElapsedTime(&ms, p.start, p.end));
+    k->ms_total[p.kind] += ms;
+    k->launches[p.kind] += 1;
+    k->spare.push_back(p.start);
+    k->spare.push_back(p.end);
+  }
+  k->pending.clear();
   return QK_OK;
 }
 
