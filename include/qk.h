@@ -61,7 +61,7 @@ typedef enum {
 } qk_status;
 
 typedef enum { QK_C128 = 0, QK_C64 = 1 } qk_dtype;
-typedef enum { QK_MATFREE = 0, QK_CSR = 1 } qk_ham_mode;
+typedef enum { QK_MATFREE = 0, QK_CSR = 1, QK_MATFREE_ROWS = 2 } qk_ham_mode;
 
 /* Version of this header the library was built from (QK_ABI_VERSION). */
 int qk_abi_version(void);
@@ -116,7 +116,7 @@ typedef struct {
   double jxy;      /* hopping: off-diagonal entry jxy/2 (Eq. (1) t = jxy/2) */
   double jz;       /* zz coupling (Eq. (1) V = jz) */
   int32_t pbc;     /* 0 open chain, 1 periodic chain */
-  int32_t mode;    /* QK_MATFREE (rows generated on the fly) or QK_CSR */
+  int32_t mode;    /* QK_MATFREE, QK_CSR or QK_MATFREE_ROWS (see qk_ham_create) */
 } qk_ham_params;
 
 typedef struct qk_ham qk_ham;
@@ -125,9 +125,13 @@ typedef struct qk_ham qk_ham;
  * Hamiltonian of Eq. (1) on basis `b` (Sec. 3, "Hamiltonian matrix
  * construction") for `batch` field sets h_host[batch][L] (host doubles,
  * copied).  QK_MATFREE generates every row on the fly in the apply kernels;
- * QK_CSR additionally stores the column indices of the off-diagonal entries
- * after an exact counting pass (the exact preallocation of Sec. 3); allowed
- * for D <= 2^24.  The basis must outlive the Hamiltonian.
+ * for L >= 18 and a single field set it processes blocks of states sharing
+ * their high bits (low-bit tables and a block list are built here), otherwise
+ * one row per thread from the stored basis.  QK_MATFREE_ROWS always uses the
+ * one-row-per-thread form (an independent second formulation).  QK_CSR
+ * stores the column indices of the off-diagonal entries after an exact
+ * counting pass (the exact preallocation of Sec. 3); allowed for D <= 2^24.
+ * The basis must outlive the Hamiltonian.
  * Errors: QK_EINVAL (NULL, batch outside [1, QK_MAX_BATCH], non-finite
  * parameters, CSR too large), QK_ENOMEM, QK_EHIP.
  */

@@ -18,7 +18,7 @@ from ._native import HamParams, KernelTime, StepInfo, lib
 
 QK_OK, QK_EINVAL, QK_ENOMEM, QK_EHIP, QK_EUNSUPPORTED, QK_ENUMERIC = range(6)
 QK_C128, QK_C64 = 0, 1
-QK_MATFREE, QK_CSR = 0, 1
+QK_MATFREE, QK_CSR, QK_MATFREE_ROWS = 0, 1, 2
 
 _DTYPE = {torch.complex128: QK_C128, torch.complex64: QK_C64}
 TORCH_DTYPE = {QK_C128: torch.complex128, QK_C64: torch.complex64}

@@ -177,7 +177,7 @@ QK_API qk_status qk_ham_create(const qk_basis* b, const qk_ham_params* p, const 
   if (batch < 1 || batch > QK_MAX_BATCH) return inval("batch must be in [1, 64]");
   if (!std::isfinite(p->jxy) || !std::isfinite(p->jz)) return inval("non-finite coupling");
   if (p->pbc != 0 && p->pbc != 1) return inval("pbc must be 0 or 1");
-  if (p->mode != QK_MATFREE && p->mode != QK_CSR) return inval("unknown mode");
+  if (p->mode != QK_MATFREE && p->mode != QK_CSR && p->mode != QK_MATFREE_ROWS) return inval("unknown mode");
   if (p->mode == QK_CSR && b->D > (1 << 24)) return inval("CSR form limited to D <= 2^24");
   qk_status st = check_fields(h_host, b->L, batch);
   if (st != QK_OK) return st;
@@ -189,6 +189,7 @@ QK_API qk_status qk_ham_create(const qk_basis* b, const qk_ham_params* p, const 
   H->p = *p;
   H->batch = batch;
   H->device = b->device;
+  H->h_host.assign(h_host, h_host + (size_t)b->L * batch);
   hipStream_t s = (hipStream_t)stream;
   const size_t fbytes = sizeof(double) * (size_t)b->L * batch;
   hipError_t e = hipMalloc((void**)&H->d_fields, fbytes);
@@ -213,6 +214,14 @@ QK_API qk_status qk_ham_create(const qk_basis* b, const qk_ham_params* p, const 
       return st;
     }
   }
+  H->llo = blocked_llo(b->L, b->N, batch, p->mode);
+  if (H->llo > 0) {
+    st = launch_blocked_build(H, s);
+    if (st != QK_OK) {
+      qk_ham_destroy(H);
+      return st;
+    }
+  }
   *out = H;
   return QK_OK;
 }
@@ -229,6 +238,11 @@ QK_API qk_status qk_ham_set_fields(qk_ham* H, const double* h_host, int32_t batc
   const size_t fbytes = sizeof(double) * (size_t)H->basis->L * batch;
   QK_HIP(hipMemcpyAsync(H->d_fields, h_host, fbytes, hipMemcpyHostToDevice, s));
   QK_HIP(hipStreamSynchronize(s));
+  H->h_host.assign(h_host, h_host + (size_t)H->basis->L * batch);
+  if (H->llo > 0) {
+    st = launch_blocked_fields(H, s);
+    if (st != QK_OK) return st;
+  }
   if (H->p.mode == QK_CSR) return launch_csr_diag(H, s);
   return QK_OK;
 }
@@ -261,6 +275,9 @@ QK_API void qk_ham_destroy(qk_ham* H) {
   if (H->d_rowptr) hipFree(H->d_rowptr);
   if (H->d_cols) hipFree(H->d_cols);
   if (H->d_diag) hipFree(H->d_diag);
+  if (H->d_lo_state) hipFree(H->d_lo_state);
+  if (H->d_lo_rank) hipFree(H->d_lo_rank);
+  if (H->d_blk) hipFree(H->d_blk);
   delete H;
 }
 
@@ -290,8 +307,8 @@ QK_API qk_status qk_krylov_create(const qk_ham* H, int32_t m, int32_t dtype, int
   k->grid = krylov_grid((uint64_t)k->D, k->batch);
   const size_t vec = elem_bytes(dtype) * (size_t)k->D * k->batch;
   hipError_t e = hipMalloc(&k->d_U, vec * (size_t)m);
-  if (e == hipSuccess) e = hipMalloc((void**)&k->d_partA, sizeof(double) * (size_t)k->grid * 2 * k->batch);
-  if (e == hipSuccess) e = hipMalloc((void**)&k->d_partB, sizeof(double) * (size_t)k->grid * k->batch);
+  if (e == hipSuccess) e = hipMalloc((void**)&k->d_partA, sizeof(double) * (size_t)kMaxPartialBlocks * 2 * k->batch);
+  if (e == hipSuccess) e = hipMalloc((void**)&k->d_partB, sizeof(double) * (size_t)kMaxPartialBlocks * k->batch);
   if (e == hipSuccess) e = hipMalloc((void**)&k->d_coef, sizeof(double) * kstate_doubles(m, k->batch));
   if (e == hipSuccess) e = hipMalloc((void**)&k->d_int, sizeof(int32_t) * 2 * k->batch);
   if (e == hipSuccess) e = hipMemset(k->d_coef, 0, sizeof(double) * kstate_doubles(m, k->batch));

@@ -1,0 +1,528 @@
+// Blocked matrix-free H x for large sectors (Sec. 3 "Hamiltonian matrix
+// construction", Eq. (1)), used by qk_ham_apply and the H-pass of every
+// Lanczos iteration.
+//
+// A state s splits into its high bits a (sites llo+1..L) and low bits b (sites
+// 1..llo).  The sorted basis lists all states with the same a contiguously:
+// block a holds rows off(a) .. off(a)+len(a)-1, with len(a) = C(llo, N-|a|),
+// and the row of s inside its block is the rank of b among the low states of
+// the same popcount.  Therefore
+//   * a hop on a bond inside the low bits stays in the block and moves the
+//     in-block rank by C(p, #set bits of b below p);
+//   * a hop on a bond inside the high bits maps block a onto block a' with
+//     the same in-block rank, i.e. a fixed row shift for the whole block;
+//   * the bond joining the two halves and the ring bond leave the block and
+//     are ranked individually.
+// One work-group processes one block at a time: it stages x of the block in
+// LDS (the low-bond neighbours are read from there), gathers the high-bond
+// neighbours as contiguous runs of the other blocks, and writes the block's
+// rows.  Work-groups are persistent; the top three bits of a select the XCD,
+// so the hops on the top high bonds connect blocks that different XCDs
+// process at the same time, and within an XCD the work-groups take blocks in
+// ascending order together.
+#include <hipcub/hipcub.hpp>
+
+#include <cstdlib>
+#include <type_traits>
+
+#include "qk_device.h"
+
+namespace qk {
+
+constexpr int kMaxHi = 24;   // row shifts per block entry (high bonds <= 21, zero-padded to a multiple of 4)
+
+// One block of the sorted basis.  Everything the rows of the block share is
+// precomputed here and read with scalar loads.
+struct BlkEntry {
+  uint32_t a;               // high bits
+  uint32_t off;             // first row
+  uint32_t offw;            // first row of the ring-partner block (high bits with the top bit flipped)
+  uint32_t nact;            // number of active high bonds (their two bits differ)
+  double dconst;            // block part of the diagonal (high fields, high zz bonds, constants)
+  int32_t delta[kMaxHi];    // row shift of each active high bond, then zeros
+  uint32_t pad[2];
+};
+static_assert(sizeof(BlkEntry) == 128, "block entry is two scalar cache lines");
+
+struct BlkArgs {
+  int L, N, pbc, llo, lhi, maxlen;
+  double half_jxy, jz, zz0, hhalf;         // zz0 = jz/4 * (number of bonds), hhalf = sum_i h_i / 2
+  const BlkEntry* blk;
+  const uint16_t* lo_state;                // [2^llo] low states grouped by popcount, ascending
+  const uint16_t* lo_rank;                 // [2^llo] rank of a low state inside its popcount group
+  const uint32_t* binom;                   // [33*33]
+  const double* fields;                    // [L]
+  uint32_t lo_base[18];                    // first index of each popcount group in lo_state
+  int xcd_first[kNumXcd + 1];              // block ranges per XCD
+};
+
+constexpr int kBlkThreads = 256;
+
+// ------------------------------------------------------------ table build
+__global__ void k_lo_tables(int llo, const uint32_t* __restrict__ gtab, BlkArgs ba, uint16_t* __restrict__ lo_state,
+                            uint16_t* __restrict__ lo_rank) {
+  const uint32_t b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= (1u << llo)) return;
+  const int k = __popc(b);
+  const uint32_t j = cns_rank(b, gtab);
+  lo_state[ba.lo_base[k] + j] = (uint16_t)b;
+  lo_rank[b] = (uint16_t)j;
+}
+
+__global__ void k_block_flags(int lhi, int llo, int N, uint32_t* __restrict__ flag) {
+  const uint32_t a = blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= (1u << lhi)) return;
+  const int k = N - __popc(a);
+  flag[a] = (k >= 0 && k <= llo) ? 1u : 0u;
+}
+
+// First row of block a: the rank of (a, lowest low state of popcount N-|a|).
+__device__ __forceinline__ uint32_t block_offset(uint32_t a, int llo, int N, const uint32_t* tab) {
+  const int k = N - __popc(a);
+  return cns_rank((a << llo) | ((1u << k) - 1u), tab);
+}
+
+__global__ void k_block_fill(int lhi, int llo, int N, const uint32_t* __restrict__ flag,
+                             const uint32_t* __restrict__ idx, const uint32_t* __restrict__ gtab,
+                             BlkEntry* __restrict__ blk) {
+  const uint32_t a = blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= (1u << lhi) || !flag[a]) return;
+  BlkEntry e;
+  e.a = a;
+  e.off = block_offset(a, llo, N, gtab);
+  const uint32_t a2 = a ^ (1u << (lhi - 1));
+  const int k2 = N - __popc(a2);
+  e.offw = (k2 >= 0 && k2 <= llo) ? block_offset(a2, llo, N, gtab) : 0u;
+  // A hop on the high bond (llo+t, llo+t+1) moves every row of the block by
+  // +-C(llo+t, number of set bits of the state below llo+t).
+  const int k_lo = N - __popc(a);
+  uint32_t n = 0;
+  for (int t = 0; t + 1 < lhi; ++t) {
+    const uint32_t b0 = (a >> t) & 1u, b1 = (a >> (t + 1)) & 1u;
+    if (b0 != b1) {
+      const int pcb = k_lo + __popc(a & ((1u << t) - 1u));
+      const int c = (int)gtab[(llo + t) * kBinomStride + pcb];
+      e.delta[n++] = b0 ? c : -c;
+    }
+  }
+  e.nact = n;
+  for (uint32_t i = n; i < (uint32_t)kMaxHi; ++i) e.delta[i] = 0;
+  e.dconst = 0.0;
+  e.pad[0] = e.pad[1] = 0u;
+  blk[idx[a]] = e;
+}
+
+// Block part of the diagonal: jz/4 * (number of bonds) - sum_i h_i / 2 plus
+// the fields on the set high bits minus jz/2 per anti-aligned high bond.
+__global__ void k_block_consts(int nblk, int llo, int lhi, double zz0, double hhalf, double jz,
+                               const double* __restrict__ fields, BlkEntry* __restrict__ blk) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nblk) return;
+  const uint32_t a = blk[i].a;
+  double f = 0.0;
+  for (int t = 0; t < lhi; ++t)
+    if ((a >> t) & 1u) f += fields[llo + t];
+  blk[i].dconst = zz0 - hhalf + f - 0.5 * jz * (double)blk[i].nact;
+}
+
+// --------------------------------------------------------- blocked rows
+// Largest block, C(LLO, LLO/2) rows.
+template <int LLO>
+constexpr int blk_max_len() {
+  return LLO == 9 ? 126 : LLO == 10 ? 252 : 462;
+}
+
+// Bytes of the two x buffers at the start of dynamic LDS; at least the
+// 2 x 256 doubles of the reductions that alias them.
+template <typename T, int LLO>
+constexpr size_t blk_xbytes() {
+  constexpr size_t b = sizeof(typename Cx<T>::V) * 2 * (size_t)blk_max_len<LLO>();
+  return b > 2 * kBlkThreads * sizeof(double) ? b : 2 * kBlkThreads * sizeof(double);
+}
+
+// Element idx of a vector through a 32-bit byte offset from a uniform base
+// (the launcher guarantees D * sizeof(V) < 2^32).
+template <typename V>
+__device__ __forceinline__ V ld32(const V* __restrict__ base, uint32_t idx) {
+  return *reinterpret_cast<const V*>(reinterpret_cast<const char*>(base) + idx * (uint32_t)sizeof(V));
+}
+template <typename V>
+__device__ __forceinline__ void st32(V* __restrict__ base, uint32_t idx, V v) {
+  *reinterpret_cast<V*>(reinterpret_cast<char*>(base) + idx * (uint32_t)sizeof(V)) = v;
+}
+
+// LLO low bits (compile-time, so the low-bond loop unrolls).  LANCZOS:
+// w = sa * H u_j - sb * u_{j-1} with the dot-product partials of the H-pass;
+// otherwise y = H x.  The x values of the next block are loaded into
+// registers while the current block's gathers are in flight and stored into
+// the second LDS buffer at the end of the step (one barrier per block).
+template <typename T, int LLO, bool LANCZOS>
+__global__ void __launch_bounds__(kBlkThreads)
+k_blk(BlkArgs ba, const typename Cx<T>::V* __restrict__ x, typename Cx<T>::V* __restrict__ y,
+      const typename Cx<T>::V* __restrict__ ujm1, KState st, LanczosArgs la, const double* __restrict__ partB, int Gp,
+      double* __restrict__ partA) {
+  using V = typename Cx<T>::V;
+  constexpr int kMaxLen = blk_max_len<LLO>();
+  static_assert(kMaxLen <= 2 * kBlkThreads, "prefetch covers two elements per thread");
+  extern __shared__ unsigned char smem[];
+  V* xsb = reinterpret_cast<V*>(smem);                                            // [2][kMaxLen]
+  uint16_t* lo_state = reinterpret_cast<uint16_t*>(smem + blk_xbytes<T, LLO>());
+  uint16_t* lo_rank = lo_state + (1 << LLO);
+  __shared__ uint32_t sbin[kBinomStride * kBinomStride];
+  __shared__ double flo0[256], flo1[256];
+  __shared__ double fld[QK_MAX_L];
+  __shared__ double tot[1], sa[1], sb[1];
+  __shared__ int act[1];
+  __shared__ int hds[2][kMaxHi];   // row shifts of the current and the next block
+  double* red = reinterpret_cast<double*>(smem);   // aliases the x buffers outside the block loop
+
+  const int tid = threadIdx.x;
+  for (int i = tid; i < kBinomStride * kBinomStride; i += kBlkThreads) sbin[i] = ba.binom[i];
+  for (int i = tid; i < (1 << LLO); i += kBlkThreads) {
+    lo_state[i] = ba.lo_state[i];
+    lo_rank[i] = ba.lo_rank[i];
+  }
+  if (tid < ba.L) fld[tid] = ba.fields[tid];
+  __syncthreads();
+  {
+    // field sums over the low bits, eight bits per table (kBlkThreads == 256 entries)
+    const int c = tid;
+    double f0 = 0.0, f1 = 0.0;
+    for (int i = 0; i < 8; ++i) {
+      if ((c >> i) & 1) {
+        if (i < LLO) f0 += fld[i];
+        if (8 + i < LLO) f1 += fld[8 + i];
+      }
+    }
+    flo0[c] = f0;
+    flo1[c] = f1;
+  }
+  if (LANCZOS) {
+    lanczos_h_scalars(1, st, la, partB, Gp, red, tot, sa, sb, act);
+  } else {
+    if (tid == 0) {
+      sa[0] = 1.0;
+      sb[0] = 0.0;
+      act[0] = 1;
+    }
+    __syncthreads();
+  }
+  const T g = (T)ba.half_jxy;
+  const double hjz = 0.5 * ba.jz;
+  const T ca = (T)sa[0], cb = (T)sb[0];
+  const bool prev = LANCZOS && la.j > 0;
+  double s1 = 0.0, s2 = 0.0;
+  const int lhi = ba.lhi;
+  const int xcd = blockIdx.x % kNumXcd, kx = blockIdx.x / kNumXcd, per = gridDim.x / kNumXcd;
+  const int first = ba.xcd_first[xcd], last = ba.xcd_first[xcd + 1];
+  int bi = first + kx;
+  const bool run = act[0] != 0;
+  __syncthreads();   // `red` (aliasing the x buffers) is no longer read
+
+  if (run && bi < last) {
+    const BlkEntry* ep = ba.blk + bi;
+    const uint32_t len = sbin[LLO * kBinomStride + (ba.N - __popc(ep->a))];
+    const uint32_t off = ep->off;
+    for (uint32_t i = tid; i < len; i += kBlkThreads) xsb[i] = ld32(x, off + i);
+    if (tid < kMaxHi) hds[0][tid] = ep->delta[tid];
+  }
+  __syncthreads();
+  int cur = 0;
+  for (; run && bi < last; bi += per) {
+    const BlkEntry* ep = ba.blk + bi;
+    const uint32_t a = ep->a, off = ep->off, offw = ep->offw;
+    const int nact = (int)ep->nact;
+    const double dconst = ep->dconst;
+    const int k_lo = ba.N - __popc(a);
+    const uint32_t len = sbin[LLO * kBinomStride + k_lo];
+    const uint32_t base = ba.lo_base[k_lo];
+    const V* xs = xsb + cur * kMaxLen;
+    // next block: its x values, loaded now and stored after the rows
+    const int nbi = bi + per;
+    const bool has_next = nbi < last;
+    uint32_t nlen = 0;
+    V p0 = {0, 0}, p1 = {0, 0};
+    int nd = 0;
+    if (has_next) {
+      const BlkEntry* en = ba.blk + nbi;
+      nlen = sbin[LLO * kBinomStride + (ba.N - __popc(en->a))];
+      const uint32_t noff = en->off;
+      if ((uint32_t)tid < nlen) p0 = ld32(x, noff + tid);
+      if ((uint32_t)tid + kBlkThreads < nlen) p1 = ld32(x, noff + tid + kBlkThreads);
+      if (tid < kMaxHi) nd = en->delta[tid];
+    }
+    const int* hd = hds[cur];
+    const uint32_t top = (a >> (lhi - 1)) & 1u;
+    for (uint32_t j = tid; j < len; j += kBlkThreads) {
+      const uint32_t b = lo_state[base + j];
+      const uint32_t r = off + j;
+      // global gathers first, so that their latencies overlap: the previous
+      // Lanczos vector, the bond joining the halves and the ring bond
+      // (inactive ones read x[r] and are discarded)
+      V um = {0, 0};
+      if (prev) um = ld32(ujm1, r);
+      const uint32_t bl = (b >> (LLO - 1)) & 1u;
+      const bool cx = (bl ^ (a & 1u)) != 0u;
+      const uint32_t pcl = (uint32_t)__popc(b & ((1u << (LLO - 1)) - 1u));
+      const uint32_t cc = sbin[(LLO - 1) * kBinomStride + pcl];
+      const V vc = ld32(x, cx ? (bl ? r + cc : r - cc) : r);
+      const bool wx = ba.pbc && ((b & 1u) != top);
+      const V vw = ld32(x, wx ? offw + lo_rank[b ^ 1u] : r);
+      // high bonds: uniform row shifts, contiguous runs of the partner blocks,
+      // four unconditional loads at a time (zero shifts pad the last group and
+      // are weighted out with uniform 0/1 factors, so no branch separates the
+      // loads).  The first group is issued before the in-block LDS work and
+      // consumed after it.
+      const V q0 = ld32(x, r + (uint32_t)hd[0]);
+      const V q1 = ld32(x, r + (uint32_t)hd[1]);
+      const V q2 = ld32(x, r + (uint32_t)hd[2]);
+      const V q3 = ld32(x, r + (uint32_t)hd[3]);
+      // in-block work from LDS
+      const V xr = xs[j];
+      const int anti = __popc((b ^ (b >> 1)) & ((1u << (LLO - 1)) - 1u)) + (cx ? 1 : 0) + (wx ? 1 : 0);
+      const double d = dconst + flo0[b & 255u] + flo1[b >> 8] - hjz * anti;
+      V hs = {0, 0};
+      int pc = 0;
+#pragma unroll
+      for (int p = 0; p < LLO - 1; ++p) {
+        const uint32_t b0 = (b >> p) & 1u, b1 = (b >> (p + 1)) & 1u;
+        if (b0 != b1) {
+          const uint32_t c = sbin[p * kBinomStride + pc];
+          const V v = xs[b0 ? j + c : j - c];
+          hs.x += v.x;
+          hs.y += v.y;
+        }
+        pc += (int)b0;
+      }
+      {
+        const T w0 = (0 < nact) ? (T)1 : (T)0, w1 = (1 < nact) ? (T)1 : (T)0;
+        const T w2 = (2 < nact) ? (T)1 : (T)0, w3 = (3 < nact) ? (T)1 : (T)0;
+        hs.x += w0 * q0.x + w1 * q1.x + w2 * q2.x + w3 * q3.x;
+        hs.y += w0 * q0.y + w1 * q1.y + w2 * q2.y + w3 * q3.y;
+      }
+      for (int g0 = 4; g0 < nact; g0 += 4) {
+        const V v0 = ld32(x, r + (uint32_t)hd[g0]);
+        const V v1 = ld32(x, r + (uint32_t)hd[g0 + 1]);
+        const V v2 = ld32(x, r + (uint32_t)hd[g0 + 2]);
+        const V v3 = ld32(x, r + (uint32_t)hd[g0 + 3]);
+        const T w1 = (g0 + 1 < nact) ? (T)1 : (T)0;
+        const T w2 = (g0 + 2 < nact) ? (T)1 : (T)0;
+        const T w3 = (g0 + 3 < nact) ? (T)1 : (T)0;
+        hs.x += v0.x + w1 * v1.x + w2 * v2.x + w3 * v3.x;
+        hs.y += v0.y + w1 * v1.y + w2 * v2.y + w3 * v3.y;
+      }
+      hs.x += (cx ? vc.x : (T)0) + (wx ? vw.x : (T)0);
+      hs.y += (cx ? vc.y : (T)0) + (wx ? vw.y : (T)0);
+      V h;
+      h.x = (T)d * xr.x + g * hs.x;
+      h.y = (T)d * xr.y + g * hs.y;
+      if (LANCZOS) {
+        V wv;
+        wv.x = ca * h.x - cb * um.x;
+        wv.y = ca * h.y - cb * um.y;
+        st32(y, r, wv);
+        s1 += (double)xr.x * (double)wv.x + (double)xr.y * (double)wv.y;
+        s2 += (double)xr.x * (double)xr.x + (double)xr.y * (double)xr.y;
+      } else {
+        st32(y, r, h);
+      }
+    }
+    if (has_next) {
+      V* xn = xsb + (cur ^ 1) * kMaxLen;
+      if ((uint32_t)tid < nlen) xn[tid] = p0;
+      if ((uint32_t)tid + kBlkThreads < nlen) xn[tid + kBlkThreads] = p1;
+      if (tid < kMaxHi) hds[cur ^ 1][tid] = nd;
+    }
+    __syncthreads();
+    cur ^= 1;
+  }
+  if (LANCZOS) {
+    double v[2] = {s1, s2};
+    block_partials<2>(v, 1, red, partA + (size_t)blockIdx.x * 2);
+  }
+}
+
+// ================================================================ launchers
+static uint64_t binom_host(int n, int k) {
+  if (k < 0 || k > n) return 0;
+  uint64_t r = 1;
+  for (int i = 1; i <= k; ++i) r = r * (uint64_t)(n - k + i) / (uint64_t)i;
+  return r;
+}
+
+// Launch-shape tunables (defaults; the autotuner and the environment
+// variables QK_BLOCKED_LLO / QK_BLOCKED_WGS_PER_CU override them).
+static int env_int(const char* name, int dflt) {
+  const char* v = getenv(name);
+  if (!v || !*v) return dflt;
+  const int x = atoi(v);
+  return x > 0 ? x : dflt;
+}
+
+int blocked_llo(int L, int N, int B, int mode) {
+  if (mode != QK_MATFREE || B != 1 || L < 18) return 0;
+  (void)N;
+  int llo = env_int("QK_BLOCKED_LLO", 11);
+  if (llo < 9) llo = 9;
+  if (llo > 11) llo = 11;
+  if (llo > L / 2) llo = L / 2;
+  return llo;
+}
+
+static BlkArgs blk_args(const qk_ham* H) {
+  BlkArgs ba{};
+  const qk_basis* b = H->basis;
+  ba.L = b->L;
+  ba.N = b->N;
+  ba.pbc = H->p.pbc;
+  ba.llo = H->llo;
+  ba.lhi = b->L - H->llo;
+  ba.maxlen = (int)binom_host(H->llo, H->llo / 2);
+  ba.half_jxy = 0.5 * H->p.jxy;
+  ba.jz = H->p.jz;
+  ba.zz0 = 0.25 * H->p.jz * (H->p.pbc ? b->L : b->L - 1);
+  double hs = 0.0;
+  for (int i = 0; i < b->L; ++i) hs += H->h_host[i];
+  ba.hhalf = 0.5 * hs;
+  ba.blk = (const BlkEntry*)H->d_blk;
+  ba.lo_state = H->d_lo_state;
+  ba.lo_rank = H->d_lo_rank;
+  ba.binom = b->d_binom;
+  ba.fields = H->d_fields;
+  uint32_t acc = 0;
+  for (int k = 0; k <= H->llo; ++k) {
+    ba.lo_base[k] = acc;
+    acc += (uint32_t)binom_host(H->llo, k);
+  }
+  for (int x = 0; x <= kNumXcd; ++x) ba.xcd_first[x] = H->xcd_first[x];
+  return ba;
+}
+
+qk_status launch_blocked_build(qk_ham* H, hipStream_t s) {
+  const qk_basis* b = H->basis;
+  const int llo = H->llo, lhi = b->L - llo;
+  const uint32_t nlo = 1u << llo, nhi = 1u << lhi;
+  QK_HIP(hipMalloc((void**)&H->d_lo_state, sizeof(uint16_t) * nlo));
+  QK_HIP(hipMalloc((void**)&H->d_lo_rank, sizeof(uint16_t) * nlo));
+  BlkArgs ba = blk_args(H);
+  hipLaunchKernelGGL(k_lo_tables, dim3((nlo + 255) / 256), dim3(256), 0, s, llo, b->d_binom, ba, H->d_lo_state,
+                     H->d_lo_rank);
+  QK_HIP(hipGetLastError());
+  uint32_t *flag = nullptr, *idx = nullptr;
+  void* tmp = nullptr;
+  size_t tmp_bytes = 0;
+  QK_HIP(hipMalloc((void**)&flag, sizeof(uint32_t) * nhi));
+  hipError_t e = hipMalloc((void**)&idx, sizeof(uint32_t) * nhi);
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(k_block_flags, dim3((nhi + 255) / 256), dim3(256), 0, s, lhi, llo, b->N, flag);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipcub::DeviceScan::ExclusiveSum(nullptr, tmp_bytes, flag, idx, (int)nhi, s);
+  if (e == hipSuccess) e = hipMalloc(&tmp, tmp_bytes + 16);
+  if (e == hipSuccess) e = hipcub::DeviceScan::ExclusiveSum(tmp, tmp_bytes, flag, idx, (int)nhi, s);
+  uint32_t last_idx = 0, last_flag = 0;
+  uint32_t xcd_idx[kNumXcd];
+  if (e == hipSuccess) e = hipMemcpyAsync(&last_idx, idx + nhi - 1, 4, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(&last_flag, flag + nhi - 1, 4, hipMemcpyDeviceToHost, s);
+  for (int x = 0; x < kNumXcd && e == hipSuccess; ++x)
+    e = hipMemcpyAsync(&xcd_idx[x], idx + ((size_t)x << (lhi - 3)), 4, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e == hipSuccess) {
+    H->nblk = (int)(last_idx + last_flag);
+    e = hipMalloc((void**)&H->d_blk, sizeof(BlkEntry) * (size_t)(H->nblk > 0 ? H->nblk : 1));
+  }
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(k_block_fill, dim3((nhi + 255) / 256), dim3(256), 0, s, lhi, llo, b->N, flag, idx,
+                       b->d_binom, (BlkEntry*)H->d_blk);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(k_block_consts, dim3((H->nblk + 255) / 256), dim3(256), 0, s, H->nblk, llo, lhi, ba.zz0,
+                       ba.hhalf, ba.jz, H->d_fields, (BlkEntry*)H->d_blk);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  hipFree(tmp);
+  hipFree(flag);
+  hipFree(idx);
+  QK_HIP(e);
+  for (int x = 0; x < kNumXcd; ++x) H->xcd_first[x] = (int)xcd_idx[x];
+  H->xcd_first[kNumXcd] = H->nblk;
+  return QK_OK;
+}
+
+qk_status launch_blocked_fields(qk_ham* H, hipStream_t s) {
+  const BlkArgs ba = blk_args(H);
+  hipLaunchKernelGGL(k_block_consts, dim3((H->nblk + 255) / 256), dim3(256), 0, s, H->nblk, ba.llo, ba.lhi, ba.zz0,
+                     ba.hhalf, ba.jz, H->d_fields, (BlkEntry*)H->d_blk);
+  QK_HIP(hipGetLastError());
+  return QK_OK;
+}
+
+bool blocked_usable(const qk_ham* H, int dtype) {
+  const uint64_t bytes = (uint64_t)H->basis->D * (dtype == QK_C128 ? 16u : 8u);
+  return H->llo > 0 && bytes < (1ull << 32);
+}
+
+template <typename T, int LLO, bool LANCZOS>
+static qk_status launch_blk_t(const qk_ham* H, const void* x, void* y, const void* ujm1, const KState* st,
+                              const LanczosArgs* la, const double* partB, int Gp, double* partA, int* grid_out,
+                              hipStream_t s) {
+  using V = typename Cx<T>::V;
+  const BlkArgs ba = blk_args(H);
+  const size_t dyn = blk_xbytes<T, LLO>() + 2 * sizeof(uint16_t) * ((size_t)1 << LLO);
+  auto kern = k_blk<T, LLO, LANCZOS>;
+  static int occ = 0;
+  if (occ == 0) {
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, kern, kBlkThreads, dyn) != hipSuccess || n < 1) n = 1;
+    occ = n;
+  }
+  int cus = 0, dev = 0;
+  hipDeviceProp_t prop;
+  QK_HIP(hipGetDevice(&dev));
+  QK_HIP(hipGetDeviceProperties(&prop, dev));
+  cus = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+  int wgs = env_int("QK_BLOCKED_WGS_PER_CU", occ);
+  if (wgs > occ) wgs = occ;
+  int G = ((cus * wgs) / kNumXcd) * kNumXcd;
+  if (G < kNumXcd) G = kNumXcd;
+  if (G > kMaxPartialBlocks) G = kMaxPartialBlocks;
+  KState stv{};
+  LanczosArgs lav{};
+  if (st) stv = *st;
+  if (la) lav = *la;
+  hipLaunchKernelGGL(kern, dim3(G), dim3(kBlkThreads), dyn, s, ba, (const V*)x, (V*)y, (const V*)ujm1, stv, lav,
+                     partB, Gp, partA);
+  QK_HIP(hipGetLastError());
+  if (grid_out) *grid_out = G;
+  return QK_OK;
+}
+
+template <typename T, bool LANCZOS>
+static qk_status launch_blk_llo(const qk_ham* H, const void* x, void* y, const void* ujm1, const KState* st,
+                                const LanczosArgs* la, const double* partB, int Gp, double* partA, int* grid_out,
+                                hipStream_t s) {
+  switch (H->llo) {
+    case 9: return launch_blk_t<T, 9, LANCZOS>(H, x, y, ujm1, st, la, partB, Gp, partA, grid_out, s);
+    case 10: return launch_blk_t<T, 10, LANCZOS>(H, x, y, ujm1, st, la, partB, Gp, partA, grid_out, s);
+    case 11: return launch_blk_t<T, 11, LANCZOS>(H, x, y, ujm1, st, la, partB, Gp, partA, grid_out, s);
+    default: set_error("no blocked kernel for this low-bit count"); return QK_EUNSUPPORTED;
+  }
+}
+
+qk_status launch_blocked_apply(const qk_ham* H, const void* x, void* y, int dtype, hipStream_t s) {
+  if (dtype == QK_C128)
+    return launch_blk_llo<double, false>(H, x, y, nullptr, nullptr, nullptr, nullptr, 0, nullptr, nullptr, s);
+  return launch_blk_llo<float, false>(H, x, y, nullptr, nullptr, nullptr, nullptr, 0, nullptr, nullptr, s);
+}
+
+qk_status launch_blocked_lanczos_h(const qk_ham* H, int dtype, const void* uj, const void* ujm1, void* w,
+                                   const KState& st, const LanczosArgs& la, const double* partB, int Gp,
+                                   double* partA, int* grid_out, hipStream_t s) {
+  if (dtype == QK_C128)
+    return launch_blk_llo<double, true>(H, uj, w, ujm1, &st, &la, partB, Gp, partA, grid_out, s);
+  return launch_blk_llo<float, true>(H, uj, w, ujm1, &st, &la, partB, Gp, partA, grid_out, s);
+}
+
+}  // namespace qk

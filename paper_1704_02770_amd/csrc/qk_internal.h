@@ -15,6 +15,7 @@ namespace qk {
 constexpr int kBinomStride = 33;        // binom[n * 33 + k] = C(n, k), n, k <= 32
 constexpr int kNumXcd = 8;              // MI355X: 8 accelerator complex dies, WGs dealt round-robin
 constexpr int kMaxBlock = 256;
+constexpr int kMaxPartialBlocks = 4096; // partial-sum slots per reduction (>= any grid used)
 
 void set_error(const std::string& msg);
 qk_status hip_fail(hipError_t e, const char* what);
@@ -50,11 +51,19 @@ struct qk_ham {
   int32_t batch = 1;
   int device = 0;
   double* d_fields = nullptr;     // [batch][L]
+  std::vector<double> h_host;     // [batch][L] copy of the fields
   // CSR form (mode == QK_CSR): off-diagonal columns, row pointers, diagonal [D][batch]
   uint32_t* d_rowptr = nullptr;   // [D + 1]
   uint32_t* d_cols = nullptr;     // [nnz]
   double* d_diag = nullptr;       // [D][batch]
   int64_t nnz = 0;
+  // blocked matrix-free form (llo > 0): low-bit tables and the block list
+  int llo = 0;
+  uint16_t* d_lo_state = nullptr; // [2^llo]
+  uint16_t* d_lo_rank = nullptr;  // [2^llo]
+  void* d_blk = nullptr;          // [nblk] block entries (high bits, first row, ring-partner first row)
+  int nblk = 0;
+  int xcd_first[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
 };
 
 struct qk_krylov {
@@ -109,6 +118,11 @@ qk_status launch_rank(const qk_basis* b, const uint64_t* d_in, int64_t n, int64_
 qk_status launch_csr_build(qk_ham* H, hipStream_t s);
 qk_status launch_csr_diag(qk_ham* H, hipStream_t s);
 qk_status launch_ham_apply(const qk_ham* H, const void* x, void* y, int dtype, hipStream_t s);
+int blocked_llo(int L, int N, int B, int mode);
+qk_status launch_blocked_build(qk_ham* H, hipStream_t s);
+qk_status launch_blocked_apply(const qk_ham* H, const void* x, void* y, int dtype, hipStream_t s);
+qk_status launch_blocked_fields(qk_ham* H, hipStream_t s);
+bool blocked_usable(const qk_ham* H, int dtype);
 qk_status launch_krylov_step(qk_krylov* k, void* psi, double dt, hipStream_t s);
 qk_status profile_mark(qk_krylov* k, int kind, bool begin, hipStream_t s);
 qk_status profile_collect(qk_krylov* k);

@@ -15,51 +15,9 @@
 #include <cmath>
 #include <type_traits>
 
-#include "qk_internal.h"
+#include "qk_device.h"
 
 namespace qk {
-
-template <typename T> struct Cx;
-template <> struct Cx<double> { using V = double2; };
-template <> struct Cx<float> { using V = float2; };
-
-// ------------------------------------------------------------------ ranking
-// Position of a state in the sorted basis: with set bits at p_1 < ... < p_N,
-// the number of sector states below it is sum_k C(p_k, k) (the counting that
-// the sorted order of Sec. 2 implies; the paper finds it by binary lookup).
-__device__ __forceinline__ uint32_t cns_rank(uint32_t s, const uint32_t* tab) {
-  uint32_t r = 0;
-  int k = 1;
-  while (s) {
-    int p = __builtin_ctz(s);
-    r += tab[p * kBinomStride + k];
-    ++k;
-    s &= s - 1u;
-  }
-  return r;
-}
-
-// The r-th state of the sorted basis (Algorithm 3's first_int()).
-__device__ __forceinline__ uint32_t cns_unrank(uint32_t r, int L, int N, const uint32_t* tab) {
-  uint32_t s = 0;
-  int k = N;
-  for (int p = L - 1; p >= 0 && k > 0; --p) {
-    uint32_t c = tab[p * kBinomStride + k];
-    if (r >= c) {
-      s |= 1u << p;
-      r -= c;
-      --k;
-    }
-  }
-  return s;
-}
-
-// Next larger integer with the same popcount (Algorithm 2).  The paper's
-// exact division of two powers of two is a right shift by ctz(v).
-__device__ __forceinline__ uint32_t next_perm(uint32_t v) {
-  uint32_t t = (v | (v - 1u)) + 1u;
-  return t | ((((t & (0u - t)) >> __builtin_ctz(v)) >> 1) - 1u);
-}
 
 __global__ void k_binom_table(uint32_t* tab) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
@@ -113,131 +71,6 @@ __global__ void k_rank(const uint64_t* __restrict__ in, int64_t n, int64_t* __re
   out[i] = (int64_t)cns_rank((uint32_t)s, tab);
 }
 
-// ------------------------------------------------------------- model rows
-__device__ __forceinline__ int anti_bonds(uint32_t s, const ModelArgs& a) {
-  if (a.pbc) {
-    uint32_t rot = ((s >> 1) | (s << (a.L - 1))) & a.lmask;
-    return __popc((s ^ rot) & a.lmask);
-  }
-  return __popc((s ^ (s >> 1)) & (a.lmask >> 1));
-}
-
-// Diagonal of Eq. (1): jz/4 * (aligned - anti-aligned bonds) + sum_i h_i (bit_i - 1/2).
-__device__ __forceinline__ double diag_value(uint32_t s, const ModelArgs& a, const double* f, double hhalf) {
-  const int nb = a.pbc ? a.L : a.L - 1;
-  double d = 0.25 * a.jz * (double)(nb - 2 * anti_bonds(s, a)) - hhalf;
-  uint32_t t = s;
-  while (t) {
-    d += f[__builtin_ctz(t)];
-    t &= t - 1u;
-  }
-  return d;
-}
-
-// Calls f(column) for every bond whose bits differ.  A particle hopping
-// p -> p+1 raises the rank by C(p, #set bits below p); p+1 -> p lowers it by
-// the same amount.  The ring bond (L-1, 0) renumbers every particle and is
-// ranked in full.
-template <class F>
-__device__ __forceinline__ void for_each_hop(uint32_t s, uint32_t r, const ModelArgs& a, const uint32_t* tab, F&& f) {
-  int pc = 0;
-  for (int p = 0; p < a.L - 1; ++p) {
-    const uint32_t b0 = (s >> p) & 1u;
-    const uint32_t b1 = (s >> (p + 1)) & 1u;
-    if (b0 != b1) {
-      const uint32_t c = tab[p * kBinomStride + pc];
-      f(b0 ? r + c : r - c);
-    }
-    pc += (int)b0;
-  }
-  if (a.pbc) {
-    const uint32_t b0 = s & 1u, b1 = (s >> (a.L - 1)) & 1u;
-    if (b0 != b1) f(cns_rank(s ^ (1u | (1u << (a.L - 1))), tab));
-  }
-}
-
-// Per-block LDS copies of the small tables every row kernel needs.
-struct RowShared {
-  uint32_t tab[kBinomStride * kBinomStride];
-  double fld[QK_MAX_BATCH * QK_MAX_L];
-  double hhalf[QK_MAX_BATCH];
-};
-
-__device__ __forceinline__ void load_row_shared(RowShared& sh, const ModelArgs& a, const uint32_t* gtab,
-                                                const double* gfields) {
-  for (int i = threadIdx.x; i < kBinomStride * kBinomStride; i += blockDim.x) sh.tab[i] = gtab[i];
-  for (int i = threadIdx.x; i < a.B * a.L; i += blockDim.x) sh.fld[i] = gfields[i];
-  __syncthreads();
-  for (int b = threadIdx.x; b < a.B; b += blockDim.x) {
-    double t = 0.0;
-    for (int i = 0; i < a.L; ++i) t += sh.fld[b * a.L + i];
-    sh.hhalf[b] = 0.5 * t;
-  }
-  __syncthreads();
-}
-
-struct HamView {
-  const uint32_t* states;
-  const uint32_t* rowptr;
-  const uint32_t* cols;
-  const double* diag;
-  uint32_t D;
-};
-
-// (H x)[r, b] and x[r, b].
-template <typename T, bool CSR>
-__device__ __forceinline__ typename Cx<T>::V h_row(uint32_t r, int b, const ModelArgs& a, const RowShared& sh,
-                                                   const HamView& hv, const typename Cx<T>::V* __restrict__ x,
-                                                   typename Cx<T>::V& xr) {
-  using V = typename Cx<T>::V;
-  const int B = a.B;
-  xr = x[(size_t)r * B + b];
-  const T g = (T)a.half_jxy;
-  V acc;
-  if (CSR) {
-    const T d = (T)hv.diag[(size_t)r * B + b];
-    acc.x = d * xr.x;
-    acc.y = d * xr.y;
-    V hs = {0, 0};
-    for (uint32_t k = hv.rowptr[r]; k < hv.rowptr[r + 1]; ++k) {
-      const V xc = x[(size_t)hv.cols[k] * B + b];
-      hs.x += xc.x;
-      hs.y += xc.y;
-    }
-    acc.x += g * hs.x;
-    acc.y += g * hs.y;
-  } else {
-    const uint32_t s = hv.states[r];
-    const T d = (T)diag_value(s, a, sh.fld + b * a.L, sh.hhalf[b]);
-    acc.x = d * xr.x;
-    acc.y = d * xr.y;
-    V hs = {0, 0};
-    for_each_hop(s, r, a, sh.tab, [&](uint32_t c) {
-      const V xc = x[(size_t)c * B + b];
-      hs.x += xc.x;
-      hs.y += xc.y;
-    });
-    acc.x += g * hs.x;
-    acc.y += g * hs.y;
-  }
-  return acc;
-}
-
-// XCD-aware tile walk: work-groups are dealt round-robin to the 8 XCDs, so
-// block i runs on XCD i % 8.  Each XCD gets one contiguous eighth of the row
-// tiles, and its blocks stride through that eighth together, which keeps the
-// rows being read on one XCD close together in that XCD's L2.
-struct TileWalk {
-  uint32_t t, t_end, step;
-  __device__ TileWalk(uint32_t ntiles) {
-    const uint32_t x = blockIdx.x % kNumXcd, k = blockIdx.x / kNumXcd, per = gridDim.x / kNumXcd;
-    const uint32_t t0 = (uint32_t)(((uint64_t)ntiles * x) / kNumXcd);
-    t_end = (uint32_t)(((uint64_t)ntiles * (x + 1)) / kNumXcd);
-    t = t0 + k;
-    step = per;
-  }
-};
-
 // ----------------------------------------------------------- H x kernels
 template <typename T, bool CSR>
 __global__ void __launch_bounds__(kMaxBlock)
@@ -256,63 +89,6 @@ k_apply(const typename Cx<T>::V* __restrict__ x, typename Cx<T>::V* __restrict__
   }
 }
 
-// ------------------------------------------------------ block reductions
-// Sums each of Q values over the threads of the block that share a batch
-// column (threadIdx % B; blockDim = B * 2^k) by a fixed tree in LDS and
-// writes the Q * B column sums to out_block.
-template <int Q>
-__device__ __forceinline__ void block_partials(const double (&v)[Q], int B, double* red, double* out_block) {
-  // red: LDS scratch of Q * blockDim doubles
-  for (int q = 0; q < Q; ++q) red[q * blockDim.x + threadIdx.x] = v[q];
-  __syncthreads();
-  for (int s = blockDim.x / 2; s >= B; s >>= 1) {
-    if (threadIdx.x < (unsigned)s)
-      for (int q = 0; q < Q; ++q) red[q * blockDim.x + threadIdx.x] += red[q * blockDim.x + threadIdx.x + s];
-    __syncthreads();
-  }
-  if (threadIdx.x < (unsigned)B)
-    for (int q = 0; q < Q; ++q) out_block[q * B + threadIdx.x] = red[q * blockDim.x + threadIdx.x];
-}
-
-// Reduces partials part[g][q][b] over g < G in a fixed order; every block
-// computes identical totals.  out[q * B + b] in LDS, valid after return.
-__device__ __forceinline__ void reduce_partials(const double* __restrict__ part, int G, int Q, int B, double* red,
-                                                double* out) {
-  const int cols = Q * B;
-  const int lanes_per_col = blockDim.x / cols > 0 ? blockDim.x / cols : 1;
-  const int c = threadIdx.x % cols;
-  const int g0 = threadIdx.x / cols;
-  double acc = 0.0;
-  if ((int)threadIdx.x < cols * lanes_per_col)
-    for (int g = g0; g < G; g += lanes_per_col) acc += part[(size_t)g * cols + c];
-  red[threadIdx.x] = acc;
-  __syncthreads();
-  if ((int)threadIdx.x < cols) {
-    double t = 0.0;
-    for (int l = 0; l < lanes_per_col; ++l) t += red[l * cols + threadIdx.x];
-    out[threadIdx.x] = t;
-  }
-  // columns beyond blockDim (Q * B > blockDim) are reduced serially
-  for (int cc = blockDim.x + threadIdx.x; cc < cols; cc += blockDim.x) {
-    double t = 0.0;
-    for (int g = 0; g < G; ++g) t += part[(size_t)g * cols + cc];
-    out[cc] = t;
-  }
-  __syncthreads();
-}
-
-// ------------------------------------------------------- Lanczos passes
-// Stored vectors u_j are unnormalised: v_j = sigma_j u_j.  Iteration j:
-//   pass A:  w = a_j H u_j - b_j u_{j-1}      (= H v_j - beta_{j-1} v_{j-1}, or H u_0 at j = 0)
-//            partials  Re<u_j, w>, |u_j|^2
-//   pass B:  u_{j+1} = c_j (w - d_j u_j)       (= w - alpha_j v_j in v-units)
-//            partial   |u_{j+1}|^2  -> beta_j
-// The scalars come from the previous pass's partials, reduced in each block.
-struct LanczosArgs {
-  int j, m;
-  double breakdown_rtol;
-};
-
 template <typename T, bool CSR>
 __global__ void __launch_bounds__(kMaxBlock)
 k_lanczos_A(const typename Cx<T>::V* __restrict__ uj, const typename Cx<T>::V* __restrict__ ujm1,
@@ -326,48 +102,8 @@ k_lanczos_A(const typename Cx<T>::V* __restrict__ uj, const typename Cx<T>::V* _
   __shared__ double sa[QK_MAX_BATCH], sb[QK_MAX_BATCH];
   __shared__ int act[QK_MAX_BATCH];
   load_row_shared(sh, a, gtab, gfields);
-  const int B = a.B, j = la.j;
-  if (j == 0) {
-    for (int b = threadIdx.x; b < B; b += blockDim.x) {
-      sa[b] = 1.0;
-      sb[b] = 0.0;
-      act[b] = 1;
-      if (blockIdx.x == 0) {
-        st.mused[b] = la.m;
-        st.status[b] = QK_OK;
-      }
-    }
-    __syncthreads();
-  } else {
-    reduce_partials(partB, Gp, 1, B, red, tot);
-    for (int b = threadIdx.x; b < B; b += blockDim.x) {
-      int active = st.mused[b] > j;
-      const double beta = sqrt(tot[b]);
-      if (active) {
-        double scale = beta;
-        for (int i = 0; i < j; ++i) scale = fmax(scale, fabs(st.alpha[i * B + b]));
-        for (int i = 0; i + 1 < j; ++i) scale = fmax(scale, st.beta[i * B + b]);
-        if (!isfinite(beta)) {
-          active = 0;
-          if (blockIdx.x == 0) {
-            st.status[b] = QK_ENUMERIC;
-            st.mused[b] = j;
-          }
-        } else if (beta <= la.breakdown_rtol * scale) {
-          active = 0;  // invariant subspace: the Krylov space stops at dimension j
-          if (blockIdx.x == 0) st.mused[b] = j;
-        }
-        if (blockIdx.x == 0) st.beta[(j - 1) * B + b] = beta;
-      }
-      if (active) {
-        sa[b] = 1.0 / beta;
-        sb[b] = beta * st.sigma[(j - 1) * B + b];
-        if (blockIdx.x == 0) st.sigma[j * B + b] = 1.0 / beta;
-      }
-      act[b] = active;
-    }
-    __syncthreads();
-  }
+  const int B = a.B;
+  lanczos_h_scalars(B, st, la, partB, Gp, red, tot, sa, sb, act);
 
   const int b = threadIdx.x % B;
   const uint32_t R = blockDim.x / B, rl = threadIdx.x / B;
@@ -383,7 +119,7 @@ k_lanczos_A(const typename Cx<T>::V* __restrict__ uj, const typename Cx<T>::V* _
       V wv;
       wv.x = ca * hx.x;
       wv.y = ca * hx.y;
-      if (j > 0) {
+      if (la.j > 0) {
         const V um = ujm1[(size_t)r * B + b];
         wv.x -= cb * um.x;
         wv.y -= cb * um.y;
@@ -697,6 +433,7 @@ static int stream_grid(uint64_t rows, int B) {
   const uint64_t R = threads / B;
   uint64_t tiles = (rows + R - 1) / R;
   uint64_t g = (uint64_t)num_cus() * 8;
+  if (g > (uint64_t)kMaxPartialBlocks) g = kMaxPartialBlocks;
   if (g > tiles) g = tiles;
   g = ((g + kNumXcd - 1) / kNumXcd) * kNumXcd;
   if (g < kNumXcd) g = kNumXcd;
@@ -795,6 +532,7 @@ qk_status launch_csr_build(qk_ham* H, hipStream_t s) {
 }
 
 qk_status launch_ham_apply(const qk_ham* H, const void* x, void* y, int dtype, hipStream_t s) {
+  if (blocked_usable(H, dtype)) return launch_blocked_apply(H, x, y, dtype, s);
   const ModelArgs a = model_args(H);
   const HamView hv = ham_view(H);
   const int threads = block_threads(a.B);
@@ -847,7 +585,11 @@ static qk_status krylov_step_t(qk_krylov* k, void* psi_v, double dt, hipStream_t
     const V* ujm1 = j == 0 ? nullptr : (j == 1 ? psi : U + (size_t)(j - 2) * stride);
     V* w = U + (size_t)j * stride;
     QK_MARK(QK_KERNEL_LANCZOS_H, true);
-    if (csr)
+    int Ga = G;
+    if (blocked_usable(H, k->dtype)) {
+      qk_status bs = launch_blocked_lanczos_h(H, k->dtype, uj, ujm1, w, st, la, k->d_partB, G, k->d_partA, &Ga, s);
+      if (bs != QK_OK) return bs;
+    } else if (csr)
       hipLaunchKernelGGL((k_lanczos_A<T, true>), dim3(G), dim3(threads), 0, s, uj, ujm1, w, a, hv,
                          H->basis->d_binom, H->d_fields, st, la, k->d_partB, G, k->d_partA);
     else
@@ -856,7 +598,7 @@ static qk_status krylov_step_t(qk_krylov* k, void* psi_v, double dt, hipStream_t
     QK_HIP(hipGetLastError());
     QK_MARK(QK_KERNEL_LANCZOS_H, false);
     QK_MARK(QK_KERNEL_LANCZOS_UPDATE, true);
-    hipLaunchKernelGGL((k_lanczos_B<T>), dim3(G), dim3(threads), 0, s, uj, w, D, B, st, la, k->d_partA, G,
+    hipLaunchKernelGGL((k_lanczos_B<T>), dim3(G), dim3(threads), 0, s, uj, w, D, B, st, la, k->d_partA, Ga,
                        k->d_partB, j + 1 < m ? 1 : 0);
     QK_HIP(hipGetLastError());
     QK_MARK(QK_KERNEL_LANCZOS_UPDATE, false);

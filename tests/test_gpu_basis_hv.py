@@ -134,3 +134,37 @@ def test_hv_full_size_sampled_rows(L, pbc):
     assert np.array_equal(st_dev, basis)
     ref = OH.apply_rows(L, N, pbc, 1.0, 1.0, h, xh, rows, basis=basis)
     assert max_rel(to_host(y)[rows], ref) < 1e-13
+
+
+BLOCKED = [(18, 9, True), (19, 9, True), (20, 10, True), (20, 7, False), (22, 11, False), (22, 11, True)]
+
+
+@pytest.mark.parametrize("dtype", [torch.complex128, torch.complex64])
+@pytest.mark.parametrize("L,N,pbc", BLOCKED)
+def test_hv_blocked_full_vector(L, N, pbc, dtype):
+    # L >= 18 with one field set runs the blocked form; every row is checked
+    h = random_fields(L, 200 + L)
+    b = qk.qk_basis_build(L, N)
+    say("hv blocked", L, N, pbc, dtype)
+    H = qk.qk_ham_create(b, 1.0, 0.8, pbc, h)
+    D = qk.qk_basis_dim(b)
+    xd = to_dev(random_complex(D, 17 + L), dtype)
+    y = to_host(qk.qk_ham_apply(H, xd))
+    ref = OH.build_csr(L, N, pbc, 1.0, 0.8, h) @ to_host(xd).astype(np.complex128)
+    assert max_rel(y, ref) < TOL[dtype]
+
+
+@pytest.mark.parametrize("pbc", [False, True])
+def test_blocked_equals_row_form(pbc):
+    # two independent device formulations of the same rows
+    L, N = 24, 12
+    h = random_fields(L, 3)
+    b = qk.qk_basis_build(L, N)
+    D = qk.qk_basis_dim(b)
+    say("blocked vs rows", L, pbc)
+    Hb = qk.qk_ham_create(b, 1.0, 1.0, pbc, h, qk.QK_MATFREE)
+    Hr = qk.qk_ham_create(b, 1.0, 1.0, pbc, h, qk.QK_MATFREE_ROWS)
+    x = to_dev(random_complex(D, 8))
+    yb = to_host(qk.qk_ham_apply(Hb, x))
+    yr = to_host(qk.qk_ham_apply(Hr, x))
+    assert max_rel(yb, yr) < 1e-14

@@ -245,3 +245,43 @@ def test_return_prob_general_state_and_determinism():
     ref = OX.evolve(Hd, p0, [0.5])[0]
     assert P == pytest.approx(OX.overlap_probability(p0, ref), abs=1e-12)
     assert np.linalg.norm(runs[0] - ref) < 1e-10
+
+
+def test_blocked_krylov_vs_expm_multiply():
+    # L=18 runs the blocked H-pass; reference: scipy's expm_multiply on the oracle's H
+    from oracle import midsize as OMS
+    L, pbc = 18, True
+    b, H, hf = _problem(L, pbc)
+    psi, r0 = _neel_psi(b, L)
+    k = qk.qk_krylov_create(H, 30)
+    dt, steps = 0.1, 10
+    P = torch.empty(steps, dtype=torch.float64, device="cuda")
+    say("blocked krylov", L)
+    for s in range(steps):
+        qk.qk_krylov_expm_step(k, psi, dt)
+        qk.qk_return_prob(b, psi, r0=r0, out=P[s:s + 1])
+    Hc = OH.build_csr(L, L // 2, pbc, 1.0, 1.0, hf)
+    t = dt * np.arange(1, steps + 1)
+    F = OMS.survival_probability(Hc, r0, t)
+    assert np.max(np.abs(to_host(P) - F)) < 1e-10
+    e0 = np.zeros(Hc.shape[0], complex)
+    e0[r0] = 1
+    ref = OMS.evolve(Hc, e0, [t[-1]])[0]
+    assert np.linalg.norm(to_host(psi) - ref) < 1e-9
+
+
+def test_blocked_complex64_vs_complex128():
+    L = 20
+    b, H, hf = _problem(L, True)
+    r0 = neel_row(L)
+    Ps = []
+    for dtype in (torch.complex128, torch.complex64):
+        psi, _ = _neel_psi(b, L, dtype)
+        k = qk.qk_krylov_create(H, 30, dtype)
+        P = torch.empty(20, dtype=torch.float64, device="cuda")
+        say("blocked", dtype)
+        for s in range(20):
+            qk.qk_krylov_expm_step(k, psi, 0.1)
+            qk.qk_return_prob(b, psi, r0=r0, out=P[s:s + 1])
+        Ps.append(to_host(P))
+    assert np.max(np.abs(Ps[0] - Ps[1])) < 1e-5
