@@ -167,9 +167,10 @@ typedef struct qk_krylov qk_krylov;
  * Workspace for Krylov steps of dimension m (1 <= m <= QK_MAX_M) on
  * Hamiltonian H (Sec. 2 "Krylov subspace methods"): m device vectors of
  * D x batch elements of `dtype`, the Lanczos coefficients and the reduction
- * scratch.  reorth: 0 = none (plain three-term recurrence), 1 = local (the
- * new vector is also orthogonalised against the previous one).  The
- * Hamiltonian must outlive the workspace.
+ * scratch.  reorth: 0 = none (plain three-term recurrence), 1 = local (each
+ * new vector is also orthogonalised against v_{j-1}, the alpha term having
+ * removed v_j; the dot product is accumulated in double; one extra vector
+ * read per iteration).  The Hamiltonian must outlive the workspace.
  */
 qk_status qk_krylov_create(const qk_ham* H, int32_t m, int32_t dtype, int32_t reorth, qk_krylov** out);
 
@@ -217,6 +218,58 @@ typedef struct {
 
 qk_status qk_krylov_profile(qk_krylov* k, int32_t enable);
 qk_status qk_krylov_profile_read(qk_krylov* k, qk_kernel_time* out);
+
+/* -------------------------------------------------------- launch shapes */
+typedef struct {
+  int32_t threads;             /* threads per block of the row-streaming kernels
+                                  (rounded down to batch * 2^k); 0 = 256 */
+  int32_t blocks_per_cu;       /* blocks per compute unit of the row-streaming kernels; 0 = 8 */
+  int32_t blocked_wgs_per_cu;  /* work-groups per compute unit of the blocked H-pass;
+                                  0 = as many as fit */
+} qk_launch_shape;
+
+/* Sets / reads the launch shape of a workspace's kernels.  Results do not
+ * depend on the shape beyond the order of floating-point reductions. */
+qk_status qk_krylov_set_shape(qk_krylov* k, const qk_launch_shape* shape);
+qk_status qk_krylov_get_shape(const qk_krylov* k, qk_launch_shape* shape);
+
+/*
+ * Autotuner: times one step of the workspace (time step dt) for a small set
+ * of launch shapes with HIP events on `stream`, on a scratch vector the call
+ * allocates and frees, and applies the fastest.  With a non-NULL cache_path
+ * the result is looked up first and stored afterwards in that JSON file,
+ * keyed by (L, n_up, boundary, batch, mode, dtype, m, reorth, compute units).
+ * Synchronous.  *chosen (may be NULL) receives the shape.
+ */
+qk_status qk_krylov_autotune(qk_krylov* k, double dt, const char* cache_path, void* stream, qk_launch_shape* chosen);
+
+/* ------------------------------------------------------- batched driver */
+typedef struct qk_batch qk_batch;
+
+/*
+ * Groups n (1..64) distinct workspaces -- any chain lengths, field-set counts
+ * and Krylov dimensions, one dtype each -- with their state vectors psi[i]
+ * (device, [D_i][B_i], updated in place) and the basis rows r0[i] of their
+ * initial basis states, so that they advance together.  The handles and
+ * vectors must outlive the batch.
+ */
+qk_status qk_batch_create(qk_krylov* const* ks, void* const* psi, const int64_t* r0, int32_t n, qk_batch** out);
+
+/* Total number of batch items (sum of the workspaces' field-set counts). */
+qk_status qk_batch_items(const qk_batch* b, int32_t* items);
+
+/*
+ * n_steps Krylov steps of length dt of every workspace.  After step k the
+ * survival probability |psi_i[r0_i]|^2 of every item is written to
+ * P_device[k * items + offset_i + item] (offsets in workspace order).  With
+ * use_graph = 1 one step of all workspaces (one graph branch each) is
+ * captured into a hipGraph on first use (and again when dt or P_device
+ * change) and replayed n_steps times; with 0 the same work is enqueued
+ * directly.  Asynchronous.
+ */
+qk_status qk_batch_run(qk_batch* b, double dt, int32_t n_steps, int32_t use_graph, double* P_device, void* stream);
+
+void qk_batch_destroy(qk_batch* b);
 
 /* ----------------------------------------------------------- observable */
 /*

@@ -14,7 +14,7 @@ import numpy as np
 import torch
 
 from . import _native
-from ._native import HamParams, KernelTime, StepInfo, lib
+from ._native import HamParams, KernelTime, LaunchShape, StepInfo, lib
 
 QK_OK, QK_EINVAL, QK_ENOMEM, QK_EHIP, QK_EUNSUPPORTED, QK_ENUMERIC = range(6)
 QK_C128, QK_C64 = 0, 1
@@ -87,6 +87,10 @@ class Ham(_Handle):
 
 class Krylov(_Handle):
     _destroy = staticmethod(lib.qk_krylov_destroy)
+
+
+class Batch(_Handle):
+    _destroy = staticmethod(lib.qk_batch_destroy)
 
 
 def qk_abi_version() -> int:
@@ -234,6 +238,67 @@ def qk_krylov_profile_read(k: Krylov) -> dict:
     return {name: (arr[i].ms_total, arr[i].launches) for i, name in enumerate(KERNEL_KINDS)}
 
 
+def _shape_dict(sh: LaunchShape) -> dict:
+    return dict(threads=sh.threads, blocks_per_cu=sh.blocks_per_cu, blocked_wgs_per_cu=sh.blocked_wgs_per_cu)
+
+
+def qk_krylov_set_shape(k: Krylov, threads: int = 0, blocks_per_cu: int = 0, blocked_wgs_per_cu: int = 0) -> None:
+    sh = LaunchShape(threads, blocks_per_cu, blocked_wgs_per_cu)
+    _check(lib.qk_krylov_set_shape(k.ptr, C.byref(sh)), "qk_krylov_set_shape")
+
+
+def qk_krylov_get_shape(k: Krylov) -> dict:
+    sh = LaunchShape()
+    _check(lib.qk_krylov_get_shape(k.ptr, C.byref(sh)), "qk_krylov_get_shape")
+    return _shape_dict(sh)
+
+
+def qk_krylov_autotune(k: Krylov, dt: float, cache_path: str | None = None, stream=None) -> dict:
+    """Times launch shapes for one step of this workspace and applies the
+    fastest (looked up in / stored to the JSON file `cache_path`)."""
+    sh = LaunchShape()
+    path = None if cache_path is None else str(cache_path).encode()
+    _check(lib.qk_krylov_autotune(k.ptr, float(dt), path, _stream(stream), C.byref(sh)), "qk_krylov_autotune")
+    return _shape_dict(sh)
+
+
+def qk_batch_create(ks, psis, r0s) -> Batch:
+    """Groups workspaces with their state vectors and initial basis rows."""
+    n = len(ks)
+    if not (len(psis) == len(r0s) == n):
+        raise ValueError("ks, psis and r0s must have the same length")
+    for k, p in zip(ks, psis):
+        D, Bn, _ = qk_ham_shape(k.H)
+        _check_vec(D, p, Bn, "psi")
+        if dtype_code(p) != k.dtype:
+            raise ValueError("psi dtype differs from its workspace")
+    karr = (C.c_void_p * n)(*[k.ptr.value for k in ks])
+    parr = (C.c_void_p * n)(*[p.data_ptr() for p in psis])
+    rarr = (C.c_int64 * n)(*[int(r) for r in r0s])
+    out = C.c_void_p()
+    _check(lib.qk_batch_create(karr, parr, rarr, n, C.byref(out)), "qk_batch_create")
+    return Batch(out, keep=(tuple(ks), tuple(psis)))
+
+
+def qk_batch_items(b: Batch) -> int:
+    n = C.c_int32()
+    _check(lib.qk_batch_items(b.ptr, C.byref(n)), "qk_batch_items")
+    return n.value
+
+
+def qk_batch_run(b: Batch, dt: float, n_steps: int, use_graph: bool = True, out: torch.Tensor | None = None,
+                 stream=None) -> torch.Tensor:
+    """n_steps steps of every workspace; returns the device tensor P[n_steps, items]."""
+    items = qk_batch_items(b)
+    if out is None:
+        out = torch.empty((n_steps, items), dtype=torch.float64, device="cuda")
+    if out.numel() < n_steps * items or out.dtype != torch.float64:
+        raise ValueError("out must be a float64 tensor of n_steps * items entries")
+    _check(lib.qk_batch_run(b.ptr, float(dt), int(n_steps), int(bool(use_graph)), _dptr(out), _stream(stream)),
+           "qk_batch_run")
+    return out
+
+
 def qk_return_prob(b: Basis, psi: torch.Tensor, r0: int = -1, psi0: torch.Tensor | None = None,
                    batch: int = 1, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
     """|<psi0|psi>|^2 per batch item into a device float64 tensor (asynchronous)."""
@@ -247,4 +312,4 @@ def qk_return_prob(b: Basis, psi: torch.Tensor, r0: int = -1, psi0: torch.Tensor
     return out
 
 
-__all__ = [n for n in dir() if n.startswith("qk_")] + ["QkError", "Basis", "Ham", "Krylov"]
+__all__ = [n for n in dir() if n.startswith("qk_")] + ["QkError", "Basis", "Ham", "Krylov", "Batch"]

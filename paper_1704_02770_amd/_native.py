@@ -32,6 +32,10 @@ class KernelTime(C.Structure):
     _fields_ = [("ms_total", f64), ("launches", i64)]
 
 
+class LaunchShape(C.Structure):
+    _fields_ = [("threads", i32), ("blocks_per_cu", i32), ("blocked_wgs_per_cu", i32)]
+
+
 class StepInfo(C.Structure):
     _fields_ = [("m_used", i32), ("status", i32), ("err_est", f64), ("beta0", f64)]
 
@@ -58,6 +62,13 @@ SIGNATURES = {
     "qk_krylov_destroy": (None, [vp]),
     "qk_krylov_profile": (i32, [vp, i32]),
     "qk_krylov_profile_read": (i32, [vp, P(KernelTime)]),
+    "qk_krylov_set_shape": (i32, [vp, P(LaunchShape)]),
+    "qk_krylov_get_shape": (i32, [vp, P(LaunchShape)]),
+    "qk_krylov_autotune": (i32, [vp, f64, C.c_char_p, vp, P(LaunchShape)]),
+    "qk_batch_create": (i32, [P(vp), P(vp), P(i64), i32, P(vp)]),
+    "qk_batch_items": (i32, [vp, P(i32)]),
+    "qk_batch_run": (i32, [vp, f64, i32, i32, vp, vp]),
+    "qk_batch_destroy": (None, [vp]),
     "qk_return_prob": (i32, [vp, i64, vp, vp, i32, i32, vp, vp]),
 }
 

@@ -8,7 +8,7 @@
 #include <string>
 #include <vector>
 
-#include "qk_internal.h"
+#include "qk_device.h"
 
 namespace qk {
 
@@ -289,10 +289,7 @@ QK_API qk_status qk_krylov_create(const qk_ham* H, int32_t m, int32_t dtype, int
   if (!H) return inval("NULL Hamiltonian");
   if (m < 1 || m > QK_MAX_M) return inval("m must be in [1, 64]");
   if (dtype != QK_C128 && dtype != QK_C64) return inval("unknown dtype");
-  if (reorth != 0) {
-    set_error("only reorth = 0 is implemented");
-    return QK_EUNSUPPORTED;
-  }
+  if (reorth != 0 && reorth != 1) return inval("reorth must be 0 or 1");
   qk_status st = check_device(H->device);
   if (st != QK_OK) return st;
   qk_krylov* k = new (std::nothrow) qk_krylov;
@@ -307,7 +304,7 @@ QK_API qk_status qk_krylov_create(const qk_ham* H, int32_t m, int32_t dtype, int
   k->grid = krylov_grid((uint64_t)k->D, k->batch);
   const size_t vec = elem_bytes(dtype) * (size_t)k->D * k->batch;
   hipError_t e = hipMalloc(&k->d_U, vec * (size_t)m);
-  if (e == hipSuccess) e = hipMalloc((void**)&k->d_partA, sizeof(double) * (size_t)kMaxPartialBlocks * 2 * k->batch);
+  if (e == hipSuccess) e = hipMalloc((void**)&k->d_partA, sizeof(double) * (size_t)kMaxPartialBlocks * kQA * k->batch);
   if (e == hipSuccess) e = hipMalloc((void**)&k->d_partB, sizeof(double) * (size_t)kMaxPartialBlocks * k->batch);
   if (e == hipSuccess) e = hipMalloc((void**)&k->d_coef, sizeof(double) * kstate_doubles(m, k->batch));
   if (e == hipSuccess) e = hipMalloc((void**)&k->d_int, sizeof(int32_t) * 2 * k->batch);
@@ -424,6 +421,80 @@ QK_API void qk_krylov_destroy(qk_krylov* k) {
   if (k->d_int) hipFree(k->d_int);
   delete k;
 }
+
+// ------------------------------------------------------------ launch shapes
+QK_API qk_status qk_krylov_set_shape(qk_krylov* k, const qk_launch_shape* shape) {
+  g_err.clear();
+  if (!k || !shape) return inval("NULL pointer");
+  return apply_shape(k, shape);
+}
+
+QK_API qk_status qk_krylov_get_shape(const qk_krylov* k, qk_launch_shape* shape) {
+  g_err.clear();
+  if (!k || !shape) return inval("NULL pointer");
+  shape->threads = k->threads;
+  shape->blocks_per_cu = k->blocks_per_cu;
+  shape->blocked_wgs_per_cu = k->blocked_wgs;
+  return QK_OK;
+}
+
+QK_API qk_status qk_krylov_autotune(qk_krylov* k, double dt, const char* cache_path, void* stream,
+                                    qk_launch_shape* chosen) {
+  g_err.clear();
+  if (!k) return inval("NULL workspace");
+  if (!std::isfinite(dt)) return inval("dt not finite");
+  qk_status st = check_device(k->device);
+  if (st != QK_OK) return st;
+  return krylov_autotune(k, dt, cache_path, (hipStream_t)stream, chosen);
+}
+
+// ----------------------------------------------------------- batched driver
+QK_API qk_status qk_batch_create(qk_krylov* const* ks, void* const* psi, const int64_t* r0, int32_t n,
+                                 qk_batch** out) {
+  g_err.clear();
+  if (!out) return inval("NULL out");
+  *out = nullptr;
+  if (n < 1 || n > 64) return inval("n must be in [1, 64]");
+  if (!ks || !psi || !r0) return inval("NULL pointer");
+  for (int i = 0; i < n; ++i) {
+    if (!ks[i] || !psi[i]) return inval("NULL workspace or vector");
+    if (ks[i]->device != ks[0]->device) return inval("workspaces on different devices");
+    if (r0[i] < 0 || r0[i] >= ks[i]->D) return inval("r0 out of range");
+    if ((uintptr_t)psi[i] % elem_bytes(ks[i]->dtype)) return inval("misaligned psi");
+    const size_t vec = elem_bytes(ks[i]->dtype) * (size_t)ks[i]->D * ks[i]->batch;
+    for (int j = 0; j < n; ++j) {
+      if (j != i && ks[j] == ks[i]) return inval("a workspace appears twice");
+      const size_t vj = elem_bytes(ks[j]->dtype) * (size_t)ks[j]->D * ks[j]->batch;
+      if (ranges_overlap(psi[i], vec, ks[j]->d_U, vj * (size_t)ks[j]->m)) return inval("psi overlaps a workspace");
+      if (j != i && ranges_overlap(psi[i], vec, psi[j], vj)) return inval("state vectors overlap");
+    }
+  }
+  qk_status st = check_device(ks[0]->device);
+  if (st != QK_OK) return st;
+  return batch_create(ks, psi, r0, n, out);
+}
+
+QK_API qk_status qk_batch_items(const qk_batch* b, int32_t* items) {
+  g_err.clear();
+  if (!b || !items) return inval("NULL pointer");
+  *items = batch_items(b);
+  return QK_OK;
+}
+
+QK_API qk_status qk_batch_run(qk_batch* b, double dt, int32_t n_steps, int32_t use_graph, double* P_device,
+                              void* stream) {
+  g_err.clear();
+  if (!b || !P_device) return inval("NULL pointer");
+  if (!std::isfinite(dt)) return inval("dt not finite");
+  if (n_steps < 0) return inval("n_steps < 0");
+  if (use_graph != 0 && use_graph != 1) return inval("use_graph must be 0 or 1");
+  qk_status st = check_device(batch_device(b));
+  if (st != QK_OK) return st;
+  if (n_steps == 0) return QK_OK;
+  return batch_run(b, dt, n_steps, use_graph, P_device, (hipStream_t)stream);
+}
+
+QK_API void qk_batch_destroy(qk_batch* b) { batch_destroy(b); }
 
 // -------------------------------------------------------------- observable
 QK_API qk_status qk_return_prob(const qk_basis* b, int64_t r0, const void* psi0, const void* psi, int32_t dtype,

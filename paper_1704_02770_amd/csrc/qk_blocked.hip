@@ -133,11 +133,11 @@ constexpr int blk_max_len() {
 }
 
 // Bytes of the two x buffers at the start of dynamic LDS; at least the
-// 2 x 256 doubles of the reductions that alias them.
+// kQA x 256 doubles of the reductions that alias them.
 template <typename T, int LLO>
 constexpr size_t blk_xbytes() {
   constexpr size_t b = sizeof(typename Cx<T>::V) * 2 * (size_t)blk_max_len<LLO>();
-  return b > 2 * kBlkThreads * sizeof(double) ? b : 2 * kBlkThreads * sizeof(double);
+  return b > kQA * kBlkThreads * sizeof(double) ? b : kQA * kBlkThreads * sizeof(double);
 }
 
 // Element idx of a vector through a 32-bit byte offset from a uniform base
@@ -211,7 +211,7 @@ k_blk(BlkArgs ba, const typename Cx<T>::V* __restrict__ x, typename Cx<T>::V* __
   const double hjz = 0.5 * ba.jz;
   const T ca = (T)sa[0], cb = (T)sb[0];
   const bool prev = LANCZOS && la.j > 0;
-  double s1 = 0.0, s2 = 0.0;
+  double s1 = 0.0, s2 = 0.0, s3r = 0.0, s3i = 0.0;
   const int lhi = ba.lhi;
   const int xcd = blockIdx.x % kNumXcd, kx = blockIdx.x / kNumXcd, per = gridDim.x / kNumXcd;
   const int first = ba.xcd_first[xcd], last = ba.xcd_first[xcd + 1];
@@ -323,6 +323,8 @@ k_blk(BlkArgs ba, const typename Cx<T>::V* __restrict__ x, typename Cx<T>::V* __
         st32(y, r, wv);
         s1 += (double)xr.x * (double)wv.x + (double)xr.y * (double)wv.y;
         s2 += (double)xr.x * (double)xr.x + (double)xr.y * (double)xr.y;
+        s3r += (double)um.x * (double)wv.x + (double)um.y * (double)wv.y;
+        s3i += (double)um.x * (double)wv.y - (double)um.y * (double)wv.x;
       } else {
         st32(y, r, h);
       }
@@ -337,8 +339,8 @@ k_blk(BlkArgs ba, const typename Cx<T>::V* __restrict__ x, typename Cx<T>::V* __
     cur ^= 1;
   }
   if (LANCZOS) {
-    double v[2] = {s1, s2};
-    block_partials<2>(v, 1, red, partA + (size_t)blockIdx.x * 2);
+    double v[kQA] = {s1, s2, s3r, s3i};
+    block_partials<kQA>(v, 1, red, partA + (size_t)blockIdx.x * kQA);
   }
 }
 
@@ -467,7 +469,7 @@ bool blocked_usable(const qk_ham* H, int dtype) {
 template <typename T, int LLO, bool LANCZOS>
 static qk_status launch_blk_t(const qk_ham* H, const void* x, void* y, const void* ujm1, const KState* st,
                               const LanczosArgs* la, const double* partB, int Gp, double* partA, int* grid_out,
-                              hipStream_t s) {
+                              int wgs_req, hipStream_t s) {
   using V = typename Cx<T>::V;
   const BlkArgs ba = blk_args(H);
   const size_t dyn = blk_xbytes<T, LLO>() + 2 * sizeof(uint16_t) * ((size_t)1 << LLO);
@@ -478,12 +480,8 @@ static qk_status launch_blk_t(const qk_ham* H, const void* x, void* y, const voi
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, kern, kBlkThreads, dyn) != hipSuccess || n < 1) n = 1;
     occ = n;
   }
-  int cus = 0, dev = 0;
-  hipDeviceProp_t prop;
-  QK_HIP(hipGetDevice(&dev));
-  QK_HIP(hipGetDeviceProperties(&prop, dev));
-  cus = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
-  int wgs = env_int("QK_BLOCKED_WGS_PER_CU", occ);
+  const int cus = qk_num_cus();
+  int wgs = wgs_req > 0 ? wgs_req : env_int("QK_BLOCKED_WGS_PER_CU", occ);
   if (wgs > occ) wgs = occ;
   int G = ((cus * wgs) / kNumXcd) * kNumXcd;
   if (G < kNumXcd) G = kNumXcd;
@@ -502,27 +500,27 @@ static qk_status launch_blk_t(const qk_ham* H, const void* x, void* y, const voi
 template <typename T, bool LANCZOS>
 static qk_status launch_blk_llo(const qk_ham* H, const void* x, void* y, const void* ujm1, const KState* st,
                                 const LanczosArgs* la, const double* partB, int Gp, double* partA, int* grid_out,
-                                hipStream_t s) {
+                                int wgs, hipStream_t s) {
   switch (H->llo) {
-    case 9: return launch_blk_t<T, 9, LANCZOS>(H, x, y, ujm1, st, la, partB, Gp, partA, grid_out, s);
-    case 10: return launch_blk_t<T, 10, LANCZOS>(H, x, y, ujm1, st, la, partB, Gp, partA, grid_out, s);
-    case 11: return launch_blk_t<T, 11, LANCZOS>(H, x, y, ujm1, st, la, partB, Gp, partA, grid_out, s);
+    case 9: return launch_blk_t<T, 9, LANCZOS>(H, x, y, ujm1, st, la, partB, Gp, partA, grid_out, wgs, s);
+    case 10: return launch_blk_t<T, 10, LANCZOS>(H, x, y, ujm1, st, la, partB, Gp, partA, grid_out, wgs, s);
+    case 11: return launch_blk_t<T, 11, LANCZOS>(H, x, y, ujm1, st, la, partB, Gp, partA, grid_out, wgs, s);
     default: set_error("no blocked kernel for this low-bit count"); return QK_EUNSUPPORTED;
   }
 }
 
 qk_status launch_blocked_apply(const qk_ham* H, const void* x, void* y, int dtype, hipStream_t s) {
   if (dtype == QK_C128)
-    return launch_blk_llo<double, false>(H, x, y, nullptr, nullptr, nullptr, nullptr, 0, nullptr, nullptr, s);
-  return launch_blk_llo<float, false>(H, x, y, nullptr, nullptr, nullptr, nullptr, 0, nullptr, nullptr, s);
+    return launch_blk_llo<double, false>(H, x, y, nullptr, nullptr, nullptr, nullptr, 0, nullptr, nullptr, 0, s);
+  return launch_blk_llo<float, false>(H, x, y, nullptr, nullptr, nullptr, nullptr, 0, nullptr, nullptr, 0, s);
 }
 
 qk_status launch_blocked_lanczos_h(const qk_ham* H, int dtype, const void* uj, const void* ujm1, void* w,
                                    const KState& st, const LanczosArgs& la, const double* partB, int Gp,
-                                   double* partA, int* grid_out, hipStream_t s) {
+                                   double* partA, int* grid_out, int wgs_per_cu, hipStream_t s) {
   if (dtype == QK_C128)
-    return launch_blk_llo<double, true>(H, uj, w, ujm1, &st, &la, partB, Gp, partA, grid_out, s);
-  return launch_blk_llo<float, true>(H, uj, w, ujm1, &st, &la, partB, Gp, partA, grid_out, s);
+    return launch_blk_llo<double, true>(H, uj, w, ujm1, &st, &la, partB, Gp, partA, grid_out, wgs_per_cu, s);
+  return launch_blk_llo<float, true>(H, uj, w, ujm1, &st, &la, partB, Gp, partA, grid_out, wgs_per_cu, s);
 }
 
 }  // namespace qk

@@ -229,7 +229,12 @@ __device__ __forceinline__ void reduce_partials(const double* __restrict__ part,
 struct LanczosArgs {
   int j, m;
   double breakdown_rtol;
+  int reorth;   // 1: the update pass also removes the component along v_{j-1}
 };
+
+// Partial sums of the H-pass per batch column: Re<u_j, w>, |u_j|^2 and the
+// complex <u_{j-1}, w> used by the local reorthogonalisation.
+constexpr int kQA = 4;
 
 
 
@@ -290,6 +295,6 @@ __device__ __forceinline__ void lanczos_h_scalars(int B, const KState& st, const
 
 qk_status launch_blocked_lanczos_h(const qk_ham* H, int dtype, const void* uj, const void* ujm1, void* w,
                                    const KState& st, const LanczosArgs& la, const double* partB, int Gp,
-                                   double* partA, int* grid_out, hipStream_t s);
+                                   double* partA, int* grid_out, int wgs_per_cu, hipStream_t s);
 
 }  // namespace qk

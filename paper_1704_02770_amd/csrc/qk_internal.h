@@ -29,9 +29,11 @@ qk_status hip_fail(hipError_t e, const char* what);
 // Threads per block for a batch of B problems: B x 2^k <= 256, so that a
 // grid-stride loop keeps each thread on one batch column and per-column
 // tree reductions halve evenly.
-inline int block_threads(int B) {
+inline int block_threads(int B, int cap = kMaxBlock) {
+  if (cap < B) cap = B;
+  if (cap > kMaxBlock) cap = kMaxBlock;
   int t = B;
-  while (t * 2 <= kMaxBlock) t *= 2;
+  while (t * 2 <= cap) t *= 2;
   return t;
 }
 
@@ -71,6 +73,10 @@ struct qk_krylov {
   int32_t m = 0, dtype = 0, reorth = 0, batch = 1;
   int64_t D = 0;
   int device = 0;
+  // launch shape (qk_krylov_set_shape / qk_krylov_autotune); 0 = default
+  int threads = 0;                // threads per block of the row-streaming kernels (B * 2^k, <= 256)
+  int blocks_per_cu = 0;          // blocks per CU of the row-streaming kernels
+  int blocked_wgs = 0;            // work-groups per CU of the blocked H-pass
   int grid = 0;                   // blocks of the streaming kernels (multiple of 8)
   void* d_U = nullptr;            // m slots of [D][batch] vectors: u_1..u_m
   double* d_partA = nullptr;      // [grid][2][batch] partial sums of the H-pass
@@ -125,6 +131,16 @@ qk_status launch_blocked_fields(qk_ham* H, hipStream_t s);
 bool blocked_usable(const qk_ham* H, int dtype);
 qk_status launch_krylov_step(qk_krylov* k, void* psi, double dt, hipStream_t s);
 qk_status profile_mark(qk_krylov* k, int kind, bool begin, hipStream_t s);
+int stream_grid(uint64_t rows, int B, int threads, int blocks_per_cu);
+int krylov_threads(const qk_krylov* k);
+int qk_num_cus();
+qk_status apply_shape(qk_krylov* k, const qk_launch_shape* sh);
+qk_status krylov_autotune(qk_krylov* k, double dt, const char* cache_path, hipStream_t s, qk_launch_shape* chosen);
+qk_status batch_create(qk_krylov* const* ks, void* const* psi, const int64_t* r0, int n, qk_batch** out);
+void batch_destroy(qk_batch* b);
+qk_status batch_run(qk_batch* b, double dt, int n_steps, int use_graph, double* P, hipStream_t s);
+int batch_items(const qk_batch* b);
+int batch_device(const qk_batch* b);
 qk_status profile_collect(qk_krylov* k);
 qk_status launch_return_prob(const qk_basis* b, int64_t r0, const void* psi0, const void* psi, int dtype,
                              int B, double* P, hipStream_t s);

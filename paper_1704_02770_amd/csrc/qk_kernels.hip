@@ -97,7 +97,7 @@ k_lanczos_A(const typename Cx<T>::V* __restrict__ uj, const typename Cx<T>::V* _
             double* __restrict__ partA) {
   using V = typename Cx<T>::V;
   __shared__ RowShared sh;
-  __shared__ double red[2 * kMaxBlock];
+  __shared__ double red[kQA * kMaxBlock];
   __shared__ double tot[QK_MAX_BATCH];
   __shared__ double sa[QK_MAX_BATCH], sb[QK_MAX_BATCH];
   __shared__ int act[QK_MAX_BATCH];
@@ -108,7 +108,7 @@ k_lanczos_A(const typename Cx<T>::V* __restrict__ uj, const typename Cx<T>::V* _
   const int b = threadIdx.x % B;
   const uint32_t R = blockDim.x / B, rl = threadIdx.x / B;
   const uint32_t ntiles = (hv.D + R - 1) / R;
-  double s1 = 0.0, s2 = 0.0;
+  double s1 = 0.0, s2 = 0.0, s3r = 0.0, s3i = 0.0;
   if (act[b]) {
     const T ca = (T)sa[b], cb = (T)sb[b];
     for (TileWalk tw(ntiles); tw.t < tw.t_end; tw.t += tw.step) {
@@ -123,27 +123,31 @@ k_lanczos_A(const typename Cx<T>::V* __restrict__ uj, const typename Cx<T>::V* _
         const V um = ujm1[(size_t)r * B + b];
         wv.x -= cb * um.x;
         wv.y -= cb * um.y;
+        s3r += (double)um.x * (double)wv.x + (double)um.y * (double)wv.y;
+        s3i += (double)um.x * (double)wv.y - (double)um.y * (double)wv.x;
       }
       w[(size_t)r * B + b] = wv;
       s1 += (double)xr.x * (double)wv.x + (double)xr.y * (double)wv.y;
       s2 += (double)xr.x * (double)xr.x + (double)xr.y * (double)xr.y;
     }
   }
-  double v[2] = {s1, s2};
-  block_partials<2>(v, B, red, partA + (size_t)blockIdx.x * 2 * B);
+  double v[kQA] = {s1, s2, s3r, s3i};
+  block_partials<kQA>(v, B, red, partA + (size_t)blockIdx.x * kQA * B);
 }
 
 template <typename T>
 __global__ void __launch_bounds__(kMaxBlock)
-k_lanczos_B(const typename Cx<T>::V* __restrict__ uj, typename Cx<T>::V* __restrict__ w, uint32_t D, int B, KState st,
-            LanczosArgs la, const double* __restrict__ partA, int Gp, double* __restrict__ partB, int store) {
+k_lanczos_B(const typename Cx<T>::V* __restrict__ uj, const typename Cx<T>::V* __restrict__ ujm1,
+            typename Cx<T>::V* __restrict__ w, uint32_t D, int B, KState st, LanczosArgs la,
+            const double* __restrict__ partA, int Gp, double* __restrict__ partB, int store) {
   using V = typename Cx<T>::V;
-  __shared__ double red[2 * kMaxBlock];
-  __shared__ double tot[2 * QK_MAX_BATCH];
-  __shared__ double sc[QK_MAX_BATCH], sd[QK_MAX_BATCH];
+  __shared__ double red[kMaxBlock];
+  __shared__ double tot[kQA * QK_MAX_BATCH];
+  __shared__ double sc[QK_MAX_BATCH], sd[QK_MAX_BATCH], ser[QK_MAX_BATCH], sei[QK_MAX_BATCH];
   __shared__ int act[QK_MAX_BATCH];
   const int j = la.j;
-  reduce_partials(partA, Gp, 2, B, red, tot);
+  const bool ro = la.reorth && j > 0;
+  reduce_partials(partA, Gp, kQA, B, red, tot);
   for (int b = threadIdx.x; b < B; b += blockDim.x) {
     int active = st.mused[b] > j;
     if (active) {
@@ -181,6 +185,10 @@ k_lanczos_B(const typename Cx<T>::V* __restrict__ uj, typename Cx<T>::V* __restr
       if (active && blockIdx.x == 0) st.alpha[j * B + b] = alpha;
       sc[b] = c;
       sd[b] = d;
+      // component of w along v_{j-1}: <v_{j-1}, w> v_{j-1} = sigma_{j-1}^2 <u_{j-1}, w> u_{j-1}
+      const double sm = ro ? st.sigma[(j - 1) * B + b] : 0.0;
+      ser[b] = sm * sm * tot[2 * B + b];
+      sei[b] = sm * sm * tot[3 * B + b];
     }
     act[b] = active;
   }
@@ -191,14 +199,19 @@ k_lanczos_B(const typename Cx<T>::V* __restrict__ uj, typename Cx<T>::V* __restr
   const uint32_t ntiles = (D + R - 1) / R;
   double s = 0.0;
   if (act[b]) {
-    const double c = sc[b], d = sd[b];
+    const double c = sc[b], d = sd[b], er = ser[b], ei = sei[b];
     for (TileWalk tw(ntiles); tw.t < tw.t_end; tw.t += tw.step) {
       const uint32_t r = tw.t * R + rl;
       if (r >= D) continue;
       const size_t i = (size_t)r * B + b;
       const V wv = w[i], u = uj[i];
-      const double nx = c * ((double)wv.x - d * (double)u.x);
-      const double ny = c * ((double)wv.y - d * (double)u.y);
+      double nx = c * ((double)wv.x - d * (double)u.x);
+      double ny = c * ((double)wv.y - d * (double)u.y);
+      if (ro) {
+        const V um = ujm1[i];
+        nx -= er * (double)um.x - ei * (double)um.y;
+        ny -= er * (double)um.y + ei * (double)um.x;
+      }
       V o;
       o.x = (T)nx;
       o.y = (T)ny;
@@ -414,7 +427,7 @@ k_csr_diag(const uint32_t* __restrict__ states, uint32_t D, ModelArgs a, const d
 }
 
 // ================================================================ launchers
-static int num_cus() {
+int qk_num_cus() {
   static int n = 0;
   if (n == 0) {
     int dev = 0;
@@ -428,11 +441,12 @@ static int num_cus() {
 
 // Blocks of a streaming kernel: enough for 8 blocks per CU, at most one per
 // tile, rounded to a multiple of the XCD count.
-static int stream_grid(uint64_t rows, int B) {
-  const int threads = block_threads(B);
+int stream_grid(uint64_t rows, int B, int threads, int blocks_per_cu) {
+  if (threads <= 0) threads = block_threads(B);
+  if (blocks_per_cu <= 0) blocks_per_cu = 8;
   const uint64_t R = threads / B;
   uint64_t tiles = (rows + R - 1) / R;
-  uint64_t g = (uint64_t)num_cus() * 8;
+  uint64_t g = (uint64_t)qk_num_cus() * blocks_per_cu;
   if (g > (uint64_t)kMaxPartialBlocks) g = kMaxPartialBlocks;
   if (g > tiles) g = tiles;
   g = ((g + kNumXcd - 1) / kNumXcd) * kNumXcd;
@@ -536,7 +550,7 @@ qk_status launch_ham_apply(const qk_ham* H, const void* x, void* y, int dtype, h
   const ModelArgs a = model_args(H);
   const HamView hv = ham_view(H);
   const int threads = block_threads(a.B);
-  const int grid = stream_grid(hv.D, a.B);
+  const int grid = stream_grid(hv.D, a.B, threads, 0);
   const bool csr = H->p.mode == QK_CSR;
   if (dtype == QK_C128) {
     if (csr)
@@ -563,7 +577,7 @@ static qk_status krylov_step_t(qk_krylov* k, void* psi_v, double dt, hipStream_t
   const qk_ham* H = k->H;
   const ModelArgs a = model_args(H);
   const HamView hv = ham_view(H);
-  const int B = a.B, threads = block_threads(B), G = k->grid, m = k->m;
+  const int B = a.B, threads = krylov_threads(k), G = k->grid, m = k->m;
   const uint32_t D = hv.D;
   const size_t stride = (size_t)D * B;
   V* psi = (V*)psi_v;
@@ -580,14 +594,15 @@ static qk_status krylov_step_t(qk_krylov* k, void* psi_v, double dt, hipStream_t
     }                                                          \
   } while (0)
   for (int j = 0; j < m; ++j) {
-    LanczosArgs la{j, m, rtol};
+    LanczosArgs la{j, m, rtol, k->reorth};
     const V* uj = j == 0 ? psi : U + (size_t)(j - 1) * stride;
     const V* ujm1 = j == 0 ? nullptr : (j == 1 ? psi : U + (size_t)(j - 2) * stride);
     V* w = U + (size_t)j * stride;
     QK_MARK(QK_KERNEL_LANCZOS_H, true);
     int Ga = G;
     if (blocked_usable(H, k->dtype)) {
-      qk_status bs = launch_blocked_lanczos_h(H, k->dtype, uj, ujm1, w, st, la, k->d_partB, G, k->d_partA, &Ga, s);
+      qk_status bs = launch_blocked_lanczos_h(H, k->dtype, uj, ujm1, w, st, la, k->d_partB, G, k->d_partA, &Ga,
+                                              k->blocked_wgs, s);
       if (bs != QK_OK) return bs;
     } else if (csr)
       hipLaunchKernelGGL((k_lanczos_A<T, true>), dim3(G), dim3(threads), 0, s, uj, ujm1, w, a, hv,
@@ -598,7 +613,7 @@ static qk_status krylov_step_t(qk_krylov* k, void* psi_v, double dt, hipStream_t
     QK_HIP(hipGetLastError());
     QK_MARK(QK_KERNEL_LANCZOS_H, false);
     QK_MARK(QK_KERNEL_LANCZOS_UPDATE, true);
-    hipLaunchKernelGGL((k_lanczos_B<T>), dim3(G), dim3(threads), 0, s, uj, w, D, B, st, la, k->d_partA, Ga,
+    hipLaunchKernelGGL((k_lanczos_B<T>), dim3(G), dim3(threads), 0, s, uj, ujm1, w, D, B, st, la, k->d_partA, Ga,
                        k->d_partB, j + 1 < m ? 1 : 0);
     QK_HIP(hipGetLastError());
     QK_MARK(QK_KERNEL_LANCZOS_UPDATE, false);
@@ -666,7 +681,7 @@ qk_status launch_return_prob(const qk_basis* b, int64_t r0, const void* psi0, co
     return QK_OK;
   }
   const int threads = block_threads(B);
-  const int G = stream_grid(D, B);
+  const int G = stream_grid(D, B, threads, 0);
   double* part = nullptr;
   QK_HIP(hipMallocAsync((void**)&part, sizeof(double) * (size_t)G * 2 * B, s));
   if (dtype == QK_C128)
@@ -685,6 +700,8 @@ qk_status launch_return_prob(const qk_basis* b, int64_t r0, const void* psi0, co
   return QK_OK;
 }
 
-int krylov_grid(uint64_t D, int B) { return stream_grid(D, B); }
+int krylov_threads(const qk_krylov* k) { return block_threads(k->batch, k->threads > 0 ? k->threads : kMaxBlock); }
+
+int krylov_grid(uint64_t D, int B) { return stream_grid(D, B, 0, 0); }
 
 }  // namespace qk

@@ -1,0 +1,128 @@
+"""GPU tests of the batched driver (one hipGraph launch per step for several
+workspaces of different chain lengths and batch sizes) and of the launch-shape
+autotuner: results must not depend on either."""
+import json
+
+import numpy as np
+import pytest
+import torch
+
+import paper_1704_02770_amd as qk
+from gpu_util import max_rel, neel_row, say, to_host
+from oracle import exact as OX
+from oracle import hamiltonian as OH
+from oracle import model as OM
+from workloads import BETA_GOLDEN, phases
+
+pytestmark = pytest.mark.gpu
+
+
+def _ws(L, Bn, dtype, h=2.0, seed=0, m=30):
+    b = qk.qk_basis_build(L, L // 2)
+    phi = phases(Bn, seed)
+    hf = np.stack([OM.fields(L, h, BETA_GOLDEN, p) for p in phi])
+    H = qk.qk_ham_create(b, 1.0, 1.0, True, hf)
+    k = qk.qk_krylov_create(H, m, dtype)
+    D = qk.qk_basis_dim(b)
+    r0 = neel_row(L)
+    psi = torch.zeros((D, Bn) if Bn > 1 else D, dtype=dtype, device="cuda")
+    psi[r0] = 1.0
+    return dict(b=b, H=H, k=k, psi=psi, r0=r0, hf=hf, L=L, B=Bn)
+
+
+def _single_run(w, steps, dt):
+    """Same workspace stepped one call at a time; P after every step."""
+    psi = w["psi"].clone()
+    P = torch.empty((steps, w["B"]), dtype=torch.float64, device="cuda")
+    for s in range(steps):
+        qk.qk_krylov_expm_step(w["k"], psi, dt)
+        qk.qk_return_prob(w["b"], psi, r0=w["r0"], batch=w["B"], out=P[s])
+    return to_host(P), psi
+
+
+@pytest.mark.parametrize("dtype", [torch.complex128, torch.complex64])
+def test_batch_graph_equals_eager_and_single(dtype):
+    ws = [_ws(12, 4, dtype, seed=1), _ws(10, 1, dtype, seed=2), _ws(14, 1, dtype, seed=3)]
+    steps, dt = 8, 0.1
+    refs = []
+    for w in ws:
+        P, _ = _single_run(w, steps, dt)
+        refs.append(P)
+    ref = np.concatenate(refs, axis=1)
+    tol = 1e-12 if dtype == torch.complex128 else 1e-6
+    for use_graph in (False, True):
+        psis = [w["psi"].clone() for w in ws]
+        bt = qk.qk_batch_create([w["k"] for w in ws], psis, [w["r0"] for w in ws])
+        assert qk.qk_batch_items(bt) == 6
+        say("batch", dtype, "graph" if use_graph else "eager")
+        P = to_host(qk.qk_batch_run(bt, dt, steps, use_graph=use_graph))
+        assert np.max(np.abs(P - ref)) < tol
+
+
+def test_graph_replays_with_eager_work_between():
+    dtype = torch.complex128
+    ws = [_ws(12, 2, dtype, seed=4), _ws(16, 1, dtype, seed=5)]
+    dt = 0.1
+    ref, _ = zip(*[_single_run(w, 12, dt) for w in ws])
+    ref = np.concatenate(ref, axis=1)
+    psis = [w["psi"].clone() for w in ws]
+    bt = qk.qk_batch_create([w["k"] for w in ws], psis, [w["r0"] for w in ws])
+    out = torch.empty((4, 3), dtype=torch.float64, device="cuda")
+    got = []
+    for rep in range(3):
+        say("graph replay", rep)
+        qk.qk_batch_run(bt, dt, 4, use_graph=True, out=out)
+        got.append(to_host(out).copy())
+        # eager work of the program between replays
+        scratch = torch.randn(1000, device="cuda").sum().item()
+        assert np.isfinite(scratch)
+    got = np.concatenate(got, axis=0)
+    assert np.max(np.abs(got - ref)) < 1e-12
+
+
+def test_mixed_lengths_fp32_vs_fp64_workload():
+    # 64 phases at L=20 plus single chains L=16, 18, 20, 22 (h=2, m=30,
+    # dt=0.1), complex64 vectors with FP64 Lanczos coefficients, against the
+    # same problems in complex128; the FP32 error is reported and bounded.
+    spec = [(20, 64), (16, 1), (18, 1), (20, 1), (22, 1)]
+    steps, dt = 20, 0.1
+    res = {}
+    for dtype in (torch.complex128, torch.complex64):
+        ws = [_ws(L, Bn, dtype, seed=i) for i, (L, Bn) in enumerate(spec)]
+        bt = qk.qk_batch_create([w["k"] for w in ws], [w["psi"] for w in ws], [w["r0"] for w in ws])
+        say("mixed lengths", dtype)
+        res[dtype] = to_host(qk.qk_batch_run(bt, dt, steps, use_graph=True))
+    err = np.max(np.abs(res[torch.complex64] - res[torch.complex128]))
+    say("complex64 vs complex128 max |dP| =", err)
+    assert res[torch.complex128].shape == (steps, 68)
+    assert err < 1e-5
+    # the L=16 member against the dense oracle
+    w16 = _ws(16, 1, torch.complex128, seed=1)
+    Hd = OH.build_dense(16, 8, True, 1.0, 1.0, w16["hf"][0])
+    F = OX.survival_probability(Hd, w16["r0"], dt * np.arange(1, steps + 1))
+    assert np.max(np.abs(res[torch.complex128][:, 64] - F)) < 1e-10
+
+
+@pytest.mark.parametrize("L,Bn,dtype", [(20, 1, torch.complex128), (20, 4, torch.complex64), (22, 1, torch.complex64)])
+def test_autotune_keeps_results_and_caches(tmp_path, L, Bn, dtype):
+    w = _ws(L, Bn, dtype, seed=7)
+    P0, psi0 = _single_run(w, 5, 0.1)
+    cache = tmp_path / "tune.json"
+    say("autotune", L, Bn, dtype)
+    shape = qk.qk_krylov_autotune(w["k"], 0.1, cache)
+    assert qk.qk_krylov_get_shape(w["k"]) == shape
+    data = json.loads(cache.read_text())
+    assert len(data) == 1 and list(data.values())[0]["threads"] == shape["threads"]
+    P1, psi1 = _single_run(w, 5, 0.1)
+    tol = 1e-13 if dtype == torch.complex128 else 2e-6
+    assert np.max(np.abs(P1 - P0)) < tol
+    assert max_rel(to_host(psi1), to_host(psi0)) < (1e-12 if dtype == torch.complex128 else 1e-5)
+    # a second workspace of the same shape reads the cache
+    w2 = _ws(L, Bn, dtype, seed=8)
+    assert qk.qk_krylov_autotune(w2["k"], 0.1, cache) == shape
+    # an explicit shape, then invalid ones
+    qk.qk_krylov_set_shape(w2["k"], threads=64 if Bn <= 64 else 0, blocks_per_cu=4)
+    with pytest.raises(qk.QkError):
+        qk.qk_krylov_set_shape(w2["k"], threads=512)
+    with pytest.raises(qk.QkError):
+        qk.qk_krylov_set_shape(w2["k"], blocks_per_cu=-1)

@@ -285,3 +285,27 @@ def test_blocked_complex64_vs_complex128():
             qk.qk_return_prob(b, psi, r0=r0, out=P[s:s + 1])
         Ps.append(to_host(P))
     assert np.max(np.abs(Ps[0] - Ps[1])) < 1e-5
+
+
+@pytest.mark.parametrize("L", [14, 20])
+def test_local_reorthogonalisation(L):
+    # reorth=1 removes the rounding component along v_{j-1}; in FP64 the
+    # result is unchanged to rounding, in FP32 it stays within 1e-5 of the oracle
+    b, H, hf = _problem(L, True)
+    r0 = neel_row(L)
+    out = {}
+    for dtype, ro in [(torch.complex128, 0), (torch.complex128, 1), (torch.complex64, 1)]:
+        psi, _ = _neel_psi(b, L, dtype)
+        k = qk.qk_krylov_create(H, 30, dtype, reorth=ro)
+        P = torch.empty(20, dtype=torch.float64, device="cuda")
+        say("reorth", L, dtype, ro)
+        for s in range(20):
+            qk.qk_krylov_expm_step(k, psi, 0.1)
+            qk.qk_return_prob(b, psi, r0=r0, out=P[s:s + 1])
+        out[(dtype, ro)] = to_host(P)
+    assert np.max(np.abs(out[(torch.complex128, 0)] - out[(torch.complex128, 1)])) < 1e-12
+    assert np.max(np.abs(out[(torch.complex64, 1)] - out[(torch.complex128, 0)])) < 1e-5
+    if L == 14:
+        Hd = OH.build_dense(L, L // 2, True, 1.0, 1.0, hf)
+        F = OX.survival_probability(Hd, r0, 0.1 * np.arange(1, 21))
+        assert np.max(np.abs(out[(torch.complex128, 1)] - F)) < 1e-10
