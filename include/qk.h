@@ -271,6 +271,24 @@ qk_status qk_batch_run(qk_batch* b, double dt, int32_t n_steps, int32_t use_grap
 
 void qk_batch_destroy(qk_batch* b);
 
+/* ------------------------------------------------------------- gradient */
+/*
+ * Survival probability F(T) = |<e_r0| exp(-iHT) |e_r0>|^2 (Sec. 4) and its
+ * derivative dF/dh_i with respect to every on-site field h_i of Eq. (1),
+ * i = 1..L (dFdh_host[i-1]), by the adjoint method: n_steps Krylov steps of
+ * dt = T / n_steps forward with every state kept as a checkpoint, then the
+ * costate lambda(s) = exp(+iH(T-s)) e_r0 propagated backward by Krylov steps
+ * of -dt; inside each step the time integral of <lambda|Z_i|psi> is taken
+ * between the two Krylov bases by Gauss-Legendre quadrature of the projected
+ * propagators.  Uses the workspace's Hamiltonian, Krylov dimension and launch
+ * shape, and allocates (n_steps + 1) state vectors of checkpoints plus one
+ * more workspace for the duration of the call.  Requires dtype QK_C128,
+ * batch 1 and m <= 32 (else QK_EUNSUPPORTED).  Synchronous; F_host and
+ * dFdh_host are host pointers.
+ */
+qk_status qk_grad_return_prob(qk_krylov* k, int64_t r0, double T, int32_t n_steps, double* F_host,
+                              double* dFdh_host, void* stream);
+
 /* ----------------------------------------------------------- observable */
 /*
  * Survival (return) probability of Sec. 4, F = |<psi0|psi>|^2, for every

@@ -151,7 +151,9 @@ def qk_ham_create(b: Basis, jxy: float, jz: float, pbc: bool, fields, mode: int 
     out = C.c_void_p()
     _check(lib.qk_ham_create(b.ptr, C.byref(p), f.ctypes.data_as(C.POINTER(C.c_double)), f.shape[0],
                              _stream(stream), C.byref(out)), "qk_ham_create")
-    return Ham(out, keep=(b,))
+    H = Ham(out, keep=(b,))
+    H.L = qk_basis_shape(b)[0]
+    return H
 
 
 def qk_ham_set_fields(H: Ham, fields, stream=None) -> None:
@@ -297,6 +299,16 @@ def qk_batch_run(b: Batch, dt: float, n_steps: int, use_graph: bool = True, out:
     _check(lib.qk_batch_run(b.ptr, float(dt), int(n_steps), int(bool(use_graph)), _dptr(out), _stream(stream)),
            "qk_batch_run")
     return out
+
+
+def qk_grad_return_prob(k: Krylov, r0: int, T: float, n_steps: int, stream=None):
+    """(F(T), dF/dh as a numpy array of length L) for the initial basis state r0."""
+    L = k.H.L
+    F = C.c_double()
+    g = np.zeros(L)
+    _check(lib.qk_grad_return_prob(k.ptr, int(r0), float(T), int(n_steps), C.byref(F),
+                                   g.ctypes.data_as(C.POINTER(C.c_double)), _stream(stream)), "qk_grad_return_prob")
+    return F.value, g
 
 
 def qk_return_prob(b: Basis, psi: torch.Tensor, r0: int = -1, psi0: torch.Tensor | None = None,

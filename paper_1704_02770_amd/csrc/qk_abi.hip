@@ -496,6 +496,23 @@ QK_API qk_status qk_batch_run(qk_batch* b, double dt, int32_t n_steps, int32_t u
 
 QK_API void qk_batch_destroy(qk_batch* b) { batch_destroy(b); }
 
+// ----------------------------------------------------------------- gradient
+QK_API qk_status qk_grad_return_prob(qk_krylov* k, int64_t r0, double T, int32_t n_steps, double* F_host,
+                                     double* dFdh_host, void* stream) {
+  g_err.clear();
+  if (!k || !F_host || !dFdh_host) return inval("NULL pointer");
+  if (!std::isfinite(T) || T < 0.0) return inval("T must be finite and >= 0");
+  if (n_steps < 1) return inval("n_steps must be >= 1");
+  if (r0 < 0 || r0 >= k->D) return inval("r0 out of range");
+  if (k->dtype != QK_C128 || k->batch != 1 || k->m > 32) {
+    set_error("the gradient needs a complex128 workspace with batch 1 and m <= 32");
+    return QK_EUNSUPPORTED;
+  }
+  qk_status st = check_device(k->device);
+  if (st != QK_OK) return st;
+  return grad_return_prob(k, r0, T, n_steps, F_host, dFdh_host, (hipStream_t)stream);
+}
+
 // -------------------------------------------------------------- observable
 QK_API qk_status qk_return_prob(const qk_basis* b, int64_t r0, const void* psi0, const void* psi, int32_t dtype,
                                 int32_t batch, double* P_device, void* stream) {

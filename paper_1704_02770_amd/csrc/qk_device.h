@@ -238,6 +238,58 @@ constexpr int kQA = 4;
 
 
 
+// (exp(-i tau T) e_1)_i in lane i of one wavefront, for the real symmetric
+// tridiagonal T with diagonal al (lane i), coupling be to component i+1 and bl
+// to component i-1 (zero outside the used dimension; `on` marks used lanes).
+// T is shifted by the centre mu of its Gershgorin interval, the time is cut
+// into substeps with |tau_s| * radius <= 1/2, and each substep sums the Taylor
+// series of the exponential applied to the vector until the terms fall below
+// 1e-18 of the sum; the phase exp(-i tau mu) is applied at the end.  All 64
+// lanes must call it (it uses cross-lane shuffles).
+__device__ __forceinline__ void tri_expm_e1(double al, double be, double bl, bool on, int i, double tau, double& er,
+                                            double& ei) {
+  double lo = on ? al - be - bl : INFINITY, hi = on ? al + be + bl : -INFINITY;
+  for (int s = 32; s > 0; s >>= 1) {
+    lo = fmin(lo, __shfl_xor(lo, s));
+    hi = fmax(hi, __shfl_xor(hi, s));
+  }
+  const double mu_shift = 0.5 * (lo + hi);
+  const double radius = 0.5 * (hi - lo);
+  const double ad = on ? al - mu_shift : 0.0;
+  // bounded substep count (a non-finite or huge norm cannot stall the wave)
+  const double nsd = ceil(fabs(tau) * radius / 0.5);
+  const int nsub = (nsd >= 1.0 && nsd <= 100000.0) ? (int)nsd : (nsd > 100000.0 ? 100000 : 1);
+  const double ts = tau / nsub;
+  double vr = (i == 0) ? 1.0 : 0.0, vi = 0.0;
+  for (int sub = 0; sub < nsub; ++sub) {
+    double sr = vr, si = vi, tr = vr, ti = vi;
+    for (int k = 1; k <= 40; ++k) {
+      // t <- (-i ts / k) (T - mu) t
+      const double up_r = __shfl_up(tr, 1), up_i = __shfl_up(ti, 1);
+      const double dn_r = __shfl_down(tr, 1), dn_i = __shfl_down(ti, 1);
+      double yr = ad * tr + (i > 0 ? bl * up_r : 0.0) + (i < 63 ? be * dn_r : 0.0);
+      double yi = ad * ti + (i > 0 ? bl * up_i : 0.0) + (i < 63 ? be * dn_i : 0.0);
+      if (!on) yr = yi = 0.0;
+      const double f = ts / k;
+      tr = f * yi;    // (-i f) (yr + i yi) = f yi - i f yr
+      ti = -f * yr;
+      sr += tr;
+      si += ti;
+      double tn = fabs(tr) + fabs(ti), sn = fabs(sr) + fabs(si);
+      for (int s = 32; s > 0; s >>= 1) {
+        tn = fmax(tn, __shfl_xor(tn, s));
+        sn = fmax(sn, __shfl_xor(sn, s));
+      }
+      if (tn <= 1e-18 * sn) break;
+    }
+    vr = sr;
+    vi = si;
+  }
+  const double cr = cos(tau * mu_shift), ci = -sin(tau * mu_shift);
+  er = vr * cr - vi * ci;
+  ei = vr * ci + vi * cr;
+}
+
 // Scalars of the H-pass of Lanczos iteration j for every batch column b,
 // from the update pass of iteration j-1 (its partial sums |u_j|^2):
 //   sa[b] = sigma_j, sb[b] = beta_{j-1} sigma_{j-1}, act[b] = column still running.

@@ -1,0 +1,294 @@
+// Derivative of the survival probability F(T) = |A(T)|^2, A(T) =
+// <psi0| exp(-iHT) |psi0> (Sec. 4) with respect to every on-site field h_i of
+// Eq. (1), by the adjoint (costate) method on top of the Krylov steps.
+//
+// H depends on h_i through h_i Z_i, Z_i = diag(bit_i - 1/2), so
+//     dA/dh_i = -i * integral_0^T <lambda(s)| Z_i |psi(s)> ds,
+//     lambda(s) = exp(+iH(T-s)) psi0,
+// and dF/dh_i = 2 Re(conj(A) dA/dh_i).  With time steps t_k = k dt:
+//   * the forward pass stores psi_k (checkpoints);
+//   * the costate runs backward, lambda_K = psi0 and lambda_k =
+//     exp(+iH dt) lambda_{k+1}, i.e. a Krylov step with time step -dt;
+//   * inside step k, psi(t_k + tau) = V p(tau) with p(tau) = exp(-i tau T) ||psi_k|| e_1
+//     (the Krylov basis V of psi_k, rebuilt from the checkpoint) and
+//     lambda(t_k + tau) = W q(tau) with q(tau) = exp(+i (dt - tau) T') ||lambda_{k+1}|| e_1
+//     (the basis W of the backward step), so
+//         integral over the step of <lambda|Z_i|psi>
+//           = sum_r z_i(r) sum_{c,d} conj(W_rc) C_cd V_rd,
+//         C_cd = integral_0^dt conj(q_c(tau)) p_d(tau) dtau.
+//     C is a small m x m matrix, integrated by Gauss-Legendre quadrature of
+//     the m-dimensional propagators (an entire function of tau, so the rule
+//     converges to rounding error), and the row sum is one pass over the two
+//     Krylov bases.
+#include <cmath>
+#include <new>
+#include <vector>
+
+#include "qk_device.h"
+
+namespace qk {
+
+constexpr int kGradMaxM = 32;      // Krylov dimension of the gradient (register-held basis rows)
+constexpr int kGaussNodes = 24;
+
+struct GaussRule {
+  double x[kGaussNodes];   // nodes on [0, 1]
+  double w[kGaussNodes];   // weights on [0, 1]
+};
+
+// Gauss-Legendre nodes and weights by Newton's method on the Legendre
+// polynomial P_n (three-term recurrence), mapped from [-1, 1] to [0, 1].
+static GaussRule gauss_legendre() {
+  GaussRule g{};
+  const int n = kGaussNodes;
+  for (int i = 0; i < n; ++i) {
+    double x = cos(M_PI * (i + 0.75) / (n + 0.5));
+    double dp = 1.0;
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = x;
+      for (int j = 2; j <= n; ++j) {
+        const double p2 = ((2.0 * j - 1.0) * x * p1 - (j - 1.0) * p0) / j;
+        p0 = p1;
+        p1 = p2;
+      }
+      dp = n * (x * p1 - p0) / (x * x - 1.0);
+      const double dx = p1 / dp;
+      x -= dx;
+      if (fabs(dx) < 1e-16) break;
+    }
+    g.x[i] = 0.5 * (x + 1.0);
+    g.w[i] = 1.0 / ((1.0 - x * x) * dp * dp);   // 2 / ((1-x^2) P_n'(x)^2) times 1/2
+  }
+  return g;
+}
+
+// C~_cd = sigma'_c sigma_d C_cd for the stored (unnormalised) basis vectors,
+// C = integral_0^dt conj(q(tau)) p(tau)^T dtau.  One wavefront; lane i owns
+// component i of p and q; C is accumulated in LDS.
+__global__ void __launch_bounds__(64)
+k_grad_coeffs(KState fw, KState bw, double dt, GaussRule gr, double* __restrict__ Ct) {
+  __shared__ double Cr[kGradMaxM][kGradMaxM], Ci[kGradMaxM][kGradMaxM];
+  __shared__ double Pr[64], Pi[64];
+  const int i = threadIdx.x;
+  const int muf = fw.mused[0], mub = bw.mused[0];
+  for (int c = 0; c < kGradMaxM; ++c)
+    if (i < kGradMaxM) {
+      Cr[c][i] = 0.0;
+      Ci[c][i] = 0.0;
+    }
+  __syncthreads();
+  if (fw.status[0] != QK_OK || bw.status[0] != QK_OK || muf <= 0 || mub <= 0) {
+    for (int c = 0; c < kGradMaxM; ++c)
+      if (i < kGradMaxM) {
+        Ct[2 * (c * kGradMaxM + i)] = 0.0;
+        Ct[2 * (c * kGradMaxM + i) + 1] = 0.0;
+      }
+    return;
+  }
+  const bool onf = i < muf, onb = i < mub;
+  const double alf = onf ? fw.alpha[i] : 0.0, bef = (i + 1 < muf) ? fw.beta[i] : 0.0;
+  const double blf = (onf && i > 0) ? fw.beta[i - 1] : 0.0;
+  const double alb = onb ? bw.alpha[i] : 0.0, beb = (i + 1 < mub) ? bw.beta[i] : 0.0;
+  const double blb = (onb && i > 0) ? bw.beta[i - 1] : 0.0;
+  const double n0f = fw.n0[0], n0b = bw.n0[0];
+  for (int q = 0; q < kGaussNodes; ++q) {
+    const double tau = dt * gr.x[q], wq = dt * gr.w[q];
+    double pr, pi, qr, qi;
+    tri_expm_e1(alf, bef, blf, onf, i, tau, pr, pi);           // exp(-i tau T) e_1
+    tri_expm_e1(alb, beb, blb, onb, i, -(dt - tau), qr, qi);   // exp(+i (dt - tau) T') e_1
+    Pr[i] = n0f * pr;
+    Pi[i] = n0f * pi;
+    qr *= n0b;
+    qi *= n0b;
+    __syncthreads();
+    if (i < mub && i < kGradMaxM)
+      for (int d = 0; d < muf && d < kGradMaxM; ++d) {
+        // conj(q_i) p_d
+        Cr[i][d] += wq * (qr * Pr[d] + qi * Pi[d]);
+        Ci[i][d] += wq * (qr * Pi[d] - qi * Pr[d]);
+      }
+    __syncthreads();
+  }
+  if (i < kGradMaxM)
+    for (int c = 0; c < kGradMaxM; ++c) {
+      const double sc = (c < mub && i < muf) ? bw.sigma[c] * fw.sigma[i] : 0.0;
+      Ct[2 * (c * kGradMaxM + i)] = sc * Cr[c][i];
+      Ct[2 * (c * kGradMaxM + i) + 1] = sc * Ci[c][i];
+    }
+}
+
+// Per row r: s_r = sum_c conj(u'_c[r]) sum_d C~_cd u_d[r] (u_0 = psi_k,
+// u'_0 = lambda_{k+1}, further vectors from the workspace slots).  Every tile
+// of 256 rows puts its s_r and states in LDS, and thread q < 2(L_max+1) adds
+// component q&1 of s_r over the tile's rows whose state has bit q>>1 set
+// (q>>1 == L_max: all rows), so each block writes 2(L_max+1) partial sums.
+constexpr int kGradQ = 2 * (QK_MAX_L + 1);
+
+__global__ void __launch_bounds__(256)
+k_grad_contract(const uint32_t* __restrict__ states, uint32_t D, int L, const double2* __restrict__ psi_k,
+                const double2* __restrict__ Uf, const double2* __restrict__ lam, const double2* __restrict__ Ub,
+                KState fw, KState bw, const double* __restrict__ Ct, double* __restrict__ part) {
+  __shared__ double2 C[kGradMaxM * kGradMaxM];
+  __shared__ double2 sbuf[256];
+  __shared__ uint32_t sst[256];
+  const int tid = threadIdx.x;
+  for (int i = tid; i < kGradMaxM * kGradMaxM; i += blockDim.x) C[i] = make_double2(Ct[2 * i], Ct[2 * i + 1]);
+  __syncthreads();
+  const int muf = fw.mused[0] < kGradMaxM ? fw.mused[0] : kGradMaxM;
+  const int mub = bw.mused[0] < kGradMaxM ? bw.mused[0] : kGradMaxM;
+  const size_t stride = D;
+  const int site = tid >> 1, comp = tid & 1;
+  double acc = 0.0;
+  for (uint32_t base = blockIdx.x * 256u; base < D; base += gridDim.x * 256u) {
+    const uint32_t r = base + tid;
+    double sr = 0.0, si = 0.0;
+    uint32_t stt = 0;
+    if (r < D) {
+      double2 u[kGradMaxM];
+#pragma unroll
+      for (int d = 0; d < kGradMaxM; ++d)
+        u[d] = (d < muf) ? (d == 0 ? psi_k[r] : Uf[(size_t)(d - 1) * stride + r]) : make_double2(0.0, 0.0);
+      for (int c = 0; c < mub; ++c) {
+        const double2 w = (c == 0) ? lam[r] : Ub[(size_t)(c - 1) * stride + r];
+        double tr = 0.0, ti = 0.0;
+#pragma unroll
+        for (int d = 0; d < kGradMaxM; ++d) {
+          const double2 cc = C[c * kGradMaxM + d];
+          tr += cc.x * u[d].x - cc.y * u[d].y;
+          ti += cc.x * u[d].y + cc.y * u[d].x;
+        }
+        sr += w.x * tr + w.y * ti;   // conj(w) t
+        si += w.x * ti - w.y * tr;
+      }
+      stt = states[r];
+    }
+    sbuf[tid] = make_double2(sr, si);
+    sst[tid] = stt;
+    __syncthreads();
+    if (tid < kGradQ && (site < L || site == QK_MAX_L)) {
+      for (int q = 0; q < 256; ++q) {
+        const bool on = site == QK_MAX_L || ((sst[q] >> site) & 1u);
+        const double v = comp ? sbuf[q].y : sbuf[q].x;
+        acc += on ? v : 0.0;
+      }
+    }
+    __syncthreads();
+  }
+  if (tid < kGradQ) part[(size_t)blockIdx.x * kGradQ + tid] = acc;
+}
+
+// dA[i] += -i (S_i - S_total / 2) summed over the blocks in a fixed order.
+__global__ void k_grad_accum(const double* __restrict__ part, int G, int L, double* __restrict__ dA) {
+  const int q = threadIdx.x;   // kGradQ threads or more
+  __shared__ double tot[kGradQ];
+  if (q < kGradQ) {
+    double t = 0.0;
+    for (int g = 0; g < G; ++g) t += part[(size_t)g * kGradQ + q];
+    tot[q] = t;
+  }
+  __syncthreads();
+  if (q < L) {
+    const double gr = tot[2 * q] - 0.5 * tot[2 * QK_MAX_L];
+    const double gi = tot[2 * q + 1] - 0.5 * tot[2 * QK_MAX_L + 1];
+    dA[2 * q] += gi;       // -i (gr + i gi) = gi - i gr
+    dA[2 * q + 1] -= gr;
+  }
+}
+
+__global__ void k_basis_vector(double2* __restrict__ v, uint32_t D, uint32_t r0) {
+  const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r < D) v[r] = make_double2(r == r0 ? 1.0 : 0.0, 0.0);
+}
+
+qk_status grad_return_prob(qk_krylov* k, int64_t r0, double T, int n_steps, double* F, double* dFdh,
+                           hipStream_t s) {
+  const qk_ham* H = k->H;
+  const uint32_t D = (uint32_t)k->D;
+  const int L = H->basis->L;
+  const double dt = T / n_steps;
+  const size_t vbytes = sizeof(double2) * (size_t)D;
+  const int G = 1024;
+  qk_krylov* kb = nullptr;   // workspace of the backward steps
+  double2* ck = nullptr;     // checkpoints psi_0 .. psi_K
+  double2* lam = nullptr;    // lambda_k
+  double2* lamp = nullptr;   // lambda_{k+1}
+  double *Ct = nullptr, *part = nullptr, *dA = nullptr;
+  qk_status st = qk_krylov_create(H, k->m, QK_C128, k->reorth, &kb);
+  if (st != QK_OK) return st;
+  kb->threads = k->threads;
+  kb->blocks_per_cu = k->blocks_per_cu;
+  kb->blocked_wgs = k->blocked_wgs;
+  kb->grid = k->grid;
+  hipError_t e = hipMalloc((void**)&ck, vbytes * (size_t)(n_steps + 1));
+  if (e == hipSuccess) e = hipMalloc((void**)&lam, vbytes);
+  if (e == hipSuccess) e = hipMalloc((void**)&lamp, vbytes);
+  if (e == hipSuccess) e = hipMalloc((void**)&Ct, sizeof(double) * 2 * kGradMaxM * kGradMaxM);
+  if (e == hipSuccess) e = hipMalloc((void**)&part, sizeof(double) * (size_t)G * kGradQ);
+  if (e == hipSuccess) e = hipMalloc((void**)&dA, sizeof(double) * 2 * L);
+  if (e == hipSuccess) e = hipMemsetAsync(dA, 0, sizeof(double) * 2 * L, s);
+  const KState fw = make_kstate(k), bw = make_kstate(kb);
+  const GaussRule gr = gauss_legendre();
+  auto chk = [&](const char* what) {
+    if (st == QK_OK && e == hipSuccess) e = hipGetLastError();
+    if (st == QK_OK && e != hipSuccess) st = hip_fail(e, what);
+  };
+  chk("qk_grad_return_prob allocation");
+  // forward pass with checkpoints
+  if (st == QK_OK) {
+    hipLaunchKernelGGL(k_basis_vector, dim3((D + 255) / 256), dim3(256), 0, s, ck, D, (uint32_t)r0);
+    chk("k_basis_vector");
+  }
+  for (int t = 0; t < n_steps && st == QK_OK; ++t) {
+    e = hipMemcpyAsync(ck + (size_t)(t + 1) * D, ck + (size_t)t * D, vbytes, hipMemcpyDeviceToDevice, s);
+    chk("checkpoint copy");
+    if (st == QK_OK) st = launch_krylov_step(k, ck + (size_t)(t + 1) * D, dt, s, true);
+  }
+  // backward pass of the costate
+  if (st == QK_OK) {
+    hipLaunchKernelGGL(k_basis_vector, dim3((D + 255) / 256), dim3(256), 0, s, lam, D, (uint32_t)r0);
+    chk("k_basis_vector");
+  }
+  for (int t = n_steps - 1; t >= 0 && st == QK_OK; --t) {
+    // Krylov basis of psi_t (the checkpoint is left unchanged)
+    st = launch_krylov_step(k, ck + (size_t)t * D, dt, s, false);
+    if (st != QK_OK) break;
+    // lambda_t = exp(+iH dt) lambda_{t+1}; lamp keeps lambda_{t+1}
+    e = hipMemcpyAsync(lamp, lam, vbytes, hipMemcpyDeviceToDevice, s);
+    chk("costate copy");
+    if (st == QK_OK) st = launch_krylov_step(kb, lam, -dt, s, true);
+    if (st != QK_OK) break;
+    hipLaunchKernelGGL(k_grad_coeffs, dim3(1), dim3(64), 0, s, fw, bw, dt, gr, Ct);
+    chk("k_grad_coeffs");
+    if (st != QK_OK) break;
+    hipLaunchKernelGGL(k_grad_contract, dim3(G), dim3(256), 0, s, H->basis->d_states, D, L,
+                       (const double2*)(ck + (size_t)t * D), (const double2*)k->d_U, (const double2*)lamp,
+                       (const double2*)kb->d_U, fw, bw, Ct, part);
+    chk("k_grad_contract");
+    if (st != QK_OK) break;
+    hipLaunchKernelGGL(k_grad_accum, dim3(1), dim3(128), 0, s, part, G, L, dA);
+    chk("k_grad_accum");
+  }
+  std::vector<double> dAh(2 * L);
+  double2 A = make_double2(0.0, 0.0);
+  if (st == QK_OK) {
+    e = hipMemcpyAsync(&A, ck + (size_t)n_steps * D + r0, sizeof(double2), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(dAh.data(), dA, sizeof(double) * 2 * L, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) st = hip_fail(e, "qk_grad_return_prob readback");
+  }
+  if (st == QK_OK) {
+    *F = A.x * A.x + A.y * A.y;
+    for (int i = 0; i < L; ++i) dFdh[i] = 2.0 * (A.x * dAh[2 * i] + A.y * dAh[2 * i + 1]);
+  }
+  hipStreamSynchronize(s);
+  hipFree(ck);
+  hipFree(lam);
+  hipFree(lamp);
+  hipFree(Ct);
+  hipFree(part);
+  hipFree(dA);
+  qk_krylov_destroy(kb);
+  return st;
+}
+
+}  // namespace qk

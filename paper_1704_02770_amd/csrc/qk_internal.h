@@ -129,7 +129,8 @@ qk_status launch_blocked_build(qk_ham* H, hipStream_t s);
 qk_status launch_blocked_apply(const qk_ham* H, const void* x, void* y, int dtype, hipStream_t s);
 qk_status launch_blocked_fields(qk_ham* H, hipStream_t s);
 bool blocked_usable(const qk_ham* H, int dtype);
-qk_status launch_krylov_step(qk_krylov* k, void* psi, double dt, hipStream_t s);
+qk_status launch_krylov_step(qk_krylov* k, void* psi, double dt, hipStream_t s, bool combine = true);
+qk_status grad_return_prob(qk_krylov* k, int64_t r0, double T, int n_steps, double* F, double* dFdh, hipStream_t s);
 qk_status profile_mark(qk_krylov* k, int kind, bool begin, hipStream_t s);
 int stream_grid(uint64_t rows, int B, int threads, int blocks_per_cu);
 int krylov_threads(const qk_krylov* k);

@@ -224,12 +224,9 @@ k_lanczos_B(const typename Cx<T>::V* __restrict__ uj, const typename Cx<T>::V* _
 }
 
 // ------------------------------------------ projected exponential (1 wave)
-// c = exp(-i tau T) e_1 for the real symmetric tridiagonal T = tridiag(beta,
-// alpha, beta) of the Lanczos recurrence.  Lane i owns component i.  T is
-// shifted by the centre of its Gershgorin interval, the step is cut into
-// substeps with ||tau_s (T - mu)|| <= 1/2, and each substep sums the Taylor
-// series of the exponential applied to the vector until the terms fall below
-// 1e-18 of the sum.
+// c = exp(-i tau T) e_1 for the tridiagonal T of the Lanczos recurrence
+// (tri_expm_e1), times ||psi|| and the stored-vector scales, plus the
+// a-posteriori error estimate ||psi|| beta_m |c_m|.
 __global__ void __launch_bounds__(64)
 k_small_expm(KState st, int m, int B, double tau, const double* __restrict__ partB, int Gp) {
   const int b = blockIdx.x;
@@ -259,47 +256,8 @@ k_small_expm(KState st, int m, int B, double tau, const double* __restrict__ par
   const double al = on ? st.alpha[i * B + b] : 0.0;
   const double be = (i + 1 < mu) ? st.beta[i * B + b] : 0.0;     // couples i and i+1
   const double bl = (on && i > 0) ? st.beta[(i - 1) * B + b] : 0.0;
-  // Gershgorin interval of T
-  double lo = on ? al - be - bl : INFINITY, hi = on ? al + be + bl : -INFINITY;
-  for (int s = 32; s > 0; s >>= 1) {
-    lo = fmin(lo, __shfl_xor(lo, s));
-    hi = fmax(hi, __shfl_xor(hi, s));
-  }
-  const double mu_shift = 0.5 * (lo + hi);
-  const double radius = 0.5 * (hi - lo);
-  const double ad = on ? al - mu_shift : 0.0;
-  // bounded substep count (a non-finite or huge norm cannot stall the wave)
-  const double nsd = ceil(fabs(tau) * radius / 0.5);
-  const int nsub = (nsd >= 1.0 && nsd <= 100000.0) ? (int)nsd : (nsd > 100000.0 ? 100000 : 1);
-  const double ts = tau / nsub;
-  double vr = (i == 0) ? 1.0 : 0.0, vi = 0.0;
-  for (int sub = 0; sub < nsub; ++sub) {
-    double sr = vr, si = vi, tr = vr, ti = vi;
-    for (int k = 1; k <= 40; ++k) {
-      // t <- (-i ts / k) (T - mu) t
-      const double up_r = __shfl_up(tr, 1), up_i = __shfl_up(ti, 1);
-      const double dn_r = __shfl_down(tr, 1), dn_i = __shfl_down(ti, 1);
-      double yr = ad * tr + (i > 0 ? bl * up_r : 0.0) + (i < 63 ? be * dn_r : 0.0);
-      double yi = ad * ti + (i > 0 ? bl * up_i : 0.0) + (i < 63 ? be * dn_i : 0.0);
-      if (!on) yr = yi = 0.0;
-      const double f = ts / k;
-      tr = f * yi;    // (-i f) (yr + i yi) = f yi - i f yr
-      ti = -f * yr;
-      sr += tr;
-      si += ti;
-      double tn = fabs(tr) + fabs(ti), sn = fabs(sr) + fabs(si);
-      for (int s = 32; s > 0; s >>= 1) {
-        tn = fmax(tn, __shfl_xor(tn, s));
-        sn = fmax(sn, __shfl_xor(sn, s));
-      }
-      if (tn <= 1e-18 * sn) break;
-    }
-    vr = sr;
-    vi = si;
-  }
-  // overall phase exp(-i tau mu)
-  const double cr = cos(tau * mu_shift), ci = -sin(tau * mu_shift);
-  const double er = vr * cr - vi * ci, ei = vr * ci + vi * cr;
+  double er, ei;
+  tri_expm_e1(al, be, bl, on, i, tau, er, ei);
   const double n0 = st.n0[b];
   if (i < m) {
     const double g = on ? n0 * st.sigma[i * B + b] : 0.0;
@@ -572,7 +530,7 @@ qk_status launch_ham_apply(const qk_ham* H, const void* x, void* y, int dtype, h
 }
 
 template <typename T>
-static qk_status krylov_step_t(qk_krylov* k, void* psi_v, double dt, hipStream_t s) {
+static qk_status krylov_step_t(qk_krylov* k, void* psi_v, double dt, hipStream_t s, bool combine) {
   using V = typename Cx<T>::V;
   const qk_ham* H = k->H;
   const ModelArgs a = model_args(H);
@@ -618,6 +576,7 @@ static qk_status krylov_step_t(qk_krylov* k, void* psi_v, double dt, hipStream_t
     QK_HIP(hipGetLastError());
     QK_MARK(QK_KERNEL_LANCZOS_UPDATE, false);
   }
+  if (!combine) return QK_OK;   // only the Krylov basis and coefficients were asked for
   QK_MARK(QK_KERNEL_SMALL_EXPM, true);
   hipLaunchKernelGGL(k_small_expm, dim3(B), dim3(64), 0, s, st, m, B, dt, k->d_partB, G);
   QK_HIP(hipGetLastError());
@@ -664,9 +623,9 @@ qk_status profile_collect(qk_krylov* k) {
   return QK_OK;
 }
 
-qk_status launch_krylov_step(qk_krylov* k, void* psi, double dt, hipStream_t s) {
-  if (k->dtype == QK_C128) return krylov_step_t<double>(k, psi, dt, s);
-  return krylov_step_t<float>(k, psi, dt, s);
+qk_status launch_krylov_step(qk_krylov* k, void* psi, double dt, hipStream_t s, bool combine) {
+  if (k->dtype == QK_C128) return krylov_step_t<double>(k, psi, dt, s, combine);
+  return krylov_step_t<float>(k, psi, dt, s, combine);
 }
 
 qk_status launch_return_prob(const qk_basis* b, int64_t r0, const void* psi0, const void* psi, int dtype, int B,
