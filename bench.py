@@ -32,7 +32,9 @@ sys.path.insert(0, ROOT)
 METRIC = "Krylov steps/sec + achieved HBM GB/s of H·v at L=28 Sz=0, plain FP64 vs batched/FP32"
 PEAK_HBM_GBS = 8000.0          # MI355X HBM3E, published
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_lanczos_h_L28.json")
-KERNEL_SRC = os.path.join(ROOT, "paper_1704_02770_amd", "csrc", "qk_kernels.hip")
+# sources of the blocked H-pass kernel; stored counter bytes are used only
+# while these files are unchanged
+KERNEL_SRCS = [os.path.join(ROOT, "paper_1704_02770_amd", "csrc", f) for f in ("qk_blocked.hip", "qk_device.h")]
 
 
 def log(*a):
@@ -57,8 +59,11 @@ def parse():
 
 
 def source_sha():
-    with open(KERNEL_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()
+    h = hashlib.sha256()
+    for p in KERNEL_SRCS:
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
 
 
 def run_form(qk, torch, b, fields, m, dt, dtype, steps, warmup, r0):
@@ -188,8 +193,8 @@ def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus > 1 or world > 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(see DESIGN.md for how the Krylov step would shard).", file=sys.stderr)
+        print("bench.py runs on one GPU only: the library has no multi-GPU path "
+              "(independent phases or a row-sharded L would each need their own process).", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch
@@ -241,7 +246,8 @@ def main():
             traffic = tr.get("bytes_per_launch")
     roof = dict(bound="hbm", achieved=round(achieved, 1), peak=PEAK_HBM_GBS, unit="GB/s",
                 frac=round(achieved / PEAK_HBM_GBS, 4), traffic=traffic,
-                kernel="k_lanczos_A<double,false> (H-pass: y = H u_j fused with the three-term update and dots)",
+                kernel=("H-pass of the Lanczos iteration, w = a H u_j - b u_{j-1} with its dot products "
+                        "(k_blk<double,11,true>, the blocked matrix-free kernel used for L >= 18)"),
                 bytes_per_launch_avg=bytes_h_step / m, ms_per_launch_avg=ms_h / max(n_h, 1))
 
     def form_summary(r, B, s):
