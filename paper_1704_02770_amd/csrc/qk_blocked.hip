@@ -16,10 +16,14 @@
 // One work-group processes one block at a time: it stages x of the block in
 // LDS (the low-bond neighbours are read from there), gathers the high-bond
 // neighbours as contiguous runs of the other blocks, and writes the block's
-// rows.  Work-groups are persistent; the top three bits of a select the XCD,
-// so the hops on the top high bonds connect blocks that different XCDs
-// process at the same time, and within an XCD the work-groups take blocks in
-// ascending order together.
+// rows.  Work-groups are persistent and sweep the blocks in ascending order
+// together, the whole grid one window of consecutive blocks at a time, so the
+// partners of the lower high bonds are being read by the whole chip at the
+// same moment and are served from the shared last-level cache.  Inside a
+// window, runs of `chunk` consecutive blocks go to one XCD, so the partners
+// across the lowest high bonds often share that XCD's L2.  The previous
+// Lanczos vector and the result are streamed with non-temporal accesses so
+// they do not evict the gathered x from the caches.
 #include <hipcub/hipcub.hpp>
 
 #include <cstdlib>
@@ -53,7 +57,8 @@ struct BlkArgs {
   const uint32_t* binom;                   // [33*33]
   const double* fields;                    // [L]
   uint32_t lo_base[18];                    // first index of each popcount group in lo_state
-  int xcd_first[kNumXcd + 1];              // block ranges per XCD
+  int nblk;                                // number of blocks
+  int chunk_log2;                          // log2 of the consecutive blocks per XCD in a window
 };
 
 constexpr int kBlkThreads = 256;
@@ -150,6 +155,23 @@ template <typename V>
 __device__ __forceinline__ void st32(V* __restrict__ base, uint32_t idx, V v) {
   *reinterpret_cast<V*>(reinterpret_cast<char*>(base) + idx * (uint32_t)sizeof(V)) = v;
 }
+// Non-temporal forms of the two above, for data read or written once per pass.
+template <typename V>
+__device__ __forceinline__ V ld32_stream(const V* __restrict__ base, uint32_t idx) {
+  using S = decltype(V{}.x);
+  typedef S E __attribute__((ext_vector_type(2)));
+  const E* p = reinterpret_cast<const E*>(reinterpret_cast<const char*>(base) + idx * (uint32_t)sizeof(V));
+  const E e = __builtin_nontemporal_load(p);
+  return V{e.x, e.y};
+}
+template <typename V>
+__device__ __forceinline__ void st32_stream(V* __restrict__ base, uint32_t idx, V v) {
+  using S = decltype(V{}.x);
+  typedef S E __attribute__((ext_vector_type(2)));
+  E* p = reinterpret_cast<E*>(reinterpret_cast<char*>(base) + idx * (uint32_t)sizeof(V));
+  const E e = {v.x, v.y};
+  __builtin_nontemporal_store(e, p);
+}
 
 // LLO low bits (compile-time, so the low-bond loop unrolls).  LANCZOS:
 // w = sa * H u_j - sb * u_{j-1} with the dot-product partials of the H-pass;
@@ -213,9 +235,13 @@ k_blk(BlkArgs ba, const typename Cx<T>::V* __restrict__ x, typename Cx<T>::V* __
   const bool prev = LANCZOS && la.j > 0;
   double s1 = 0.0, s2 = 0.0, s3r = 0.0, s3i = 0.0;
   const int lhi = ba.lhi;
-  const int xcd = blockIdx.x % kNumXcd, kx = blockIdx.x / kNumXcd, per = gridDim.x / kNumXcd;
-  const int first = ba.xcd_first[xcd], last = ba.xcd_first[xcd + 1];
-  int bi = first + kx;
+  // work-group w runs on XCD w % 8; in every window of gridDim.x blocks the
+  // XCD takes chunks of 2^chunk_log2 consecutive blocks (the launcher makes
+  // gridDim.x / 8 a multiple of the chunk)
+  const int xcd = blockIdx.x % kNumXcd, kx = blockIdx.x / kNumXcd;
+  const int cl = ba.chunk_log2;
+  const int per = (int)gridDim.x, last = ba.nblk;
+  int bi = ((((kx >> cl) * kNumXcd) + xcd) << cl) + (kx & ((1 << cl) - 1));
   const bool run = act[0] != 0;
   __syncthreads();   // `red` (aliasing the x buffers) is no longer read
 
@@ -260,7 +286,7 @@ k_blk(BlkArgs ba, const typename Cx<T>::V* __restrict__ x, typename Cx<T>::V* __
       // Lanczos vector, the bond joining the halves and the ring bond
       // (inactive ones read x[r] and are discarded)
       V um = {0, 0};
-      if (prev) um = ld32(ujm1, r);
+      if (prev) um = ld32_stream(ujm1, r);
       const uint32_t bl = (b >> (LLO - 1)) & 1u;
       const bool cx = (bl ^ (a & 1u)) != 0u;
       const uint32_t pcl = (uint32_t)__popc(b & ((1u << (LLO - 1)) - 1u));
@@ -320,13 +346,13 @@ k_blk(BlkArgs ba, const typename Cx<T>::V* __restrict__ x, typename Cx<T>::V* __
         V wv;
         wv.x = ca * h.x - cb * um.x;
         wv.y = ca * h.y - cb * um.y;
-        st32(y, r, wv);
+        st32_stream(y, r, wv);
         s1 += (double)xr.x * (double)wv.x + (double)xr.y * (double)wv.y;
         s2 += (double)xr.x * (double)xr.x + (double)xr.y * (double)xr.y;
         s3r += (double)um.x * (double)wv.x + (double)um.y * (double)wv.y;
         s3i += (double)um.x * (double)wv.y - (double)um.y * (double)wv.x;
       } else {
-        st32(y, r, h);
+        st32_stream(y, r, h);
       }
     }
     if (has_next) {
@@ -396,7 +422,8 @@ static BlkArgs blk_args(const qk_ham* H) {
     ba.lo_base[k] = acc;
     acc += (uint32_t)binom_host(H->llo, k);
   }
-  for (int x = 0; x <= kNumXcd; ++x) ba.xcd_first[x] = H->xcd_first[x];
+  ba.nblk = H->nblk;
+  ba.chunk_log2 = 0;
   return ba;
 }
 
@@ -423,11 +450,8 @@ qk_status launch_blocked_build(qk_ham* H, hipStream_t s) {
   if (e == hipSuccess) e = hipMalloc(&tmp, tmp_bytes + 16);
   if (e == hipSuccess) e = hipcub::DeviceScan::ExclusiveSum(tmp, tmp_bytes, flag, idx, (int)nhi, s);
   uint32_t last_idx = 0, last_flag = 0;
-  uint32_t xcd_idx[kNumXcd];
   if (e == hipSuccess) e = hipMemcpyAsync(&last_idx, idx + nhi - 1, 4, hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipMemcpyAsync(&last_flag, flag + nhi - 1, 4, hipMemcpyDeviceToHost, s);
-  for (int x = 0; x < kNumXcd && e == hipSuccess; ++x)
-    e = hipMemcpyAsync(&xcd_idx[x], idx + ((size_t)x << (lhi - 3)), 4, hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e == hipSuccess) {
     H->nblk = (int)(last_idx + last_flag);
@@ -448,8 +472,6 @@ qk_status launch_blocked_build(qk_ham* H, hipStream_t s) {
   hipFree(flag);
   hipFree(idx);
   QK_HIP(e);
-  for (int x = 0; x < kNumXcd; ++x) H->xcd_first[x] = (int)xcd_idx[x];
-  H->xcd_first[kNumXcd] = H->nblk;
   return QK_OK;
 }
 
@@ -471,7 +493,7 @@ static qk_status launch_blk_t(const qk_ham* H, const void* x, void* y, const voi
                               const LanczosArgs* la, const double* partB, int Gp, double* partA, int* grid_out,
                               int wgs_req, hipStream_t s) {
   using V = typename Cx<T>::V;
-  const BlkArgs ba = blk_args(H);
+  BlkArgs ba = blk_args(H);
   const size_t dyn = blk_xbytes<T, LLO>() + 2 * sizeof(uint16_t) * ((size_t)1 << LLO);
   auto kern = k_blk<T, LLO, LANCZOS>;
   static int occ = 0;
@@ -486,6 +508,11 @@ static qk_status launch_blk_t(const qk_ham* H, const void* x, void* y, const voi
   int G = ((cus * wgs) / kNumXcd) * kNumXcd;
   if (G < kNumXcd) G = kNumXcd;
   if (G > kMaxPartialBlocks) G = kMaxPartialBlocks;
+  // chunk of consecutive blocks per XCD: 8, or the largest power of two
+  // dividing the work-groups per XCD
+  int cl = 3;
+  while (cl > 0 && (G / kNumXcd) % (1 << cl) != 0) --cl;
+  ba.chunk_log2 = cl;
   KState stv{};
   LanczosArgs lav{};
   if (st) stv = *st;

@@ -65,7 +65,6 @@ struct qk_ham {
   uint16_t* d_lo_rank = nullptr;  // [2^llo]
   void* d_blk = nullptr;          // [nblk] block entries (high bits, first row, ring-partner first row)
   int nblk = 0;
-  int xcd_first[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
 };
 
 struct qk_krylov {

@@ -1,0 +1,161 @@
+"""GPU parity at full size, in the launch configuration the benchmark times
+(blocked matrix-free H-pass, B = 1): the mid-size L=24 chain against exact
+propagation at short times and against the free-fermion closed form at all
+200 output times; the L=28 and L=30 chains against the free-fermion closed
+form (zz coupling 0, same kernels); and, where no exact reference exists
+(L=28/30 with zz coupling), the invariants and the FP64/FP32 agreement."""
+import math
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import paper_1704_02770_amd as qk
+from gpu_util import say, to_host
+from oracle import basis as OB
+from oracle import freefermion as OF
+from oracle import hamiltonian as OH
+from oracle import model as OM
+from workloads import BETA_GOLDEN, log_times, phases
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "l24_short_times.txt")
+PHI = float(phases(1, 0)[0])
+
+
+def _neel_row(b, L):
+    return int(qk.qk_basis_rank(b, [OM.neel_state(L)])[0])
+
+
+def _evolve(b, H, L, times, m, dt, dtype=torch.complex128):
+    """P at each output time; each gap is cut into ceil(gap / dt) equal steps."""
+    k = qk.qk_krylov_create(H, m, dtype)
+    D = qk.qk_basis_dim(b)
+    r0 = _neel_row(b, L)
+    psi = torch.zeros(D, dtype=dtype, device="cuda")
+    psi[r0] = 1.0
+    P = torch.empty(len(times), dtype=torch.float64, device="cuda")
+    t_prev = 0.0
+    for i, t in enumerate(times):
+        gap = float(t) - t_prev
+        n = max(1, math.ceil(gap / dt - 1e-12))
+        for _ in range(n):
+            qk.qk_krylov_expm_step(k, psi, gap / n)
+        qk.qk_return_prob(b, psi, r0=r0, out=P[i:i + 1])
+        t_prev = float(t)
+    return to_host(P), psi, r0
+
+
+def _read_golden():
+    rows = [ln.split() for ln in open(GOLDEN) if not ln.startswith("#")]
+    times = np.array([float(x) for x in rows[0]])
+    cases = {(int(r[0]), float(r[1])): np.array([float(x) for x in r[2:]]) for r in rows[1:]}
+    return times, cases
+
+
+@pytest.mark.parametrize("pbc", [False, True])
+def test_l24_short_times_vs_exact(pbc):
+    # h in {0, 1, 3}, log-spaced output times up to t = 1, m = 30, steps <= 0.1;
+    # expected values written by tests/golden/make_golden_l24.py (oracle only)
+    times, cases = _read_golden()
+    b = qk.qk_basis_build(24, 12)
+    for h in (0.0, 1.0, 3.0):
+        hf = OM.fields(24, h, BETA_GOLDEN, PHI)
+        H = qk.qk_ham_create(b, 1.0, 1.0, pbc, hf)
+        say("L24 short times", pbc, h)
+        P, _, _ = _evolve(b, H, 24, times, 30, 0.1)
+        err = np.max(np.abs(P - cases[(int(pbc), h)]))
+        say("  max |dP| =", err)
+        assert err < 1e-10
+
+
+@pytest.mark.parametrize("pbc", [False, True])
+def test_l24_free_fermions_all_times(pbc):
+    # zz coupling 0: the closed form holds at every one of the 200 output times to t = 100
+    times = log_times()
+    b = qk.qk_basis_build(24, 12)
+    for h in (0.0, 1.0, 3.0):
+        hf = OM.fields(24, h, BETA_GOLDEN, PHI)
+        H = qk.qk_ham_create(b, 1.0, 0.0, pbc, hf)
+        say("L24 free fermions", pbc, h)
+        P, psi, _ = _evolve(b, H, 24, times, 30, 0.1)
+        ref = OF.survival_probability(24, 12, pbc, 1.0, hf, OM.neel_state(24), times)
+        err = np.max(np.abs(P - ref))
+        say("  max |dP| =", err)
+        assert err < 1e-10
+        assert abs(torch.linalg.vector_norm(psi).item() - 1.0) < 1e-11
+
+
+@pytest.mark.parametrize("L,m,dt,t_end,h", [(28, 30, 0.1, 2.0, 1.5), (30, 20, 0.05, 0.5, 0.0), (30, 20, 0.05, 0.5, 2.0)])
+def test_large_free_fermions(L, m, dt, t_end, h):
+    b = qk.qk_basis_build(L, L // 2)
+    hf = OM.fields(L, h, BETA_GOLDEN, PHI)
+    H = qk.qk_ham_create(b, 1.0, 0.0, True, hf)
+    times = dt * np.arange(1, int(round(t_end / dt)) + 1)
+    say("free fermions", L, m, dt, h)
+    P, psi, _ = _evolve(b, H, L, times, m, dt)
+    ref = OF.survival_probability(L, L // 2, True, 1.0, hf, OM.neel_state(L), times)
+    err = np.max(np.abs(P - ref))
+    say("  max |dP| =", err)
+    assert err < 1e-10
+    assert abs(torch.linalg.vector_norm(psi).item() - 1.0) < 1e-11
+
+
+def test_l28_benchmark_workload_invariants():
+    # the benchmark chain (L=28 ring, h=1.5, m=30, dt=0.1, zz coupling 1): no
+    # exact reference; first Lanczos coefficients against closed forms, norm
+    # and energy conservation, complex64 storage against complex128
+    L = 28
+    b = qk.qk_basis_build(L, L // 2)
+    hf = OM.fields(L, 1.5, BETA_GOLDEN, PHI)
+    H = qk.qk_ham_create(b, 1.0, 1.0, True, hf)
+    times = 0.1 * np.arange(1, 11)
+    say("L28 workload fp64")
+    P64, psi, r0 = _evolve(b, H, L, times, 30, 0.1)
+    # energy <psi|H|psi> equals the Neel diagonal element (oracle) at every time
+    E0 = float(OH.diagonal(np.array([OM.neel_state(L)]), L, True, 1.0, hf)[0])
+    y = qk.qk_ham_apply(H, psi)
+    E = torch.vdot(psi, y).real.item()
+    say("  E =", E, "E0 =", E0)
+    assert abs(E - E0) < 1e-10 * max(1.0, abs(E0))
+    assert abs(torch.linalg.vector_norm(psi).item() - 1.0) < 1e-12
+    # alpha_0 = E0 and beta_0 = (jxy/2) sqrt(L) for the first step from the Neel state
+    k = qk.qk_krylov_create(H, 30)
+    e = torch.zeros_like(psi)
+    e[r0] = 1.0
+    qk.qk_krylov_expm_step(k, e, 0.1)
+    alpha, beta, mu = qk.qk_krylov_coefficients(k)
+    assert mu == 30
+    assert abs(alpha[0] - E0) < 1e-12 * max(1.0, abs(E0))
+    assert abs(beta[0] - 0.5 * math.sqrt(L)) < 1e-12
+    # P(t) is even in t and 1 - beta_0^2 t^2 + O(t^4): check the first output
+    assert abs(P64[0] - (1.0 - 0.25 * L * 0.01)) < 0.25 * L * 0.01 * 0.1
+    del k, e, y
+    say("L28 workload fp32")
+    P32, _, _ = _evolve(b, H, L, times, 30, 0.1, torch.complex64)
+    err = np.max(np.abs(P32 - P64))
+    say("  complex64 vs complex128 max |dP| =", err)
+    assert err < 1e-5
+
+
+@pytest.mark.parametrize("h", [0.0, 2.0])
+def test_l30_fp64_vs_fp32(h):
+    # the large chain with zz coupling: m = 20, dt = 0.05, Krylov basis resident
+    # in HBM (about 50 GB in complex128)
+    L = 30
+    b = qk.qk_basis_build(L, L // 2)
+    hf = OM.fields(L, h, BETA_GOLDEN, PHI)
+    H = qk.qk_ham_create(b, 1.0, 1.0, True, hf)
+    times = 0.05 * np.arange(1, 11)
+    say("L30 fp64", h)
+    P64, psi, _ = _evolve(b, H, L, times, 20, 0.05)
+    assert abs(torch.linalg.vector_norm(psi).item() - 1.0) < 1e-12
+    del psi
+    torch.cuda.empty_cache()
+    say("L30 fp32", h)
+    P32, _, _ = _evolve(b, H, L, times, 20, 0.05, torch.complex64)
+    err = np.max(np.abs(P32 - P64))
+    say("  complex64 vs complex128 max |dP| =", err)
+    assert err < 1e-5
