@@ -370,6 +370,181 @@ k_blk(BlkArgs ba, const typename Cx<T>::V* __restrict__ x, typename Cx<T>::V* __
   }
 }
 
+// ------------------------------------------------ blocked rows, batched
+// The same decomposition for B > 1 phases in the [D][B] layout (B a power of
+// two): element e = j * B + b of a block is row j, phase b, so a gather of a
+// partner run reads B consecutive values per row.  The fields differ per
+// phase, so the diagonal is assembled per element from the phase's fields in
+// LDS (the block table's constant holds phase 0 only and is not used here).
+// llo is a runtime value chosen so that one block of B phases fits the LDS
+// buffer; the block is staged once (no double buffer).  Each thread keeps the
+// phase tid % B for the whole kernel.
+constexpr int kBlkbThreads = 256;
+constexpr uint64_t kBlkbBudget = 32768;   // LDS bytes of one staged block of B phases (complex128)
+
+__host__ __device__ inline size_t blkb_xbytes(uint32_t maxlen, int B, size_t vbytes) {
+  const size_t b = (size_t)maxlen * B * vbytes;
+  const size_t r = (size_t)kQA * kBlkbThreads * sizeof(double);
+  return ((b > r ? b : r) + 15) & ~(size_t)15;
+}
+
+template <typename T, bool LANCZOS>
+__global__ void __launch_bounds__(kBlkbThreads)
+k_blkb(BlkArgs ba, int B, int lb, const typename Cx<T>::V* __restrict__ x, typename Cx<T>::V* __restrict__ y,
+       const typename Cx<T>::V* __restrict__ ujm1, KState st, LanczosArgs la, const double* __restrict__ partB, int Gp,
+       double* __restrict__ partA) {
+  using V = typename Cx<T>::V;
+  extern __shared__ unsigned char smem[];
+  const int llo = ba.llo, L = ba.L, lhi = ba.lhi;
+  V* xs = reinterpret_cast<V*>(smem);
+  const size_t xb = blkb_xbytes((uint32_t)ba.maxlen, B, sizeof(V));
+  uint16_t* lo_state = reinterpret_cast<uint16_t*>(smem + xb);
+  uint16_t* lo_rank = lo_state + (1 << llo);
+  double* fld = reinterpret_cast<double*>(smem + xb + (((size_t)4 << llo) + 15 & ~(size_t)15));   // [B][L]
+  double* hic = fld + (size_t)B * L;   // per phase: block constant of the diagonal
+  double* hh = hic + B;                // per phase: sum of the fields / 2
+  __shared__ uint32_t sbin[kBinomStride * kBinomStride];
+  __shared__ double tot[QK_MAX_BATCH], sa[QK_MAX_BATCH], sb[QK_MAX_BATCH];
+  __shared__ int act[QK_MAX_BATCH];
+  double* red = reinterpret_cast<double*>(smem);   // aliases xs outside the block loop
+
+  const int tid = threadIdx.x;
+  for (int i = tid; i < kBinomStride * kBinomStride; i += kBlkbThreads) sbin[i] = ba.binom[i];
+  for (int i = tid; i < (1 << llo); i += kBlkbThreads) {
+    lo_state[i] = ba.lo_state[i];
+    lo_rank[i] = ba.lo_rank[i];
+  }
+  for (int i = tid; i < B * L; i += kBlkbThreads) fld[i] = ba.fields[i];
+  __syncthreads();
+  for (int b = tid; b < B; b += kBlkbThreads) {
+    double f = 0.0;
+    for (int i = 0; i < L; ++i) f += fld[b * L + i];
+    hh[b] = 0.5 * f;
+  }
+  if (LANCZOS) {
+    lanczos_h_scalars(B, st, la, partB, Gp, red, tot, sa, sb, act);
+  } else {
+    for (int b = tid; b < B; b += kBlkbThreads) {
+      sa[b] = 1.0;
+      sb[b] = 0.0;
+      act[b] = 1;
+    }
+    __syncthreads();
+  }
+  const int bc = tid & (B - 1);   // this thread's phase
+  const bool mine = act[bc] != 0;
+  const T g = (T)ba.half_jxy;
+  const double hjz = 0.5 * ba.jz;
+  const T ca = (T)sa[bc], cb = (T)sb[bc];
+  const bool prev = LANCZOS && la.j > 0;
+  const double* fb = fld + (size_t)bc * L;
+  double s1 = 0.0, s2 = 0.0, s3r = 0.0, s3i = 0.0;
+  const int xcd = blockIdx.x % kNumXcd, kx = blockIdx.x / kNumXcd;
+  const int cl = ba.chunk_log2;
+  const int last = ba.nblk;
+  int bi = ((((kx >> cl) * kNumXcd) + xcd) << cl) + (kx & ((1 << cl) - 1));
+  __syncthreads();   // `red` (aliasing xs) is no longer read
+
+  for (; bi < last; bi += (int)gridDim.x) {
+    const BlkEntry* ep = ba.blk + bi;
+    const uint32_t a = ep->a, off = ep->off, offw = ep->offw;
+    const int nact = (int)ep->nact;
+    const int k_lo = ba.N - __popc(a);
+    const uint32_t len = sbin[llo * kBinomStride + k_lo];
+    const uint32_t base = ba.lo_base[k_lo];
+    const uint32_t nel = len << lb;
+    const size_t eoff = (size_t)off << lb;
+    for (uint32_t e = tid; e < nel; e += kBlkbThreads) xs[e] = x[eoff + e];
+    if (tid < B) {
+      double f = ba.zz0 - 0.5 * ba.jz * (double)nact - hh[tid];
+      for (int t = 0; t < lhi; ++t)
+        if ((a >> t) & 1u) f += fld[tid * L + llo + t];
+      hic[tid] = f;
+    }
+    __syncthreads();
+    const uint32_t top = (a >> (lhi - 1)) & 1u;
+    const double dblk = hic[bc];
+    if (mine) {
+      for (uint32_t e = tid; e < nel; e += kBlkbThreads) {
+        const uint32_t j = e >> lb;
+        const uint32_t bs = lo_state[base + j];
+        const uint32_t r = off + j;
+        V um = {0, 0};
+        if (prev) um = ujm1[((size_t)r << lb) + bc];
+        const uint32_t bl = (bs >> (llo - 1)) & 1u;
+        const bool cx = (bl ^ (a & 1u)) != 0u;
+        const uint32_t pcl = (uint32_t)__popc(bs & ((1u << (llo - 1)) - 1u));
+        const uint32_t cc = sbin[(llo - 1) * kBinomStride + pcl];
+        const uint32_t rc = cx ? (bl ? r + cc : r - cc) : r;
+        const V vc = x[((size_t)rc << lb) + bc];
+        const bool wx = ba.pbc && ((bs & 1u) != top);
+        const uint32_t rw = wx ? offw + lo_rank[bs ^ 1u] : r;
+        const V vw = x[((size_t)rw << lb) + bc];
+        const V q0 = x[((size_t)(r + (uint32_t)ep->delta[0]) << lb) + bc];
+        const V q1 = x[((size_t)(r + (uint32_t)ep->delta[1]) << lb) + bc];
+        const V q2 = x[((size_t)(r + (uint32_t)ep->delta[2]) << lb) + bc];
+        const V q3 = x[((size_t)(r + (uint32_t)ep->delta[3]) << lb) + bc];
+        const V xr = xs[e];
+        const int anti = __popc((bs ^ (bs >> 1)) & ((1u << (llo - 1)) - 1u)) + (cx ? 1 : 0) + (wx ? 1 : 0);
+        double d = dblk - hjz * anti;
+        for (int i = 0; i < llo; ++i) d += ((bs >> i) & 1u) ? fb[i] : 0.0;
+        V hs = {0, 0};
+        int pc = 0;
+        for (int p = 0; p < llo - 1; ++p) {
+          const uint32_t b0 = (bs >> p) & 1u, b1 = (bs >> (p + 1)) & 1u;
+          if (b0 != b1) {
+            const uint32_t c = sbin[p * kBinomStride + pc];
+            const V v = xs[((b0 ? j + c : j - c) << lb) + bc];
+            hs.x += v.x;
+            hs.y += v.y;
+          }
+          pc += (int)b0;
+        }
+        {
+          const T w0 = (0 < nact) ? (T)1 : (T)0, w1 = (1 < nact) ? (T)1 : (T)0;
+          const T w2 = (2 < nact) ? (T)1 : (T)0, w3 = (3 < nact) ? (T)1 : (T)0;
+          hs.x += w0 * q0.x + w1 * q1.x + w2 * q2.x + w3 * q3.x;
+          hs.y += w0 * q0.y + w1 * q1.y + w2 * q2.y + w3 * q3.y;
+        }
+        for (int g0 = 4; g0 < nact; g0 += 4) {
+          const V v0 = x[((size_t)(r + (uint32_t)ep->delta[g0]) << lb) + bc];
+          const V v1 = x[((size_t)(r + (uint32_t)ep->delta[g0 + 1]) << lb) + bc];
+          const V v2 = x[((size_t)(r + (uint32_t)ep->delta[g0 + 2]) << lb) + bc];
+          const V v3 = x[((size_t)(r + (uint32_t)ep->delta[g0 + 3]) << lb) + bc];
+          const T w1 = (g0 + 1 < nact) ? (T)1 : (T)0;
+          const T w2 = (g0 + 2 < nact) ? (T)1 : (T)0;
+          const T w3 = (g0 + 3 < nact) ? (T)1 : (T)0;
+          hs.x += v0.x + w1 * v1.x + w2 * v2.x + w3 * v3.x;
+          hs.y += v0.y + w1 * v1.y + w2 * v2.y + w3 * v3.y;
+        }
+        hs.x += (cx ? vc.x : (T)0) + (wx ? vw.x : (T)0);
+        hs.y += (cx ? vc.y : (T)0) + (wx ? vw.y : (T)0);
+        V h;
+        h.x = (T)d * xr.x + g * hs.x;
+        h.y = (T)d * xr.y + g * hs.y;
+        const size_t o = ((size_t)r << lb) + bc;
+        if (LANCZOS) {
+          V wv;
+          wv.x = ca * h.x - cb * um.x;
+          wv.y = ca * h.y - cb * um.y;
+          y[o] = wv;
+          s1 += (double)xr.x * (double)wv.x + (double)xr.y * (double)wv.y;
+          s2 += (double)xr.x * (double)xr.x + (double)xr.y * (double)xr.y;
+          s3r += (double)um.x * (double)wv.x + (double)um.y * (double)wv.y;
+          s3i += (double)um.x * (double)wv.y - (double)um.y * (double)wv.x;
+        } else {
+          y[o] = h;
+        }
+      }
+    }
+    __syncthreads();   // xs and hic are rewritten by the next block
+  }
+  if (LANCZOS) {
+    double v[kQA] = {s1, s2, s3r, s3i};
+    block_partials<kQA>(v, B, red, partA + (size_t)blockIdx.x * kQA * B);
+  }
+}
+
 // ================================================================ launchers
 static uint64_t binom_host(int n, int k) {
   if (k < 0 || k > n) return 0;
@@ -388,13 +563,24 @@ static int env_int(const char* name, int dflt) {
 }
 
 int blocked_llo(int L, int N, int B, int mode) {
-  if (mode != QK_MATFREE || B != 1 || L < 18) return 0;
   (void)N;
-  int llo = env_int("QK_BLOCKED_LLO", 11);
-  if (llo < 9) llo = 9;
-  if (llo > 11) llo = 11;
-  if (llo > L / 2) llo = L / 2;
-  return llo;
+  if (mode != QK_MATFREE || L < 18) return 0;
+  if (B == 1) {
+    int llo = env_int("QK_BLOCKED_LLO", 11);
+    if (llo < 9) llo = 9;
+    if (llo > 11) llo = 11;
+    if (llo > L / 2) llo = L / 2;
+    return llo;
+  }
+  // batches: B a power of two; the largest llo whose biggest block of B
+  // complex128 phases fits kBlkbBudget bytes of LDS, with at most 2^20 block
+  // entries (128 MB of table)
+  if (B < 2 || B > QK_MAX_BATCH || (B & (B - 1)) != 0) return 0;
+  for (int llo = (L / 2 < 11 ? L / 2 : 11); llo >= 5; --llo) {
+    const uint64_t bytes = binom_host(llo, llo / 2) * (uint64_t)B * 16u;
+    if (bytes <= kBlkbBudget && L - llo <= 20) return llo;
+  }
+  return 0;
 }
 
 static BlkArgs blk_args(const qk_ham* H) {
@@ -484,8 +670,43 @@ qk_status launch_blocked_fields(qk_ham* H, hipStream_t s) {
 }
 
 bool blocked_usable(const qk_ham* H, int dtype) {
+  // the single-phase kernel addresses vectors with 32-bit byte offsets
   const uint64_t bytes = (uint64_t)H->basis->D * (dtype == QK_C128 ? 16u : 8u);
-  return H->llo > 0 && bytes < (1ull << 32);
+  return H->llo > 0 && (H->batch > 1 || bytes < (1ull << 32));
+}
+
+template <typename T, bool LANCZOS>
+static qk_status launch_blkb_t(const qk_ham* H, const void* x, void* y, const void* ujm1, const KState* st,
+                               const LanczosArgs* la, const double* partB, int Gp, double* partA, int* grid_out,
+                               int wgs_req, hipStream_t s) {
+  using V = typename Cx<T>::V;
+  BlkArgs ba = blk_args(H);
+  const int B = H->batch;
+  int lb = 0;
+  while ((1 << lb) < B) ++lb;
+  const size_t dyn = blkb_xbytes((uint32_t)ba.maxlen, B, sizeof(V)) + ((((size_t)4 << ba.llo) + 15) & ~(size_t)15) +
+                     sizeof(double) * ((size_t)B * ba.L + 2 * (size_t)B);
+  auto kern = k_blkb<T, LANCZOS>;
+  int occ = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, kBlkbThreads, dyn) != hipSuccess || occ < 1) occ = 1;
+  const int cus = qk_num_cus();
+  int wgs = wgs_req > 0 ? wgs_req : env_int("QK_BLOCKED_WGS_PER_CU", occ);
+  if (wgs > occ) wgs = occ;
+  int G = ((cus * wgs) / kNumXcd) * kNumXcd;
+  if (G < kNumXcd) G = kNumXcd;
+  if (G > kMaxPartialBlocks) G = kMaxPartialBlocks;
+  int cl = 3;
+  while (cl > 0 && (G / kNumXcd) % (1 << cl) != 0) --cl;
+  ba.chunk_log2 = cl;
+  KState stv{};
+  LanczosArgs lav{};
+  if (st) stv = *st;
+  if (la) lav = *la;
+  hipLaunchKernelGGL(kern, dim3(G), dim3(kBlkbThreads), dyn, s, ba, B, lb, (const V*)x, (V*)y, (const V*)ujm1, stv,
+                     lav, partB, Gp, partA);
+  QK_HIP(hipGetLastError());
+  if (grid_out) *grid_out = G;
+  return QK_OK;
 }
 
 template <typename T, int LLO, bool LANCZOS>
@@ -537,6 +758,11 @@ static qk_status launch_blk_llo(const qk_ham* H, const void* x, void* y, const v
 }
 
 qk_status launch_blocked_apply(const qk_ham* H, const void* x, void* y, int dtype, hipStream_t s) {
+  if (H->batch > 1) {
+    if (dtype == QK_C128)
+      return launch_blkb_t<double, false>(H, x, y, nullptr, nullptr, nullptr, nullptr, 0, nullptr, nullptr, 0, s);
+    return launch_blkb_t<float, false>(H, x, y, nullptr, nullptr, nullptr, nullptr, 0, nullptr, nullptr, 0, s);
+  }
   if (dtype == QK_C128)
     return launch_blk_llo<double, false>(H, x, y, nullptr, nullptr, nullptr, nullptr, 0, nullptr, nullptr, 0, s);
   return launch_blk_llo<float, false>(H, x, y, nullptr, nullptr, nullptr, nullptr, 0, nullptr, nullptr, 0, s);
@@ -545,6 +771,11 @@ qk_status launch_blocked_apply(const qk_ham* H, const void* x, void* y, int dtyp
 qk_status launch_blocked_lanczos_h(const qk_ham* H, int dtype, const void* uj, const void* ujm1, void* w,
                                    const KState& st, const LanczosArgs& la, const double* partB, int Gp,
                                    double* partA, int* grid_out, int wgs_per_cu, hipStream_t s) {
+  if (H->batch > 1) {
+    if (dtype == QK_C128)
+      return launch_blkb_t<double, true>(H, uj, w, ujm1, &st, &la, partB, Gp, partA, grid_out, wgs_per_cu, s);
+    return launch_blkb_t<float, true>(H, uj, w, ujm1, &st, &la, partB, Gp, partA, grid_out, wgs_per_cu, s);
+  }
   if (dtype == QK_C128)
     return launch_blk_llo<double, true>(H, uj, w, ujm1, &st, &la, partB, Gp, partA, grid_out, wgs_per_cu, s);
   return launch_blk_llo<float, true>(H, uj, w, ujm1, &st, &la, partB, Gp, partA, grid_out, wgs_per_cu, s);

@@ -270,37 +270,75 @@ k_small_expm(KState st, int m, int B, double tau, const double* __restrict__ par
 
 // ------------------------------------------------ Krylov combination
 // psi[r, b] = sum_{j < m_used} gamma_j u_j[r, b], u_0 = psi, accumulated in
-// double and rounded once.
-template <typename T>
+// double and rounded once.  The [D][B] arrays are walked as flat elements
+// i = r * B + b; a thread takes the E consecutive elements of one access
+// (E = 2 packs two complex64 values into 16 bytes) and issues the loads of
+// four Krylov vectors before it accumulates them.  Columns whose step failed
+// or had nothing to propagate are left unchanged.
+template <typename T, int E>
 __global__ void __launch_bounds__(kMaxBlock)
 k_combine(typename Cx<T>::V* __restrict__ psi, const typename Cx<T>::V* __restrict__ U, uint32_t D, int B, int m,
           KState st) {
   using V = typename Cx<T>::V;
-  const int b = threadIdx.x % B;
-  const uint32_t R = blockDim.x / B, rl = threadIdx.x / B;
-  const int mu = st.mused[b];
-  if (st.status[b] != QK_OK || mu <= 0) return;
-  const uint32_t ntiles = (D + R - 1) / R;
-  const size_t stride = (size_t)D * B;
-  for (TileWalk tw(ntiles); tw.t < tw.t_end; tw.t += tw.step) {
-    const uint32_t r = tw.t * R + rl;
-    if (r >= D) continue;
-    const size_t i = (size_t)r * B + b;
-    const V p = psi[i];
-    double gr = st.gre[b], gi = st.gim[b];
-    double ar = gr * (double)p.x - gi * (double)p.y;
-    double ai = gr * (double)p.y + gi * (double)p.x;
-    for (int jj = 1; jj < mu; ++jj) {
-      const V u = U[(size_t)(jj - 1) * stride + i];
-      gr = st.gre[jj * B + b];
-      gi = st.gim[jj * B + b];
-      ar += gr * (double)u.x - gi * (double)u.y;
-      ai += gr * (double)u.y + gi * (double)u.x;
+  struct alignas(sizeof(V) * E) Pack {
+    V v[E];
+  };
+  const uint64_t np = (uint64_t)D * B / E;   // packs per vector (the launcher makes D * B a multiple of E)
+  const Pack* Up = reinterpret_cast<const Pack*>(U);
+  Pack* Pp = reinterpret_cast<Pack*>(psi);
+  for (uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; p < np; p += (uint64_t)gridDim.x * blockDim.x) {
+    int bc[E], mu[E];
+    bool ok[E];
+    int mumax = 0;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      bc[e] = (int)((p * E + e) % (uint64_t)B);
+      mu[e] = st.mused[bc[e]];
+      ok[e] = st.status[bc[e]] == QK_OK && mu[e] > 0;
+      if (ok[e] && mu[e] > mumax) mumax = mu[e];
     }
-    V o;
-    o.x = (T)ar;
-    o.y = (T)ai;
-    psi[i] = o;
+    const Pack p0 = Pp[p];
+    double ar[E], ai[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const double gr = st.gre[bc[e]], gi = st.gim[bc[e]];
+      ar[e] = gr * (double)p0.v[e].x - gi * (double)p0.v[e].y;
+      ai[e] = gr * (double)p0.v[e].y + gi * (double)p0.v[e].x;
+    }
+    int jj = 1;
+    for (; jj + 3 < mumax; jj += 4) {
+      Pack u[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) u[k] = Up[(uint64_t)(jj - 1 + k) * np + p];
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+          if (jj + k < mu[e]) {
+            const double gr = st.gre[(jj + k) * B + bc[e]], gi = st.gim[(jj + k) * B + bc[e]];
+            ar[e] += gr * (double)u[k].v[e].x - gi * (double)u[k].v[e].y;
+            ai[e] += gr * (double)u[k].v[e].y + gi * (double)u[k].v[e].x;
+          }
+        }
+    }
+    for (; jj < mumax; ++jj) {
+      const Pack u = Up[(uint64_t)(jj - 1) * np + p];
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        if (jj < mu[e]) {
+          const double gr = st.gre[jj * B + bc[e]], gi = st.gim[jj * B + bc[e]];
+          ar[e] += gr * (double)u.v[e].x - gi * (double)u.v[e].y;
+          ai[e] += gr * (double)u.v[e].y + gi * (double)u.v[e].x;
+        }
+      }
+    }
+    Pack o;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      o.v[e].x = ok[e] ? (T)ar[e] : p0.v[e].x;
+      o.v[e].y = ok[e] ? (T)ai[e] : p0.v[e].y;
+    }
+    Pp[p] = o;
   }
 }
 
@@ -582,7 +620,14 @@ static qk_status krylov_step_t(qk_krylov* k, void* psi_v, double dt, hipStream_t
   QK_HIP(hipGetLastError());
   QK_MARK(QK_KERNEL_SMALL_EXPM, false);
   QK_MARK(QK_KERNEL_COMBINE, true);
-  hipLaunchKernelGGL((k_combine<T>), dim3(G), dim3(threads), 0, s, psi, U, D, B, m, st);
+  // complex64 elements go two to a 16-byte access when the vector length and
+  // both base addresses allow it
+  const bool pack2 = sizeof(V) == 8 && ((uint64_t)D * B) % 2 == 0 && ((uintptr_t)psi % 16) == 0 &&
+                     ((uintptr_t)U % 16) == 0;
+  if (pack2)
+    hipLaunchKernelGGL((k_combine<T, 2>), dim3(G), dim3(threads), 0, s, psi, U, D, B, m, st);
+  else
+    hipLaunchKernelGGL((k_combine<T, 1>), dim3(G), dim3(threads), 0, s, psi, U, D, B, m, st);
   QK_HIP(hipGetLastError());
   QK_MARK(QK_KERNEL_COMBINE, false);
 #undef QK_MARK

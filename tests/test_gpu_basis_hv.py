@@ -168,3 +168,33 @@ def test_blocked_equals_row_form(pbc):
     yb = to_host(qk.qk_ham_apply(Hb, x))
     yr = to_host(qk.qk_ham_apply(Hr, x))
     assert max_rel(yb, yr) < 1e-14
+
+
+BATCHED_BLOCKED = [(18, 9, True, 2), (18, 9, False, 4), (20, 10, True, 8), (20, 10, False, 64), (19, 9, True, 16),
+                   (22, 11, True, 32)]
+
+
+@pytest.mark.parametrize("dtype", [torch.complex128, torch.complex64])
+@pytest.mark.parametrize("L,N,pbc,Bn", BATCHED_BLOCKED)
+def test_hv_blocked_batched(L, N, pbc, Bn, dtype):
+    # B phases in the [D][B] layout with L >= 18 run the batched blocked form.
+    # Reference per phase: the oracle's H with zero fields (hops and zz) plus
+    # the phase's field part of the oracle's diagonal.
+    hs = np.stack([random_fields(L, 300 + i) for i in range(Bn)])
+    b = qk.qk_basis_build(L, N)
+    D = qk.qk_basis_dim(b)
+    say("hv blocked batched", L, N, pbc, Bn, dtype)
+    H = qk.qk_ham_create(b, 1.0, 0.7, pbc, hs)
+    X = random_complex(D * Bn, 40 + Bn).reshape(D, Bn)
+    xd = to_dev(X, dtype)
+    y = to_host(qk.qk_ham_apply(H, xd))
+    Xc = to_host(xd).astype(np.complex128)
+    H0 = OH.build_csr(L, N, pbc, 1.0, 0.7, np.zeros(L))
+    st = OB.sector_states(L, N)
+    dfield = OH.diagonal(st, L, pbc, 0.7, hs) - OH.diagonal(st, L, pbc, 0.7, np.zeros(L))[:, None]
+    ref = H0 @ Xc + dfield * Xc
+    assert max_rel(y, ref) < TOL[dtype] * 4
+    # the same rows through the row-form kernel
+    Hr = qk.qk_ham_create(b, 1.0, 0.7, pbc, hs, qk.QK_MATFREE_ROWS)
+    yr = to_host(qk.qk_ham_apply(Hr, xd))
+    assert max_rel(y, yr) < TOL[dtype] * 4

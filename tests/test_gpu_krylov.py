@@ -309,3 +309,34 @@ def test_local_reorthogonalisation(L):
         Hd = OH.build_dense(L, L // 2, True, 1.0, 1.0, hf)
         F = OX.survival_probability(Hd, r0, 0.1 * np.arange(1, 21))
         assert np.max(np.abs(out[(torch.complex128, 1)] - F)) < 1e-10
+
+
+@pytest.mark.parametrize("dtype", [torch.complex128, torch.complex64])
+def test_blocked_batched_equals_single(dtype):
+    # 8 phases at L=20 (batched blocked H-pass) against each phase alone
+    # (single-phase blocked H-pass); one phase also against expm_multiply
+    from oracle import midsize as OMS
+    L, Bn, steps, dt = 20, 8, 6, 0.1
+    b, Hb, hs = _problem(L, True, h=2.0, Bn=Bn)
+    D = qk.qk_basis_dim(b)
+    r0 = neel_row(L)
+    psib = torch.zeros((D, Bn), dtype=dtype, device="cuda")
+    psib[r0] = 1.0
+    kb = qk.qk_krylov_create(Hb, 30, dtype)
+    say("blocked batched krylov", dtype)
+    for _ in range(steps):
+        qk.qk_krylov_expm_step(kb, psib, dt)
+    Pb = to_host(qk.qk_return_prob(b, psib, r0=r0, batch=Bn))
+    tol = 1e-12 if dtype == torch.complex128 else 2e-5
+    for i in range(Bn):
+        H1 = qk.qk_ham_create(b, 1.0, 1.0, True, hs[i])
+        p1 = torch.zeros(D, dtype=dtype, device="cuda")
+        p1[r0] = 1.0
+        k1 = qk.qk_krylov_create(H1, 30, dtype)
+        for _ in range(steps):
+            qk.qk_krylov_expm_step(k1, p1, dt)
+        assert max_rel(to_host(psib[:, i].contiguous()), to_host(p1)) < tol
+    if dtype == torch.complex128:
+        Hc = OH.build_csr(L, L // 2, True, 1.0, 1.0, hs[3])
+        F = OMS.survival_probability(Hc, r0, [dt * steps])[0]
+        assert abs(Pb[3] - F) < 1e-10
