@@ -273,15 +273,28 @@ k_small_expm(KState st, int m, int B, double tau, const double* __restrict__ par
 // double and rounded once.  The [D][B] arrays are walked as flat elements
 // i = r * B + b; a thread takes the E consecutive elements of one access
 // (E = 2 packs two complex64 values into 16 bytes) and issues the loads of
-// four Krylov vectors before it accumulates them.  Columns whose step failed
-// or had nothing to propagate are left unchanged.
-template <typename T, int E>
+// kCombineUnroll Krylov vectors before it accumulates them.  With one column
+// the coefficients are uniform (scalar loads); with several they are staged
+// in LDS.  Columns whose step failed or had nothing to propagate are left
+// unchanged.
+constexpr int kCombineUnroll = 8;
+
+template <typename T, int E, bool ONE>
 __global__ void __launch_bounds__(kMaxBlock)
 k_combine(typename Cx<T>::V* __restrict__ psi, const typename Cx<T>::V* __restrict__ U, uint32_t D, int B, int m,
           KState st) {
   using V = typename Cx<T>::V;
   struct alignas(sizeof(V) * E) Pack {
     V v[E];
+  };
+  extern __shared__ double2 cf[];   // [m][B] coefficients when B > 1
+  if (!ONE) {
+    for (int i = threadIdx.x; i < m * B; i += blockDim.x) cf[i] = make_double2(st.gre[i], st.gim[i]);
+    __syncthreads();
+  }
+  auto coef = [&](int j, int b) -> double2 {
+    if (ONE) return make_double2(st.gre[j], st.gim[j]);
+    return cf[j * B + b];
   };
   const uint64_t np = (uint64_t)D * B / E;   // packs per vector (the launcher makes D * B a multiple of E)
   const Pack* Up = reinterpret_cast<const Pack*>(U);
@@ -292,7 +305,7 @@ k_combine(typename Cx<T>::V* __restrict__ psi, const typename Cx<T>::V* __restri
     int mumax = 0;
 #pragma unroll
     for (int e = 0; e < E; ++e) {
-      bc[e] = (int)((p * E + e) % (uint64_t)B);
+      bc[e] = ONE ? 0 : (int)((p * E + e) % (uint64_t)B);
       mu[e] = st.mused[bc[e]];
       ok[e] = st.status[bc[e]] == QK_OK && mu[e] > 0;
       if (ok[e] && mu[e] > mumax) mumax = mu[e];
@@ -301,23 +314,23 @@ k_combine(typename Cx<T>::V* __restrict__ psi, const typename Cx<T>::V* __restri
     double ar[E], ai[E];
 #pragma unroll
     for (int e = 0; e < E; ++e) {
-      const double gr = st.gre[bc[e]], gi = st.gim[bc[e]];
-      ar[e] = gr * (double)p0.v[e].x - gi * (double)p0.v[e].y;
-      ai[e] = gr * (double)p0.v[e].y + gi * (double)p0.v[e].x;
+      const double2 g = coef(0, bc[e]);
+      ar[e] = g.x * (double)p0.v[e].x - g.y * (double)p0.v[e].y;
+      ai[e] = g.x * (double)p0.v[e].y + g.y * (double)p0.v[e].x;
     }
     int jj = 1;
-    for (; jj + 3 < mumax; jj += 4) {
-      Pack u[4];
+    for (; jj + kCombineUnroll - 1 < mumax; jj += kCombineUnroll) {
+      Pack u[kCombineUnroll];
 #pragma unroll
-      for (int k = 0; k < 4; ++k) u[k] = Up[(uint64_t)(jj - 1 + k) * np + p];
+      for (int k = 0; k < kCombineUnroll; ++k) u[k] = Up[(uint64_t)(jj - 1 + k) * np + p];
 #pragma unroll
-      for (int k = 0; k < 4; ++k)
+      for (int k = 0; k < kCombineUnroll; ++k)
 #pragma unroll
         for (int e = 0; e < E; ++e) {
-          if (jj + k < mu[e]) {
-            const double gr = st.gre[(jj + k) * B + bc[e]], gi = st.gim[(jj + k) * B + bc[e]];
-            ar[e] += gr * (double)u[k].v[e].x - gi * (double)u[k].v[e].y;
-            ai[e] += gr * (double)u[k].v[e].y + gi * (double)u[k].v[e].x;
+          if (ONE || jj + k < mu[e]) {
+            const double2 g = coef(jj + k, bc[e]);
+            ar[e] += g.x * (double)u[k].v[e].x - g.y * (double)u[k].v[e].y;
+            ai[e] += g.x * (double)u[k].v[e].y + g.y * (double)u[k].v[e].x;
           }
         }
     }
@@ -325,10 +338,10 @@ k_combine(typename Cx<T>::V* __restrict__ psi, const typename Cx<T>::V* __restri
       const Pack u = Up[(uint64_t)(jj - 1) * np + p];
 #pragma unroll
       for (int e = 0; e < E; ++e) {
-        if (jj < mu[e]) {
-          const double gr = st.gre[jj * B + bc[e]], gi = st.gim[jj * B + bc[e]];
-          ar[e] += gr * (double)u.v[e].x - gi * (double)u.v[e].y;
-          ai[e] += gr * (double)u.v[e].y + gi * (double)u.v[e].x;
+        if (ONE || jj < mu[e]) {
+          const double2 g = coef(jj, bc[e]);
+          ar[e] += g.x * (double)u.v[e].x - g.y * (double)u.v[e].y;
+          ai[e] += g.x * (double)u.v[e].y + g.y * (double)u.v[e].x;
         }
       }
     }
@@ -624,10 +637,18 @@ static qk_status krylov_step_t(qk_krylov* k, void* psi_v, double dt, hipStream_t
   // both base addresses allow it
   const bool pack2 = sizeof(V) == 8 && ((uint64_t)D * B) % 2 == 0 && ((uintptr_t)psi % 16) == 0 &&
                      ((uintptr_t)U % 16) == 0;
-  if (pack2)
-    hipLaunchKernelGGL((k_combine<T, 2>), dim3(G), dim3(threads), 0, s, psi, U, D, B, m, st);
-  else
-    hipLaunchKernelGGL((k_combine<T, 1>), dim3(G), dim3(threads), 0, s, psi, U, D, B, m, st);
+  const size_t cfb = B > 1 ? sizeof(double2) * (size_t)m * B : 0;
+  if (B == 1) {
+    if (pack2)
+      hipLaunchKernelGGL((k_combine<T, 2, true>), dim3(G), dim3(threads), 0, s, psi, U, D, B, m, st);
+    else
+      hipLaunchKernelGGL((k_combine<T, 1, true>), dim3(G), dim3(threads), 0, s, psi, U, D, B, m, st);
+  } else {
+    if (pack2)
+      hipLaunchKernelGGL((k_combine<T, 2, false>), dim3(G), dim3(threads), cfb, s, psi, U, D, B, m, st);
+    else
+      hipLaunchKernelGGL((k_combine<T, 1, false>), dim3(G), dim3(threads), cfb, s, psi, U, D, B, m, st);
+  }
   QK_HIP(hipGetLastError());
   QK_MARK(QK_KERNEL_COMBINE, false);
 #undef QK_MARK
