@@ -11,7 +11,9 @@ survival probability.  Inputs are synthetic and resident in HBM before the
 timed region starts.
 
 Forms: plain complex128 (the headline `value`), complex64 storage, and a
-batch of 8 phases in complex64 ([D][8] layout).  Also reported: standalone
+batch of 8 phases in complex64 ([D][8] layout); `adaptive` runs the same
+complex128 chain to t = 2 with error-controlled steps (tolerance 1e-7 per unit
+time, the paper's setting) and reports its step count and wall time.  Also reported: standalone
 y = H x throughput (algorithmic bytes 2 s D per call), a device-copy ceiling,
 the roofline of the dominant kernel from HIP events recorded on the step's
 stream, and the CPU oracle timed on a bounded sample of the same workload.
@@ -51,7 +53,9 @@ def parse():
     ap.add_argument("--dt", type=float, default=0.1)
     ap.add_argument("--h", type=float, default=1.5)
     ap.add_argument("--batch", type=int, default=8)
-    ap.add_argument("--forms", default="fp64,fp32,batched")
+    ap.add_argument("--forms", default="fp64,fp32,batched,adaptive")
+    ap.add_argument("--adaptive-t", type=float, default=2.0)
+    ap.add_argument("--adaptive-tol", type=float, default=1e-7)
     ap.add_argument("--hv-reps", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU time of the oracle sample")
@@ -106,6 +110,30 @@ def run_form(qk, torch, b, fields, m, dt, dtype, steps, warmup, r0):
     torch.cuda.synchronize()
     torch.cuda.empty_cache()
     return out
+
+
+def run_adaptive(qk, torch, b, fields, m, r0, t_end, tol):
+    """Adaptive stepping with error control from the Neel state to t_end
+    (complex128), timed; also the same interval in fixed steps of 0.1."""
+    D = qk.qk_basis_dim(b)
+    H = qk.qk_ham_create(b, 1.0, 1.0, True, fields)
+    k = qk.qk_krylov_create(H, m, torch.complex128)
+    psi = torch.zeros(D, dtype=torch.complex128, device="cuda")
+    psi[r0] = 1.0
+    qk.qk_krylov_evolve(k, psi, 0.1, tol, dt_init=0.1)   # warm-up
+    psi.zero_()
+    psi[r0] = 1.0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    info = qk.qk_krylov_evolve(k, psi, t_end, tol, dt_init=0.1)
+    torch.cuda.synchronize()
+    sec = time.perf_counter() - t0
+    P = abs(psi[r0].item()) ** 2
+    del k, H, psi
+    torch.cuda.empty_cache()
+    return dict(t_end=t_end, tol=tol, m=m, sec=round(sec, 4), steps=info["steps"], dt_min=info["dt_min"],
+                dt_max=info["dt_max"], err_est_sum=info["err_sum"], P_end=P,
+                time_units_per_s=round(t_end / sec, 3))
 
 
 def hv_throughput(qk, torch, b, fields, dtype, reps):
@@ -214,6 +242,7 @@ def main():
 
     res = {}
     hv = {}
+    adaptive = None
     log("H*x throughput")
     hv["fp64"] = hv_throughput(qk, torch, b, fields1, torch.complex128, args.hv_reps)
     hv["fp32"] = hv_throughput(qk, torch, b, fields1, torch.complex64, args.hv_reps)
@@ -226,9 +255,13 @@ def main():
         elif f == "batched":
             fb = qk.qk_fields_quasiperiodic(L, args.h, BETA_GOLDEN, phases(args.batch, 0))
             res[f] = run_form(qk, torch, b, fb, m, dt, torch.complex64, args.steps, args.warmup, r0)
+        elif f == "adaptive":
+            adaptive = run_adaptive(qk, torch, b, fields1, m, r0, args.adaptive_t, args.adaptive_tol)
         else:
             raise SystemExit(f"unknown form {f}")
 
+    if not res:
+        raise SystemExit("at least one of the forms fp64, fp32, batched is needed")
     head = res.get("fp64") or next(iter(res.values()))
     steps = args.steps
     value = steps / head["sec"]
@@ -286,6 +319,8 @@ def main():
         B = args.batch if f == "batched" else 1
         s = 16 if f == "fp64" else 8
         out["forms"][f] = form_summary(r, B, s)
+    if adaptive is not None:
+        out["adaptive"] = adaptive
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         cb = cpu_baseline(L, m, fields1[0], True, args.cpu_seconds)

@@ -189,6 +189,36 @@ qk_status qk_krylov_create(const qk_ham* H, int32_t m, int32_t dtype, int32_t re
 qk_status qk_krylov_expm_step(qk_krylov* k, void* psi, double dt, void* stream, qk_step_info* info_host);
 
 /*
+ * Adaptive evolution psi <- exp(-i t H) psi with error control, as in the
+ * paper's runs (Sec. 4-5 use Expokit / SLEPc's Krylov exponential with a
+ * tolerance): each step builds the Krylov basis once, then the device picks
+ * the longest step tau <= min(dt_try, dt_max, time left) whose a-posteriori
+ * estimate ||psi|| beta_m |[exp(-i tau T_m)]_{m,1}| is at most 1.2 tau tol,
+ * shrinking tau by Expokit's rule 0.9 tau (tau tol / err)^(1/(m-1)) on the
+ * small tridiagonal only, and proposes the next dt_try by the same rule
+ * (at most 10 tau).  tol is an error per unit time: the summed estimates stay
+ * below about tol * t.  All batch items advance by the smallest accepted
+ * step.  t >= 0; tol > 0; dt_init > 0 (first trial step); dt_max > 0;
+ * max_steps >= 1 bounds the accepted steps (QK_ENUMERIC with a message when
+ * t is not reached).  Synchronous (one small read-back per step).  info_host
+ * (may be NULL) receives the number of steps, the smallest and largest
+ * accepted step and the sum of the error estimates of batch item 0.
+ */
+typedef struct {
+  double tol;
+  double dt_init;
+  double dt_max;
+  int32_t max_steps;
+} qk_adapt_params;
+typedef struct {
+  int32_t steps;
+  double dt_min, dt_max;
+  double err_sum;
+} qk_adapt_info;
+qk_status qk_krylov_evolve(qk_krylov* k, void* psi, double t, const qk_adapt_params* p, void* stream,
+                           qk_adapt_info* info_host);
+
+/*
  * Lanczos coefficients of the last completed step for batch item `item`
  * (synchronous): alpha[0..m_used-1], beta[0..m_used-1] (beta[j] = norm of
  * the (j+1)-th residual), *m_used.  Arrays hold at least m entries.

@@ -14,7 +14,7 @@ import numpy as np
 import torch
 
 from . import _native
-from ._native import HamParams, KernelTime, LaunchShape, StepInfo, lib
+from ._native import AdaptInfo, AdaptParams, HamParams, KernelTime, LaunchShape, StepInfo, lib
 
 QK_OK, QK_EINVAL, QK_ENOMEM, QK_EHIP, QK_EUNSUPPORTED, QK_ENUMERIC = range(6)
 QK_C128, QK_C64 = 0, 1
@@ -212,6 +212,21 @@ def qk_krylov_expm_step(k: Krylov, psi: torch.Tensor, dt: float, stream=None, in
     if st not in (QK_OK, QK_ENUMERIC):
         _check(st, "qk_krylov_expm_step")
     return res
+
+
+def qk_krylov_evolve(k: Krylov, psi: torch.Tensor, t: float, tol: float, dt_init: float = 0.1,
+                     dt_max: float = 1e30, max_steps: int = 1000000, stream=None) -> dict:
+    """psi <- exp(-i t H) psi in place by adaptive Krylov steps with error
+    control (tol per unit time).  Returns steps, dt_min, dt_max, err_sum."""
+    D, Bn, _ = qk_ham_shape(k.H)
+    _check_vec(D, psi, Bn, "psi")
+    if dtype_code(psi) != k.dtype:
+        raise ValueError("psi dtype differs from the workspace dtype")
+    prm = AdaptParams(float(tol), float(dt_init), float(dt_max), int(max_steps))
+    inf = AdaptInfo()
+    _check(lib.qk_krylov_evolve(k.ptr, _dptr(psi), float(t), C.byref(prm), _stream(stream), C.byref(inf)),
+           "qk_krylov_evolve")
+    return dict(steps=inf.steps, dt_min=inf.dt_min, dt_max=inf.dt_max, err_sum=inf.err_sum)
 
 
 def qk_krylov_coefficients(k: Krylov, item: int = 0):

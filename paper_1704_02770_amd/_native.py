@@ -36,6 +36,14 @@ class LaunchShape(C.Structure):
     _fields_ = [("threads", i32), ("blocks_per_cu", i32), ("blocked_wgs_per_cu", i32)]
 
 
+class AdaptParams(C.Structure):
+    _fields_ = [("tol", C.c_double), ("dt_init", C.c_double), ("dt_max", C.c_double), ("max_steps", C.c_int32)]
+
+
+class AdaptInfo(C.Structure):
+    _fields_ = [("steps", C.c_int32), ("dt_min", C.c_double), ("dt_max", C.c_double), ("err_sum", C.c_double)]
+
+
 class StepInfo(C.Structure):
     _fields_ = [("m_used", i32), ("status", i32), ("err_est", f64), ("beta0", f64)]
 
@@ -58,6 +66,7 @@ SIGNATURES = {
     "qk_ham_destroy": (None, [vp]),
     "qk_krylov_create": (i32, [vp, i32, i32, i32, P(vp)]),
     "qk_krylov_expm_step": (i32, [vp, vp, f64, vp, P(StepInfo)]),
+    "qk_krylov_evolve": (i32, [vp, vp, f64, P(AdaptParams), vp, P(AdaptInfo)]),
     "qk_krylov_coefficients": (i32, [vp, i32, P(f64), P(f64), P(i32)]),
     "qk_krylov_destroy": (None, [vp]),
     "qk_krylov_profile": (i32, [vp, i32]),

@@ -2,6 +2,7 @@
 // reporting around the launchers in qk_kernels.hip.  Every entry point
 // validates its arguments before touching the device and converts HIP
 // failures into QK_EHIP with the runtime's message in qk_last_error().
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -349,6 +350,71 @@ QK_API qk_status qk_krylov_expm_step(qk_krylov* k, void* psi, double dt, void* s
   }
   if (worst != QK_OK) set_error("non-finite Lanczos coefficient");
   return worst;
+}
+
+QK_API qk_status qk_krylov_evolve(qk_krylov* k, void* psi, double t, const qk_adapt_params* p, void* stream,
+                                  qk_adapt_info* info) {
+  g_err.clear();
+  if (!k || !psi || !p) return inval("NULL pointer");
+  if (!std::isfinite(t) || t < 0.0) return inval("t must be finite and >= 0");
+  if (!(p->tol > 0.0) || !std::isfinite(p->tol)) return inval("tol must be finite and > 0");
+  if (!(p->dt_init > 0.0) || !std::isfinite(p->dt_init)) return inval("dt_init must be finite and > 0");
+  if (!(p->dt_max > 0.0) || !std::isfinite(p->dt_max)) return inval("dt_max must be finite and > 0");
+  if (p->max_steps < 1) return inval("max_steps must be >= 1");
+  if ((uintptr_t)psi % elem_bytes(k->dtype)) return inval("misaligned psi");
+  qk_status st = check_device(k->device);
+  if (st != QK_OK) return st;
+  const size_t vec = elem_bytes(k->dtype) * (size_t)k->D * k->batch;
+  if (ranges_overlap(psi, vec, k->d_U, vec * (size_t)k->m)) return inval("psi overlaps the Krylov workspace");
+  hipStream_t s = (hipStream_t)stream;
+  const int B = k->batch;
+  const KState ks = make_kstate(k);
+  std::vector<double> tau(2 * B);
+  std::vector<int32_t> iv(2 * B);
+  double done = 0.0, dt_try = p->dt_init, err_sum = 0.0, dmin = INFINITY, dmax = 0.0;
+  int steps = 0;
+  while (t - done > 1e-14 * t) {
+    if (steps >= p->max_steps) {
+      set_error("adaptive evolution did not reach t within max_steps");
+      return QK_ENUMERIC;
+    }
+    double tau_max = std::min(std::min(dt_try, p->dt_max), t - done);
+    st = launch_krylov_adaptive_step(k, psi, tau_max, p->tol, s);
+    if (st != QK_OK) return st;
+    QK_HIP(hipMemcpyAsync(tau.data(), ks.tau, sizeof(double) * 2 * B, hipMemcpyDeviceToHost, s));
+    QK_HIP(hipMemcpyAsync(iv.data(), k->d_int, sizeof(int32_t) * 2 * B, hipMemcpyDeviceToHost, s));
+    double e0 = 0.0;
+    QK_HIP(hipMemcpyAsync(&e0, ks.err, sizeof(double), hipMemcpyDeviceToHost, s));
+    QK_HIP(hipStreamSynchronize(s));
+    for (int b = 0; b < B; ++b)
+      if (iv[B + b] != QK_OK) {
+        set_error("non-finite Lanczos coefficient");
+        return QK_ENUMERIC;
+      }
+    double acc = tau[0], nxt = tau[B];
+    for (int b = 1; b < B; ++b) {
+      acc = std::min(acc, tau[b]);
+      nxt = std::min(nxt, tau[B + b]);
+    }
+    if (!(acc > 0.0)) {
+      set_error("adaptive step collapsed to zero");
+      return QK_ENUMERIC;
+    }
+    // the last step lands exactly on t
+    done = (acc >= t - done) ? t : done + acc;
+    ++steps;
+    err_sum += e0;
+    dmin = std::min(dmin, acc);
+    dmax = std::max(dmax, acc);
+    dt_try = nxt > 0.0 ? nxt : acc;
+  }
+  if (info) {
+    info->steps = steps;
+    info->dt_min = steps ? dmin : 0.0;
+    info->dt_max = dmax;
+    info->err_sum = err_sum;
+  }
+  return QK_OK;
 }
 
 QK_API qk_status qk_krylov_coefficients(const qk_krylov* k, int32_t item, double* alpha, double* beta,

@@ -104,9 +104,10 @@ struct KState {
   double* err;     // [B]
   int32_t* mused;  // [B]
   int32_t* status; // [B]
+  double* tau;     // [2][B]      adaptive steps: accepted step, suggested next step
 };
 
-inline size_t kstate_doubles(int m, int B) { return (size_t)B * (5 * m + 1 + 2 + 1); }
+inline size_t kstate_doubles(int m, int B) { return (size_t)B * (5 * m + 1 + 2 + 1 + 2); }
 KState make_kstate(const qk_krylov* k);
 
 // Model arguments of the matrix-free rows.
@@ -129,6 +130,10 @@ qk_status launch_blocked_apply(const qk_ham* H, const void* x, void* y, int dtyp
 qk_status launch_blocked_fields(qk_ham* H, hipStream_t s);
 bool blocked_usable(const qk_ham* H, int dtype);
 qk_status launch_krylov_step(qk_krylov* k, void* psi, double dt, hipStream_t s, bool combine = true);
+// One step of at most tau_max whose length the device chooses from the error
+// estimate: st.tau[b] receives the accepted step of column b, st.tau[B + b] a
+// suggested next step; every column advances by the smallest accepted step.
+qk_status launch_krylov_adaptive_step(qk_krylov* k, void* psi, double tau_max, double tol, hipStream_t s);
 qk_status grad_return_prob(qk_krylov* k, int64_t r0, double T, int n_steps, double* F, double* dFdh, hipStream_t s);
 qk_status profile_mark(qk_krylov* k, int kind, bool begin, hipStream_t s);
 int stream_grid(uint64_t rows, int B, int threads, int blocks_per_cu);

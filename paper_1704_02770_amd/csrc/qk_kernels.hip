@@ -224,15 +224,11 @@ k_lanczos_B(const typename Cx<T>::V* __restrict__ uj, const typename Cx<T>::V* _
 }
 
 // ------------------------------------------ projected exponential (1 wave)
-// c = exp(-i tau T) e_1 for the tridiagonal T of the Lanczos recurrence
-// (tri_expm_e1), times ||psi|| and the stored-vector scales, plus the
-// a-posteriori error estimate ||psi|| beta_m |c_m|.
-__global__ void __launch_bounds__(64)
-k_small_expm(KState st, int m, int B, double tau, const double* __restrict__ partB, int Gp) {
-  const int b = blockIdx.x;
+// ||u_m|| of the last update pass (the norm of the residual after m steps;
+// only meaningful when the recurrence ran all m steps), reduced by one wave.
+__device__ __forceinline__ double last_residual_norm(const double* __restrict__ partB, int Gp, int B, int b,
+                                                     double* red) {
   const int i = threadIdx.x;
-  __shared__ double red[64];
-  // ||u_m||^2 of the last pass (only meaningful when the recurrence ran m steps)
   double acc = 0.0;
   for (int g = i; g < Gp; g += 64) acc += partB[(size_t)g * B + b];
   red[i] = acc;
@@ -241,7 +237,40 @@ k_small_expm(KState st, int m, int B, double tau, const double* __restrict__ par
     if (i < s) red[i] += red[i + s];
     __syncthreads();
   }
-  const double beta_last = sqrt(red[0]);
+  return sqrt(red[0]);
+}
+
+// Tridiagonal entries of column b seen by lane i (zero outside m_used).
+struct TriLane {
+  double al, be, bl;
+  bool on;
+};
+__device__ __forceinline__ TriLane tri_lane(const KState& st, int B, int b, int mu) {
+  const int i = threadIdx.x;
+  TriLane t;
+  t.on = i < mu;
+  t.al = t.on ? st.alpha[i * B + b] : 0.0;
+  t.be = (i + 1 < mu) ? st.beta[i * B + b] : 0.0;     // couples i and i+1
+  t.bl = (t.on && i > 0) ? st.beta[(i - 1) * B + b] : 0.0;
+  return t;
+}
+
+// c = exp(-i tau T) e_1 for the tridiagonal T of the Lanczos recurrence
+// (tri_expm_e1), times ||psi|| and the stored-vector scales, plus the
+// a-posteriori error estimate ||psi|| beta_m |c_m|.  With tau_dev != NULL the
+// step is the smallest of tau_dev[0..B) (the accepted steps of an adaptive
+// step, so that all columns stay at the same time).
+__global__ void __launch_bounds__(64)
+k_small_expm(KState st, int m, int B, double tau, const double* __restrict__ tau_dev, const double* __restrict__ partB,
+             int Gp) {
+  const int b = blockIdx.x;
+  const int i = threadIdx.x;
+  __shared__ double red[64];
+  const double beta_last = last_residual_norm(partB, Gp, B, b, red);
+  if (tau_dev) {
+    tau = tau_dev[0];
+    for (int c = 1; c < B; ++c) tau = fmin(tau, tau_dev[c]);
+  }
   const int mu = st.mused[b];
   if (st.status[b] != QK_OK || mu <= 0) {
     if (i < m) {
@@ -252,20 +281,58 @@ k_small_expm(KState st, int m, int B, double tau, const double* __restrict__ par
     return;
   }
   if (mu == m && i == 0) st.beta[(m - 1) * B + b] = beta_last;
-  const bool on = i < mu;
-  const double al = on ? st.alpha[i * B + b] : 0.0;
-  const double be = (i + 1 < mu) ? st.beta[i * B + b] : 0.0;     // couples i and i+1
-  const double bl = (on && i > 0) ? st.beta[(i - 1) * B + b] : 0.0;
+  const TriLane t = tri_lane(st, B, b, mu);
   double er, ei;
-  tri_expm_e1(al, be, bl, on, i, tau, er, ei);
+  tri_expm_e1(t.al, t.be, t.bl, t.on, i, tau, er, ei);
   const double n0 = st.n0[b];
   if (i < m) {
-    const double g = on ? n0 * st.sigma[i * B + b] : 0.0;
+    const double g = t.on ? n0 * st.sigma[i * B + b] : 0.0;
     st.gre[i * B + b] = g * er;
     st.gim[i * B + b] = g * ei;
   }
   const double last = __shfl(sqrt(er * er + ei * ei), mu - 1);
   if (i == 0) st.err[b] = (mu == m) ? n0 * beta_last * last : 0.0;
+}
+
+// Step-size control of one adaptive step (the rule of Expokit, which the
+// paper's runs use through SLEPc): starting from tau_max, the step tau of
+// column b is accepted when the estimate err(tau) = ||psi|| beta_m
+// |[exp(-i tau T)]_{m,1}| is at most 1.2 tau tol, and otherwise replaced by
+// 0.9 tau (tau tol / err)^(1 / (m - 1)), kept within [tau / 10, 0.9 tau].  The
+// Krylov basis does not depend on tau, so only the small exponential is
+// recomputed.  A recurrence that stopped early spans an invariant subspace
+// and accepts tau_max.  st.tau[b] = accepted step, st.tau[B + b] = suggested
+// next step (0.9 tau (tau tol / err)^(1/(m-1)), at most 10 tau).
+__global__ void __launch_bounds__(64)
+k_step_size(KState st, int m, int B, double tau_max, double tol, const double* __restrict__ partB, int Gp) {
+  const int b = blockIdx.x;
+  const int i = threadIdx.x;
+  __shared__ double red[64];
+  const double beta_last = last_residual_norm(partB, Gp, B, b, red);
+  const int mu = st.mused[b];
+  double tau = tau_max, next = tau_max;
+  if (st.status[b] == QK_OK && mu == m && m > 1) {
+    const TriLane t = tri_lane(st, B, b, mu);
+    const double n0 = st.n0[b];
+    const double xm = 1.0 / (double)(m - 1);
+    double err = 0.0;
+    for (int it = 0; it < 60; ++it) {
+      double er, ei;
+      tri_expm_e1(t.al, t.be, t.bl, t.on, i, tau, er, ei);
+      err = n0 * beta_last * __shfl(sqrt(er * er + ei * ei), mu - 1);
+      if (err <= 1.2 * tau * tol) break;
+      double nt = 0.9 * tau * pow(tau * tol / err, xm);
+      if (!(nt >= 0.1 * tau)) nt = 0.1 * tau;   // also catches a NaN estimate
+      if (nt > 0.9 * tau) nt = 0.9 * tau;
+      tau = nt;
+    }
+    next = (err > 0.0) ? 0.9 * tau * pow(tau * tol / err, xm) : 10.0 * tau;
+    if (!(next <= 10.0 * tau)) next = 10.0 * tau;
+  }
+  if (i == 0) {
+    st.tau[b] = tau;
+    st.tau[B + b] = next;
+  }
 }
 
 // ------------------------------------------------ Krylov combination
@@ -498,6 +565,7 @@ KState make_kstate(const qk_krylov* k) {
   s.err = p + (size_t)(5 * m + 2) * B;
   s.mused = k->d_int;
   s.status = k->d_int + B;
+  s.tau = p + (size_t)(5 * m + 3) * B;
   return s;
 }
 
@@ -580,8 +648,13 @@ qk_status launch_ham_apply(const qk_ham* H, const void* x, void* y, int dtype, h
   return QK_OK;
 }
 
+struct AdaptiveStep {
+  double tau_max, tol;
+};
+
 template <typename T>
-static qk_status krylov_step_t(qk_krylov* k, void* psi_v, double dt, hipStream_t s, bool combine) {
+static qk_status krylov_step_t(qk_krylov* k, void* psi_v, double dt, hipStream_t s, bool combine,
+                               const AdaptiveStep* ad = nullptr) {
   using V = typename Cx<T>::V;
   const qk_ham* H = k->H;
   const ModelArgs a = model_args(H);
@@ -629,7 +702,12 @@ static qk_status krylov_step_t(qk_krylov* k, void* psi_v, double dt, hipStream_t
   }
   if (!combine) return QK_OK;   // only the Krylov basis and coefficients were asked for
   QK_MARK(QK_KERNEL_SMALL_EXPM, true);
-  hipLaunchKernelGGL(k_small_expm, dim3(B), dim3(64), 0, s, st, m, B, dt, k->d_partB, G);
+  if (ad) {
+    hipLaunchKernelGGL(k_step_size, dim3(B), dim3(64), 0, s, st, m, B, ad->tau_max, ad->tol, k->d_partB, G);
+    QK_HIP(hipGetLastError());
+  }
+  hipLaunchKernelGGL(k_small_expm, dim3(B), dim3(64), 0, s, st, m, B, dt, ad ? (const double*)st.tau : nullptr,
+                     k->d_partB, G);
   QK_HIP(hipGetLastError());
   QK_MARK(QK_KERNEL_SMALL_EXPM, false);
   QK_MARK(QK_KERNEL_COMBINE, true);
@@ -692,6 +770,12 @@ qk_status profile_collect(qk_krylov* k) {
 qk_status launch_krylov_step(qk_krylov* k, void* psi, double dt, hipStream_t s, bool combine) {
   if (k->dtype == QK_C128) return krylov_step_t<double>(k, psi, dt, s, combine);
   return krylov_step_t<float>(k, psi, dt, s, combine);
+}
+
+qk_status launch_krylov_adaptive_step(qk_krylov* k, void* psi, double tau_max, double tol, hipStream_t s) {
+  const AdaptiveStep ad{tau_max, tol};
+  if (k->dtype == QK_C128) return krylov_step_t<double>(k, psi, tau_max, s, true, &ad);
+  return krylov_step_t<float>(k, psi, tau_max, s, true, &ad);
 }
 
 qk_status launch_return_prob(const qk_basis* b, int64_t r0, const void* psi0, const void* psi, int dtype, int B,
