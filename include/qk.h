@@ -279,9 +279,12 @@ typedef struct qk_batch qk_batch;
 /*
  * Groups n (1..64) distinct workspaces -- any chain lengths, field-set counts
  * and Krylov dimensions, one dtype each -- with their state vectors psi[i]
- * (device, [D_i][B_i], updated in place) and the basis rows r0[i] of their
- * initial basis states, so that they advance together.  The handles and
- * vectors must outlive the batch.
+ * (device, [D_i][B_i], updated in place), so that they advance together.
+ * r0[i] >= 0: the items start from the basis state of row r0[i] and their
+ * survival probability is |psi[r0]|^2; r0[i] < 0: any initial vectors (for
+ * instance the random initial states of Sec. 4's disorder averages) -- the
+ * batch copies psi[i] as given now and records |<psi0, psi>|^2.  The handles
+ * and vectors must outlive the batch.  Synchronous.
  */
 qk_status qk_batch_create(qk_krylov* const* ks, void* const* psi, const int64_t* r0, int32_t n, qk_batch** out);
 
@@ -298,6 +301,17 @@ qk_status qk_batch_items(const qk_batch* b, int32_t* items);
  * directly.  Asynchronous.
  */
 qk_status qk_batch_run(qk_batch* b, double dt, int32_t n_steps, int32_t use_graph, double* P_device, void* stream);
+
+/*
+ * qk_batch_run that also writes the temporal autocorrelation of Sec. 4,
+ * C(t) = (1/t) integral_0^t P(t') dt', of every item after step k to
+ * C_device[k * items + offset_i + item] (C_device may be NULL).  The integral
+ * runs from the creation of the batch over every step taken since (in either
+ * entry point), by the trapezoid rule on the step grid; t is the total time
+ * stepped.  Asynchronous.
+ */
+qk_status qk_batch_run_autocorr(qk_batch* b, double dt, int32_t n_steps, int32_t use_graph, double* P_device,
+                                double* C_device, void* stream);
 
 void qk_batch_destroy(qk_batch* b);
 

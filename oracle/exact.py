@@ -61,3 +61,22 @@ def autocorrelation(times: np.ndarray, F: np.ndarray) -> np.ndarray:
     out[0] = F[0]
     out[1:] = integ[1:] / times[1:]
     return out
+
+
+def autocorrelation_exact(H: np.ndarray, psi0: np.ndarray, times, eigsys=None) -> np.ndarray:
+    """C(t) = (1/t) * integral_0^t |<psi0| exp(-iHt') |psi0>|^2 dt' (Sec. 4) in
+    closed form.  With w_n = |<n|psi0>|^2 over the eigenvectors of H,
+    |A(t')|^2 = sum_{n,m} w_n w_m exp(-i (E_n - E_m) t'), whose time average
+    over [0, t] is sum_{n,m} w_n w_m sin((E_n - E_m) t) / ((E_n - E_m) t)
+    (the imaginary parts cancel between (n, m) and (m, n)); the limit t -> 0
+    is (sum_n w_n)^2."""
+    w, U = eig(H) if eigsys is None else eigsys
+    c = U.T @ np.asarray(psi0, dtype=np.complex128)
+    wn = np.abs(c) ** 2
+    times = np.atleast_1d(np.asarray(times, dtype=np.float64))
+    dE = w[:, None] - w[None, :]
+    out = np.empty(len(times))
+    for k, t in enumerate(times):
+        # np.sinc(x) = sin(pi x) / (pi x)
+        out[k] = float(wn @ np.sinc(dE * t / np.pi) @ wn)
+    return out

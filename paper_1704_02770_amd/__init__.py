@@ -280,7 +280,8 @@ def qk_krylov_autotune(k: Krylov, dt: float, cache_path: str | None = None, stre
 
 
 def qk_batch_create(ks, psis, r0s) -> Batch:
-    """Groups workspaces with their state vectors and initial basis rows."""
+    """Groups workspaces with their state vectors and initial basis rows
+    (r0 < 0: the vector as given is the initial state; its overlap is recorded)."""
     n = len(ks)
     if not (len(psis) == len(r0s) == n):
         raise ValueError("ks, psis and r0s must have the same length")
@@ -314,6 +315,23 @@ def qk_batch_run(b: Batch, dt: float, n_steps: int, use_graph: bool = True, out:
     _check(lib.qk_batch_run(b.ptr, float(dt), int(n_steps), int(bool(use_graph)), _dptr(out), _stream(stream)),
            "qk_batch_run")
     return out
+
+
+def qk_batch_run_autocorr(b: Batch, dt: float, n_steps: int, use_graph: bool = True, out: torch.Tensor | None = None,
+                          out_c: torch.Tensor | None = None, stream=None):
+    """As qk_batch_run, plus the temporal autocorrelation C(t) of every item
+    after every step; returns the device tensors (P, C), each [n_steps, items]."""
+    items = qk_batch_items(b)
+    if out is None:
+        out = torch.empty((n_steps, items), dtype=torch.float64, device="cuda")
+    if out_c is None:
+        out_c = torch.empty((n_steps, items), dtype=torch.float64, device="cuda")
+    for t in (out, out_c):
+        if t.numel() < n_steps * items or t.dtype != torch.float64:
+            raise ValueError("out and out_c must be float64 tensors of n_steps * items entries")
+    _check(lib.qk_batch_run_autocorr(b.ptr, float(dt), int(n_steps), int(bool(use_graph)), _dptr(out), _dptr(out_c),
+                                     _stream(stream)), "qk_batch_run_autocorr")
+    return out, out_c
 
 
 def qk_grad_return_prob(k: Krylov, r0: int, T: float, n_steps: int, stream=None):

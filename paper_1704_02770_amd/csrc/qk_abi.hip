@@ -525,7 +525,7 @@ QK_API qk_status qk_batch_create(qk_krylov* const* ks, void* const* psi, const i
   for (int i = 0; i < n; ++i) {
     if (!ks[i] || !psi[i]) return inval("NULL workspace or vector");
     if (ks[i]->device != ks[0]->device) return inval("workspaces on different devices");
-    if (r0[i] < 0 || r0[i] >= ks[i]->D) return inval("r0 out of range");
+    if (r0[i] >= ks[i]->D) return inval("r0 out of range");
     if ((uintptr_t)psi[i] % elem_bytes(ks[i]->dtype)) return inval("misaligned psi");
     const size_t vec = elem_bytes(ks[i]->dtype) * (size_t)ks[i]->D * ks[i]->batch;
     for (int j = 0; j < n; ++j) {
@@ -547,8 +547,8 @@ QK_API qk_status qk_batch_items(const qk_batch* b, int32_t* items) {
   return QK_OK;
 }
 
-QK_API qk_status qk_batch_run(qk_batch* b, double dt, int32_t n_steps, int32_t use_graph, double* P_device,
-                              void* stream) {
+QK_API qk_status qk_batch_run_autocorr(qk_batch* b, double dt, int32_t n_steps, int32_t use_graph, double* P_device,
+                                       double* C_device, void* stream) {
   g_err.clear();
   if (!b || !P_device) return inval("NULL pointer");
   if (!std::isfinite(dt)) return inval("dt not finite");
@@ -557,7 +557,12 @@ QK_API qk_status qk_batch_run(qk_batch* b, double dt, int32_t n_steps, int32_t u
   qk_status st = check_device(batch_device(b));
   if (st != QK_OK) return st;
   if (n_steps == 0) return QK_OK;
-  return batch_run(b, dt, n_steps, use_graph, P_device, (hipStream_t)stream);
+  return batch_run(b, dt, n_steps, use_graph, P_device, C_device, (hipStream_t)stream);
+}
+
+QK_API qk_status qk_batch_run(qk_batch* b, double dt, int32_t n_steps, int32_t use_graph, double* P_device,
+                              void* stream) {
+  return qk_batch_run_autocorr(b, dt, n_steps, use_graph, P_device, nullptr, stream);
 }
 
 QK_API void qk_batch_destroy(qk_batch* b) { batch_destroy(b); }

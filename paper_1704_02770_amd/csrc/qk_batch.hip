@@ -12,6 +12,12 @@
 // joined back into the caller's stream -- and replayed for every step, with
 // the survival probability of every batch item recorded on the device at a
 // device-side step counter.  No host round trip and one graph launch per step.
+//
+// Items start from a basis state (probability |psi[r0]|^2) or from any state
+// (r0 < 0: the driver keeps a copy psi0 of the vector given at creation and
+// records |<psi0, psi>|^2).  Every step also advances the temporal
+// autocorrelation C(t) = (1/t) integral_0^t P(t') dt' of Sec. 4 by the
+// trapezoid rule on the step grid, from the creation of the batch on.
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -38,6 +44,28 @@ __global__ void k_record(const typename Cx<T>::V* __restrict__ psi, uint32_t r0,
 
 __global__ void k_counter(int* counter, int reset) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *counter = reset ? 0 : *counter + 1;
+}
+
+// Trapezoid step of the autocorrelation integral for every item: S += dt/2
+// (P_prev + P_now), P_prev = P_now, t += dt, C = S / t (written when C is
+// not NULL).  One block; `state` = [S(items), P_prev(items), t].
+__global__ void __launch_bounds__(256)
+k_autocorr(const double* __restrict__ P, const int* __restrict__ counter, int items, double dt, double* state,
+           double* C) {
+  const int c = *counter;
+  double* S = state;
+  double* prev = state + items;
+  double* tp = state + 2 * (size_t)items;
+  const double t = *tp + dt;
+  for (int j = threadIdx.x; j < items; j += blockDim.x) {
+    const double pn = P[(size_t)c * items + j];
+    const double sj = S[j] + 0.5 * dt * (prev[j] + pn);
+    S[j] = sj;
+    prev[j] = pn;
+    if (C) C[(size_t)c * items + j] = (t > 0.0) ? sj / t : pn;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) *tp = t;
 }
 
 // Deterministic pseudo-random complex entries (an integer hash of the index),
@@ -248,6 +276,10 @@ struct qk_batch {
   std::vector<qk_krylov*> ks;
   std::vector<void*> psi;
   std::vector<int64_t> r0;
+  std::vector<void*> psi0;          // copy of the initial vector of items with r0 < 0 (else NULL)
+  std::vector<double*> part;        // overlap partial sums of those items
+  std::vector<int> ogrid;           // their overlap grid
+  double* d_state = nullptr;        // autocorrelation state: S[items], P_prev[items], t
   std::vector<int> item_off;
   int items = 0;
   int device = 0;
@@ -260,11 +292,22 @@ struct qk_batch {
   hipGraphExec_t exec = nullptr;
   double graph_dt = NAN;
   double* graph_P = nullptr;
+  double* graph_C = nullptr;
 };
 
 namespace qk {
 
 int batch_items(const qk_batch* b) { return b->items; }
+
+// Survival probability of workspace i's items at the current step counter:
+// P[(*counter) * items + offset + b].
+static qk_status record_item(qk_batch* b, int i, double* P, hipStream_t s) {
+  const qk_krylov* k = b->ks[i];
+  if (b->r0[i] >= 0)
+    return launch_record(k, b->psi[i], b->r0[i], P, b->d_counter, b->item_off[i], b->items, s);
+  return launch_overlap_record(b->psi0[i], b->psi[i], k->dtype, (uint32_t)k->D, k->batch, b->part[i], b->ogrid[i], P,
+                               b->d_counter, b->item_off[i], b->items, s);
+}
 int batch_device(const qk_batch* b) { return b->device; }
 
 void batch_release(qk_batch* b) {
@@ -288,6 +331,22 @@ qk_status batch_create(qk_krylov* const* ks, void* const* psi, const int64_t* r0
   }
   b->items = off;
   hipError_t e = hipMalloc((void**)&b->d_counter, sizeof(int));
+  if (e == hipSuccess) e = hipMalloc((void**)&b->d_state, sizeof(double) * (2 * (size_t)off + 1));
+  for (int i = 0; i < n; ++i) {
+    void* p0 = nullptr;
+    double* pa = nullptr;
+    int G = 0;
+    if (e == hipSuccess && r0[i] < 0) {
+      const size_t vec = (ks[i]->dtype == QK_C128 ? 16 : 8) * (size_t)ks[i]->D * ks[i]->batch;
+      G = overlap_grid((uint32_t)ks[i]->D, ks[i]->batch);
+      e = hipMalloc(&p0, vec);
+      if (e == hipSuccess) e = hipMalloc((void**)&pa, sizeof(double) * (size_t)G * 2 * ks[i]->batch);
+      if (e == hipSuccess) e = hipMemcpy(p0, psi[i], vec, hipMemcpyDeviceToDevice);
+    }
+    b->psi0.push_back(p0);
+    b->part.push_back(pa);
+    b->ogrid.push_back(G);
+  }
   if (e == hipSuccess) e = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming);
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);   // default priority
   for (int i = 0; i < n && e == hipSuccess; ++i) {
@@ -300,6 +359,21 @@ qk_status batch_create(qk_krylov* const* ks, void* const* psi, const int64_t* r0
   }
   if (e != hipSuccess) {
     qk_status st = hip_fail(e, "qk_batch_create");
+    batch_destroy(b);
+    return st;
+  }
+  // autocorrelation state: S = 0, t = 0, P_prev = P of the vectors as given
+  qk_status st = QK_OK;
+  e = hipMemset(b->d_state, 0, sizeof(double) * (2 * (size_t)off + 1));
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(k_counter, dim3(1), dim3(64), 0, nullptr, b->d_counter, 1);
+    e = hipGetLastError();
+  }
+  for (int i = 0; i < n && e == hipSuccess && st == QK_OK; ++i)
+    st = record_item(b, i, b->d_state + off, nullptr);
+  if (e == hipSuccess && st == QK_OK) e = hipDeviceSynchronize();
+  if (e != hipSuccess || st != QK_OK) {
+    if (st == QK_OK) st = hip_fail(e, "qk_batch_create");
     batch_destroy(b);
     return st;
   }
@@ -316,29 +390,36 @@ void batch_destroy(qk_batch* b) {
   if (b->fork) hipEventDestroy(b->fork);
   if (b->cap) hipStreamDestroy(b->cap);
   if (b->d_counter) hipFree(b->d_counter);
+  if (b->d_state) hipFree(b->d_state);
+  for (auto p : b->psi0)
+    if (p) hipFree(p);
+  for (auto p : b->part)
+    if (p) hipFree(p);
   delete b;
 }
 
 // One step of every workspace, each on its own stream forked from `s` and
-// joined back, then the step counter advances.
-static qk_status batch_step(qk_batch* b, double dt, double* P, hipStream_t s) {
+// joined back, then the autocorrelation advances and the step counter moves on.
+static qk_status batch_step(qk_batch* b, double dt, double* P, double* C, hipStream_t s) {
   QK_HIP(hipEventRecord(b->fork, s));
   for (size_t i = 0; i < b->ks.size(); ++i) {
     hipStream_t si = b->streams[i];
     QK_HIP(hipStreamWaitEvent(si, b->fork, 0));
     qk_status st = launch_krylov_step(b->ks[i], b->psi[i], dt, si);
     if (st != QK_OK) return st;
-    st = launch_record(b->ks[i], b->psi[i], b->r0[i], P, b->d_counter, b->item_off[i], b->items, si);
+    st = record_item(b, (int)i, P, si);
     if (st != QK_OK) return st;
     QK_HIP(hipEventRecord(b->joins[i], si));
     QK_HIP(hipStreamWaitEvent(s, b->joins[i], 0));
   }
+  hipLaunchKernelGGL(k_autocorr, dim3(1), dim3(256), 0, s, P, b->d_counter, b->items, dt, b->d_state, C);
+  QK_HIP(hipGetLastError());
   hipLaunchKernelGGL(k_counter, dim3(1), dim3(64), 0, s, b->d_counter, 0);
   QK_HIP(hipGetLastError());
   return QK_OK;
 }
 
-qk_status batch_run(qk_batch* b, double dt, int n_steps, int use_graph, double* P, hipStream_t s) {
+qk_status batch_run(qk_batch* b, double dt, int n_steps, int use_graph, double* P, double* C, hipStream_t s) {
   std::vector<bool> prof(b->ks.size());
   for (size_t i = 0; i < b->ks.size(); ++i) {
     prof[i] = b->ks[i]->profiling;
@@ -355,18 +436,18 @@ qk_status batch_run(qk_batch* b, double dt, int n_steps, int use_graph, double* 
   }
   qk_status st = QK_OK;
   if (!use_graph) {
-    for (int k = 0; k < n_steps && st == QK_OK; ++k) st = batch_step(b, dt, P, s);
+    for (int k = 0; k < n_steps && st == QK_OK; ++k) st = batch_step(b, dt, P, C, s);
     restore();
     return st;
   }
-  if (!b->exec || b->graph_dt != dt || b->graph_P != P) {
+  if (!b->exec || b->graph_dt != dt || b->graph_P != P || b->graph_C != C) {
     batch_release(b);
     hipError_t e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) {
       restore();
       return hip_fail(e, "hipStreamBeginCapture");
     }
-    st = batch_step(b, dt, P, b->cap);
+    st = batch_step(b, dt, P, C, b->cap);
     hipGraph_t g = nullptr;
     e = hipStreamEndCapture(b->cap, &g);
     if (st != QK_OK || e != hipSuccess) {
@@ -383,6 +464,7 @@ qk_status batch_run(qk_batch* b, double dt, int n_steps, int use_graph, double* 
     }
     b->graph_dt = dt;
     b->graph_P = P;
+    b->graph_C = C;
   }
   for (int k = 0; k < n_steps; ++k) {
     hipError_t e = hipGraphLaunch(b->exec, s);

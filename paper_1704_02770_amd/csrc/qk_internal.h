@@ -133,6 +133,12 @@ qk_status launch_krylov_step(qk_krylov* k, void* psi, double dt, hipStream_t s, 
 // One step of at most tau_max whose length the device chooses from the error
 // estimate: st.tau[b] receives the accepted step of column b, st.tau[B + b] a
 // suggested next step; every column advances by the smallest accepted step.
+// Overlap |<psi0, psi>|^2 of every column written at the batched driver's
+// record position (counter == NULL: P[b]); part holds G * 2 * B doubles with
+// G = overlap_grid(D, B).
+int overlap_grid(uint32_t D, int B);
+qk_status launch_overlap_record(const void* psi0, const void* psi, int dtype, uint32_t D, int B, double* part, int G,
+                                double* P, const int* counter, int off, int items, hipStream_t s);
 qk_status launch_krylov_adaptive_step(qk_krylov* k, void* psi, double tau_max, double tol, hipStream_t s);
 qk_status grad_return_prob(qk_krylov* k, int64_t r0, double T, int n_steps, double* F, double* dFdh, hipStream_t s);
 qk_status profile_mark(qk_krylov* k, int kind, bool begin, hipStream_t s);
@@ -143,7 +149,7 @@ qk_status apply_shape(qk_krylov* k, const qk_launch_shape* sh);
 qk_status krylov_autotune(qk_krylov* k, double dt, const char* cache_path, hipStream_t s, qk_launch_shape* chosen);
 qk_status batch_create(qk_krylov* const* ks, void* const* psi, const int64_t* r0, int n, qk_batch** out);
 void batch_destroy(qk_batch* b);
-qk_status batch_run(qk_batch* b, double dt, int n_steps, int use_graph, double* P, hipStream_t s);
+qk_status batch_run(qk_batch* b, double dt, int n_steps, int use_graph, double* P, double* C, hipStream_t s);
 int batch_items(const qk_batch* b);
 int batch_device(const qk_batch* b);
 qk_status profile_collect(qk_krylov* k);

@@ -452,11 +452,16 @@ k_overlap_partial(const typename Cx<T>::V* __restrict__ psi0, const typename Cx<
   block_partials<2>(v, B, red, part + (size_t)blockIdx.x * 2 * B);
 }
 
-__global__ void __launch_bounds__(kMaxBlock) k_overlap_final(const double* __restrict__ part, int G, int B, double* P) {
+// |<psi0, psi>|^2 per column into P[b], or, with a step counter, into
+// P[(*counter) * items + off + b] (the batched driver's record layout).
+__global__ void __launch_bounds__(kMaxBlock)
+k_overlap_final(const double* __restrict__ part, int G, int B, double* P, const int* __restrict__ counter, int off,
+                int items) {
   __shared__ double red[kMaxBlock];
   __shared__ double tot[2 * QK_MAX_BATCH];
   reduce_partials(part, G, 2, B, red, tot);
-  for (int b = threadIdx.x; b < B; b += blockDim.x) P[b] = tot[b] * tot[b] + tot[B + b] * tot[B + b];
+  double* out = counter ? P + (size_t)(*counter) * items + off : P;
+  for (int b = threadIdx.x; b < B; b += blockDim.x) out[b] = tot[b] * tot[b] + tot[B + b] * tot[B + b];
 }
 
 // ------------------------------------------------------------- CSR form
@@ -801,11 +806,28 @@ qk_status launch_return_prob(const qk_basis* b, int64_t r0, const void* psi0, co
                        (const float2*)psi, D, B, part);
   hipError_t e = hipGetLastError();
   if (e == hipSuccess) {
-    hipLaunchKernelGGL(k_overlap_final, dim3(1), dim3(kMaxBlock), 0, s, part, G, B, P);
+    hipLaunchKernelGGL(k_overlap_final, dim3(1), dim3(kMaxBlock), 0, s, part, G, B, P, (const int*)nullptr, 0, 0);
     e = hipGetLastError();
   }
   QK_HIP(hipFreeAsync(part, s));
   QK_HIP(e);
+  return QK_OK;
+}
+
+int overlap_grid(uint32_t D, int B) { return stream_grid(D, B, block_threads(B), 0); }
+
+qk_status launch_overlap_record(const void* psi0, const void* psi, int dtype, uint32_t D, int B, double* part, int G,
+                                double* P, const int* counter, int off, int items, hipStream_t s) {
+  const int threads = block_threads(B);
+  if (dtype == QK_C128)
+    hipLaunchKernelGGL(k_overlap_partial<double>, dim3(G), dim3(threads), 0, s, (const double2*)psi0,
+                       (const double2*)psi, D, B, part);
+  else
+    hipLaunchKernelGGL(k_overlap_partial<float>, dim3(G), dim3(threads), 0, s, (const float2*)psi0,
+                       (const float2*)psi, D, B, part);
+  QK_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_overlap_final, dim3(1), dim3(kMaxBlock), 0, s, part, G, B, P, counter, off, items);
+  QK_HIP(hipGetLastError());
   return QK_OK;
 }
 

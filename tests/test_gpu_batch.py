@@ -12,7 +12,7 @@ from gpu_util import max_rel, neel_row, say, to_host
 from oracle import exact as OX
 from oracle import hamiltonian as OH
 from oracle import model as OM
-from workloads import BETA_GOLDEN, phases
+from workloads import BETA_GOLDEN, phases, random_complex
 
 pytestmark = pytest.mark.gpu
 
@@ -126,3 +126,65 @@ def test_autotune_keeps_results_and_caches(tmp_path, L, Bn, dtype):
         qk.qk_krylov_set_shape(w2["k"], threads=512)
     with pytest.raises(qk.QkError):
         qk.qk_krylov_set_shape(w2["k"], blocks_per_cu=-1)
+
+
+def _random_states(D, Bn, seed, dtype):
+    z = random_complex(D * Bn, seed).reshape(D, Bn) if Bn > 1 else random_complex(D, seed)
+    z = z / np.linalg.norm(z, axis=0)
+    return torch.from_numpy(np.ascontiguousarray(z)).to(device="cuda", dtype=dtype)
+
+
+@pytest.mark.parametrize("use_graph", [False, True])
+def test_autocorrelation_and_random_initial_states(use_graph):
+    # a basis-state workspace (Neel, 3 phases, L=12) and a workspace of random
+    # initial states (2 phases, L=10) in one batch; P and C(t) after every
+    # step against the oracle: exact P, its trapezoid average on the same grid
+    # and the closed form of C(t)
+    dtype, dt, steps = torch.complex128, 0.05, 120
+    w1 = _ws(12, 3, dtype, h=1.5, seed=11, m=24)
+    w2 = _ws(10, 2, dtype, h=3.0, seed=12, m=24)
+    D2 = w2["psi"].shape[0]
+    psi2 = _random_states(D2, 2, 21, dtype)
+    psi2_init = to_host(psi2).copy()
+    bt = qk.qk_batch_create([w1["k"], w2["k"]], [w1["psi"], psi2], [w1["r0"], -1])
+    say("autocorrelation", use_graph)
+    P1, C1 = qk.qk_batch_run_autocorr(bt, dt, steps // 2, use_graph=use_graph)
+    P2, C2 = qk.qk_batch_run_autocorr(bt, dt, steps - steps // 2, use_graph=use_graph)
+    P = np.concatenate([to_host(P1), to_host(P2)])
+    C = np.concatenate([to_host(C1), to_host(C2)])
+    t = dt * np.arange(0, steps + 1)
+    refP = np.empty((steps, 5))
+    refC = np.empty((steps, 5))
+    closed = np.empty(5)
+    cases = [(12, w1["hf"][i], None, i) for i in range(3)] + [(10, w2["hf"][i], psi2_init[:, i], i) for i in range(2)]
+    for j, (L, hf, p0, i) in enumerate(cases):
+        Hd = OH.build_dense(L, L // 2, True, 1.0, 1.0, hf)
+        eig = OX.eig(Hd)
+        if p0 is None:
+            p0 = np.zeros(len(Hd), complex)
+            p0[w1["r0"]] = 1.0
+        Pt = np.array([OX.overlap_probability(p0, v) for v in OX.evolve(Hd, p0, t, eig)])
+        refP[:, j] = Pt[1:]
+        refC[:, j] = OX.autocorrelation(t, Pt)[1:]
+        closed[j] = OX.autocorrelation_exact(Hd, p0, [t[-1]], eig)[0]
+    assert np.max(np.abs(P - refP)) < 1e-10
+    assert np.max(np.abs(C - refC)) < 1e-10
+    # trapezoid against the closed form: O(dt^2)
+    assert np.max(np.abs(C[-1] - closed)) < 2e-3
+
+
+def test_random_initial_states_complex64():
+    dtype, dt, steps = torch.complex64, 0.1, 20
+    w = _ws(14, 4, dtype, h=2.0, seed=13, m=24)
+    D = w["psi"].shape[0]
+    psi = _random_states(D, 4, 22, dtype)
+    p_init = to_host(psi).astype(np.complex128)
+    bt = qk.qk_batch_create([w["k"]], [psi], [-1])
+    say("random initial states c64")
+    P, C = qk.qk_batch_run_autocorr(bt, dt, steps)
+    P = to_host(P)
+    t = dt * np.arange(1, steps + 1)
+    for i in range(4):
+        Hd = OH.build_dense(14, 7, True, 1.0, 1.0, w["hf"][i])
+        ref = [OX.overlap_probability(p_init[:, i], v) for v in OX.evolve(Hd, p_init[:, i], t)]
+        assert np.max(np.abs(P[:, i] - ref)) < 1e-5

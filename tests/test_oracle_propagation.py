@@ -170,3 +170,41 @@ def test_saad_estimate_tracks_error():
             psi, info = K.expm_step(lambda v: H @ v, psi0, dt, m)
             err = np.linalg.norm(psi - X.evolve(H, psi0, [dt])[0])
             assert err < info["err_est"] < err * 100
+
+
+def test_autocorrelation_exact_two_level_closed_form():
+    # two sites, one particle, open chain: P(t) = 1 - (jxy/W)^2 sin^2(W t / 2),
+    # W = sqrt(jxy^2 + (h1 - h2)^2), so its time average over [0, t] is
+    # 1 - (jxy/W)^2 (1/2 - sin(W t) / (2 W t))
+    jxy, h = 0.8, np.array([0.9, -0.4])
+    Hd = Hm.build_dense(2, 1, False, jxy, 0.3, h)
+    W = np.sqrt(jxy ** 2 + (h[0] - h[1]) ** 2)
+    t = np.array([1e-9, 0.3, 1.7, 12.0])
+    e0 = np.array([1.0, 0.0])
+    ref = 1.0 - (jxy / W) ** 2 * (0.5 - np.sin(W * t) / (2 * W * t))
+    assert np.max(np.abs(X.autocorrelation_exact(Hd, e0, t) - ref)) < 1e-12
+
+
+def test_autocorrelation_exact_limits_and_trapezoid():
+    L = 8
+    hf = M.fields(L, 1.2, BETA_GOLDEN, 0.7)
+    Hd = Hm.build_dense(L, L // 2, True, 1.0, 1.0, hf)
+    eig = X.eig(Hd)
+    rng = np.random.default_rng(3)
+    psi0 = rng.standard_normal(len(Hd)) + 1j * rng.standard_normal(len(Hd))
+    psi0 /= np.linalg.norm(psi0)
+    # t -> 0: C = P(0) = 1
+    assert abs(X.autocorrelation_exact(Hd, psi0, [1e-10], eig)[0] - 1.0) < 1e-12
+    # long times: C -> sum_n w_n^2 (inverse participation ratio), within O(1/t)
+    c = eig[1].T @ psi0
+    ipr = float(np.sum(np.abs(c) ** 4))
+    T = 1e6
+    assert abs(X.autocorrelation_exact(Hd, psi0, [T], eig)[0] - ipr) < 1e-4
+    # the trapezoid rule on exact P converges to the closed form as dt^2
+    errs = []
+    for dt in (0.02, 0.01):
+        t = dt * np.arange(0, int(round(3.0 / dt)) + 1)
+        P = np.array([X.overlap_probability(psi0, v) for v in X.evolve(Hd, psi0, t, eig)])
+        Ct = X.autocorrelation(t, P)
+        errs.append(abs(Ct[-1] - X.autocorrelation_exact(Hd, psi0, [3.0], eig)[0]))
+    assert errs[0] < 1e-4 and 3.0 < errs[0] / errs[1] < 5.0
