@@ -170,7 +170,10 @@ typedef struct qk_krylov qk_krylov;
  * scratch.  reorth: 0 = none (plain three-term recurrence), 1 = local (each
  * new vector is also orthogonalised against v_{j-1}, the alpha term having
  * removed v_j; the dot product is accumulated in double; one extra vector
- * read per iteration).  The Hamiltonian must outlive the workspace.
+ * read per iteration), 2 = full (classical Gram-Schmidt applied twice against
+ * all previous vectors, dot products and coefficients in double; about
+ * 4 (j + 2) extra vector reads at iteration j).  The Hamiltonian must outlive
+ * the workspace.
  */
 qk_status qk_krylov_create(const qk_ham* H, int32_t m, int32_t dtype, int32_t reorth, qk_krylov** out);
 
@@ -324,14 +327,17 @@ void qk_batch_destroy(qk_batch* b);
  * costate lambda(s) = exp(+iH(T-s)) e_r0 propagated backward by Krylov steps
  * of -dt; inside each step the time integral of <lambda|Z_i|psi> is taken
  * between the two Krylov bases by Gauss-Legendre quadrature of the projected
- * propagators.  Uses the workspace's Hamiltonian, Krylov dimension and launch
- * shape, and allocates (n_steps + 1) state vectors of checkpoints plus one
- * more workspace for the duration of the call.  Requires dtype QK_C128,
- * batch 1 and m <= 32 (else QK_EUNSUPPORTED).  Synchronous; F_host and
- * dFdh_host are host pointers.
+ * propagators.  The forward states are kept every ckpt_every (>= 1) steps;
+ * the backward sweep recomputes the states of one segment from its
+ * checkpoint (one extra forward pass in total, identical results), so the
+ * call holds n_steps / ckpt_every + ckpt_every + 2 state vectors plus one more
+ * workspace, allocated for its duration.  Uses the workspace's Hamiltonian,
+ * Krylov dimension and launch shape.  Requires dtype QK_C128, batch 1 and
+ * m <= 32 (else QK_EUNSUPPORTED).  Synchronous; F_host and dFdh_host are host
+ * pointers.
  */
-qk_status qk_grad_return_prob(qk_krylov* k, int64_t r0, double T, int32_t n_steps, double* F_host,
-                              double* dFdh_host, void* stream);
+qk_status qk_grad_return_prob(qk_krylov* k, int64_t r0, double T, int32_t n_steps, int32_t ckpt_every,
+                              double* F_host, double* dFdh_host, void* stream);
 
 /* ----------------------------------------------------------- observable */
 /*

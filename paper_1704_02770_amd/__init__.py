@@ -334,12 +334,13 @@ def qk_batch_run_autocorr(b: Batch, dt: float, n_steps: int, use_graph: bool = T
     return out, out_c
 
 
-def qk_grad_return_prob(k: Krylov, r0: int, T: float, n_steps: int, stream=None):
-    """(F(T), dF/dh as a numpy array of length L) for the initial basis state r0."""
+def qk_grad_return_prob(k: Krylov, r0: int, T: float, n_steps: int, ckpt_every: int = 1, stream=None):
+    """(F(T), dF/dh as a numpy array of length L) for the initial basis state r0;
+    forward states are kept every ckpt_every steps."""
     L = k.H.L
     F = C.c_double()
     g = np.zeros(L)
-    _check(lib.qk_grad_return_prob(k.ptr, int(r0), float(T), int(n_steps), C.byref(F),
+    _check(lib.qk_grad_return_prob(k.ptr, int(r0), float(T), int(n_steps), int(ckpt_every), C.byref(F),
                                    g.ctypes.data_as(C.POINTER(C.c_double)), _stream(stream)), "qk_grad_return_prob")
     return F.value, g
 

@@ -79,7 +79,7 @@ SIGNATURES = {
     "qk_batch_run": (i32, [vp, f64, i32, i32, vp, vp]),
     "qk_batch_run_autocorr": (i32, [vp, f64, i32, i32, vp, vp, vp]),
     "qk_batch_destroy": (None, [vp]),
-    "qk_grad_return_prob": (i32, [vp, i64, f64, i32, P(f64), P(f64), vp]),
+    "qk_grad_return_prob": (i32, [vp, i64, f64, i32, i32, P(f64), P(f64), vp]),
     "qk_return_prob": (i32, [vp, i64, vp, vp, i32, i32, vp, vp]),
 }
 

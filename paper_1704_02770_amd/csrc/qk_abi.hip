@@ -290,7 +290,7 @@ QK_API qk_status qk_krylov_create(const qk_ham* H, int32_t m, int32_t dtype, int
   if (!H) return inval("NULL Hamiltonian");
   if (m < 1 || m > QK_MAX_M) return inval("m must be in [1, 64]");
   if (dtype != QK_C128 && dtype != QK_C64) return inval("unknown dtype");
-  if (reorth != 0 && reorth != 1) return inval("reorth must be 0 or 1");
+  if (reorth < 0 || reorth > 2) return inval("reorth must be 0, 1 or 2");
   qk_status st = check_device(H->device);
   if (st != QK_OK) return st;
   qk_krylov* k = new (std::nothrow) qk_krylov;
@@ -311,6 +311,11 @@ QK_API qk_status qk_krylov_create(const qk_ham* H, int32_t m, int32_t dtype, int
   if (e == hipSuccess) e = hipMalloc((void**)&k->d_int, sizeof(int32_t) * 2 * k->batch);
   if (e == hipSuccess) e = hipMemset(k->d_coef, 0, sizeof(double) * kstate_doubles(m, k->batch));
   if (e == hipSuccess) e = hipMemset(k->d_int, 0, sizeof(int32_t) * 2 * k->batch);
+  if (e == hipSuccess && reorth == 2) {
+    const size_t chunks = (size_t)(m + kReorthChunk - 1) / kReorthChunk;
+    e = hipMalloc((void**)&k->d_rpart, sizeof(double) * chunks * kReorthGrid * 2 * kReorthChunk * k->batch);
+    if (e == hipSuccess) e = hipMalloc((void**)&k->d_rcoef, sizeof(double) * (size_t)m * 2 * k->batch);
+  }
   if (e != hipSuccess) {
     st = hip_fail(e, "qk_krylov_create allocation");
     qk_krylov_destroy(k);
@@ -483,6 +488,8 @@ QK_API void qk_krylov_destroy(qk_krylov* k) {
   if (k->d_U) hipFree(k->d_U);
   if (k->d_partA) hipFree(k->d_partA);
   if (k->d_partB) hipFree(k->d_partB);
+  if (k->d_rpart) hipFree(k->d_rpart);
+  if (k->d_rcoef) hipFree(k->d_rcoef);
   if (k->d_coef) hipFree(k->d_coef);
   if (k->d_int) hipFree(k->d_int);
   delete k;
@@ -568,12 +575,13 @@ QK_API qk_status qk_batch_run(qk_batch* b, double dt, int32_t n_steps, int32_t u
 QK_API void qk_batch_destroy(qk_batch* b) { batch_destroy(b); }
 
 // ----------------------------------------------------------------- gradient
-QK_API qk_status qk_grad_return_prob(qk_krylov* k, int64_t r0, double T, int32_t n_steps, double* F_host,
-                                     double* dFdh_host, void* stream) {
+QK_API qk_status qk_grad_return_prob(qk_krylov* k, int64_t r0, double T, int32_t n_steps, int32_t ckpt_every,
+                                     double* F_host, double* dFdh_host, void* stream) {
   g_err.clear();
   if (!k || !F_host || !dFdh_host) return inval("NULL pointer");
   if (!std::isfinite(T) || T < 0.0) return inval("T must be finite and >= 0");
   if (n_steps < 1) return inval("n_steps must be >= 1");
+  if (ckpt_every < 1) return inval("ckpt_every must be >= 1");
   if (r0 < 0 || r0 >= k->D) return inval("r0 out of range");
   if (k->dtype != QK_C128 || k->batch != 1 || k->m > 32) {
     set_error("the gradient needs a complex128 workspace with batch 1 and m <= 32");
@@ -581,7 +589,7 @@ QK_API qk_status qk_grad_return_prob(qk_krylov* k, int64_t r0, double T, int32_t
   }
   qk_status st = check_device(k->device);
   if (st != QK_OK) return st;
-  return grad_return_prob(k, r0, T, n_steps, F_host, dFdh_host, (hipStream_t)stream);
+  return grad_return_prob(k, r0, T, n_steps, ckpt_every, F_host, dFdh_host, (hipStream_t)stream);
 }
 
 // -------------------------------------------------------------- observable

@@ -200,7 +200,7 @@ __global__ void k_basis_vector(double2* __restrict__ v, uint32_t D, uint32_t r0)
   if (r < D) v[r] = make_double2(r == r0 ? 1.0 : 0.0, 0.0);
 }
 
-qk_status grad_return_prob(qk_krylov* k, int64_t r0, double T, int n_steps, double* F, double* dFdh,
+qk_status grad_return_prob(qk_krylov* k, int64_t r0, double T, int n_steps, int ckpt_every, double* F, double* dFdh,
                            hipStream_t s) {
   const qk_ham* H = k->H;
   const uint32_t D = (uint32_t)k->D;
@@ -208,8 +208,12 @@ qk_status grad_return_prob(qk_krylov* k, int64_t r0, double T, int n_steps, doub
   const double dt = T / n_steps;
   const size_t vbytes = sizeof(double2) * (size_t)D;
   const int G = 1024;
+  const int c = ckpt_every < 1 ? 1 : (ckpt_every > n_steps ? n_steps : ckpt_every);
+  const int nck = n_steps / c + 1;   // checkpoints psi_0, psi_c, psi_2c, ...
   qk_krylov* kb = nullptr;   // workspace of the backward steps
-  double2* ck = nullptr;     // checkpoints psi_0 .. psi_K
+  double2* ck = nullptr;     // checkpoints
+  double2* seg = nullptr;    // recomputed states of one segment after its checkpoint (c - 1)
+  double2* cur = nullptr;    // running forward state
   double2* lam = nullptr;    // lambda_k
   double2* lamp = nullptr;   // lambda_{k+1}
   double *Ct = nullptr, *part = nullptr, *dA = nullptr;
@@ -219,7 +223,9 @@ qk_status grad_return_prob(qk_krylov* k, int64_t r0, double T, int n_steps, doub
   kb->blocks_per_cu = k->blocks_per_cu;
   kb->blocked_wgs = k->blocked_wgs;
   kb->grid = k->grid;
-  hipError_t e = hipMalloc((void**)&ck, vbytes * (size_t)(n_steps + 1));
+  hipError_t e = hipMalloc((void**)&ck, vbytes * (size_t)nck);
+  if (e == hipSuccess && c > 1) e = hipMalloc((void**)&seg, vbytes * (size_t)(c - 1));
+  if (e == hipSuccess) e = hipMalloc((void**)&cur, vbytes);
   if (e == hipSuccess) e = hipMalloc((void**)&lam, vbytes);
   if (e == hipSuccess) e = hipMalloc((void**)&lamp, vbytes);
   if (e == hipSuccess) e = hipMalloc((void**)&Ct, sizeof(double) * 2 * kGradMaxM * kGradMaxM);
@@ -233,24 +239,50 @@ qk_status grad_return_prob(qk_krylov* k, int64_t r0, double T, int n_steps, doub
     if (st == QK_OK && e != hipSuccess) st = hip_fail(e, what);
   };
   chk("qk_grad_return_prob allocation");
-  // forward pass with checkpoints
+  // forward pass, keeping psi_t for t = 0, c, 2c, ...
   if (st == QK_OK) {
-    hipLaunchKernelGGL(k_basis_vector, dim3((D + 255) / 256), dim3(256), 0, s, ck, D, (uint32_t)r0);
+    hipLaunchKernelGGL(k_basis_vector, dim3((D + 255) / 256), dim3(256), 0, s, cur, D, (uint32_t)r0);
     chk("k_basis_vector");
   }
-  for (int t = 0; t < n_steps && st == QK_OK; ++t) {
-    e = hipMemcpyAsync(ck + (size_t)(t + 1) * D, ck + (size_t)t * D, vbytes, hipMemcpyDeviceToDevice, s);
+  if (st == QK_OK) {
+    e = hipMemcpyAsync(ck, cur, vbytes, hipMemcpyDeviceToDevice, s);
     chk("checkpoint copy");
-    if (st == QK_OK) st = launch_krylov_step(k, ck + (size_t)(t + 1) * D, dt, s, true);
   }
+  for (int t = 0; t < n_steps && st == QK_OK; ++t) {
+    st = launch_krylov_step(k, cur, dt, s, true);
+    if (st == QK_OK && (t + 1) % c == 0 && (t + 1) / c < nck) {
+      e = hipMemcpyAsync(ck + (size_t)((t + 1) / c) * D, cur, vbytes, hipMemcpyDeviceToDevice, s);
+      chk("checkpoint copy");
+    }
+  }
+  double2 A = make_double2(0.0, 0.0);
+  if (st == QK_OK) {
+    e = hipMemcpyAsync(&A, cur + r0, sizeof(double2), hipMemcpyDeviceToHost, s);
+    chk("qk_grad_return_prob readback");
+  }
+  // psi_t inside the segment of checkpoint j: the checkpoint itself or a recomputed state
+  auto state_at = [&](int t) -> double2* {
+    const int j = t / c, o = t - j * c;
+    return o == 0 ? ck + (size_t)j * D : seg + (size_t)(o - 1) * D;
+  };
   // backward pass of the costate
   if (st == QK_OK) {
     hipLaunchKernelGGL(k_basis_vector, dim3((D + 255) / 256), dim3(256), 0, s, lam, D, (uint32_t)r0);
     chk("k_basis_vector");
   }
   for (int t = n_steps - 1; t >= 0 && st == QK_OK; --t) {
-    // Krylov basis of psi_t (the checkpoint is left unchanged)
-    st = launch_krylov_step(k, ck + (size_t)t * D, dt, s, false);
+    if (t % c == c - 1 || t == n_steps - 1) {
+      // entering a segment from its end: recompute its states after the checkpoint
+      const int t0 = (t / c) * c;
+      for (int u = t0 + 1; u <= t && st == QK_OK; ++u) {
+        e = hipMemcpyAsync(state_at(u), state_at(u - 1), vbytes, hipMemcpyDeviceToDevice, s);
+        chk("segment copy");
+        if (st == QK_OK) st = launch_krylov_step(k, state_at(u), dt, s, true);
+      }
+      if (st != QK_OK) break;
+    }
+    // Krylov basis of psi_t (the stored state is left unchanged)
+    st = launch_krylov_step(k, state_at(t), dt, s, false);
     if (st != QK_OK) break;
     // lambda_t = exp(+iH dt) lambda_{t+1}; lamp keeps lambda_{t+1}
     e = hipMemcpyAsync(lamp, lam, vbytes, hipMemcpyDeviceToDevice, s);
@@ -261,7 +293,7 @@ qk_status grad_return_prob(qk_krylov* k, int64_t r0, double T, int n_steps, doub
     chk("k_grad_coeffs");
     if (st != QK_OK) break;
     hipLaunchKernelGGL(k_grad_contract, dim3(G), dim3(256), 0, s, H->basis->d_states, D, L,
-                       (const double2*)(ck + (size_t)t * D), (const double2*)k->d_U, (const double2*)lamp,
+                       (const double2*)state_at(t), (const double2*)k->d_U, (const double2*)lamp,
                        (const double2*)kb->d_U, fw, bw, Ct, part);
     chk("k_grad_contract");
     if (st != QK_OK) break;
@@ -269,10 +301,8 @@ qk_status grad_return_prob(qk_krylov* k, int64_t r0, double T, int n_steps, doub
     chk("k_grad_accum");
   }
   std::vector<double> dAh(2 * L);
-  double2 A = make_double2(0.0, 0.0);
   if (st == QK_OK) {
-    e = hipMemcpyAsync(&A, ck + (size_t)n_steps * D + r0, sizeof(double2), hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess) e = hipMemcpyAsync(dAh.data(), dA, sizeof(double) * 2 * L, hipMemcpyDeviceToHost, s);
+    e = hipMemcpyAsync(dAh.data(), dA, sizeof(double) * 2 * L, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) st = hip_fail(e, "qk_grad_return_prob readback");
   }
@@ -282,6 +312,8 @@ qk_status grad_return_prob(qk_krylov* k, int64_t r0, double T, int n_steps, doub
   }
   hipStreamSynchronize(s);
   hipFree(ck);
+  hipFree(seg);
+  hipFree(cur);
   hipFree(lam);
   hipFree(lamp);
   hipFree(Ct);

@@ -15,6 +15,8 @@ namespace qk {
 constexpr int kBinomStride = 33;        // binom[n * 33 + k] = C(n, k), n, k <= 32
 constexpr int kNumXcd = 8;              // MI355X: 8 accelerator complex dies, WGs dealt round-robin
 constexpr int kMaxBlock = 256;
+constexpr int kReorthChunk = 8;         // Krylov vectors per dot-product pass of the full reorthogonalisation
+constexpr int kReorthGrid = 512;        // blocks of that pass
 constexpr int kMaxPartialBlocks = 4096; // partial-sum slots per reduction (>= any grid used)
 
 void set_error(const std::string& msg);
@@ -82,6 +84,8 @@ struct qk_krylov {
   double* d_partB = nullptr;      // [grid][1][batch] partial sums of the update pass
   double* d_coef = nullptr;       // coefficient block, see qk::KState
   int32_t* d_int = nullptr;       // [2][batch]: m_used, status
+  double* d_rpart = nullptr;      // full reorthogonalisation: [chunks][kReorthGrid][2 kReorthChunk][batch] partial dots
+  double* d_rcoef = nullptr;      // full reorthogonalisation: [m][2][batch] projection coefficients
   // event timing (qk_krylov_profile)
   bool profiling = false;
   struct Pending { int kind; hipEvent_t start, end; };
@@ -140,7 +144,8 @@ int overlap_grid(uint32_t D, int B);
 qk_status launch_overlap_record(const void* psi0, const void* psi, int dtype, uint32_t D, int B, double* part, int G,
                                 double* P, const int* counter, int off, int items, hipStream_t s);
 qk_status launch_krylov_adaptive_step(qk_krylov* k, void* psi, double tau_max, double tol, hipStream_t s);
-qk_status grad_return_prob(qk_krylov* k, int64_t r0, double T, int n_steps, double* F, double* dFdh, hipStream_t s);
+qk_status grad_return_prob(qk_krylov* k, int64_t r0, double T, int n_steps, int ckpt_every, double* F, double* dFdh,
+                           hipStream_t s);
 qk_status profile_mark(qk_krylov* k, int kind, bool begin, hipStream_t s);
 int stream_grid(uint64_t rows, int B, int threads, int blocks_per_cu);
 int krylov_threads(const qk_krylov* k);

@@ -223,6 +223,92 @@ k_lanczos_B(const typename Cx<T>::V* __restrict__ uj, const typename Cx<T>::V* _
   block_partials<1>(v, B, red, partB + (size_t)blockIdx.x * B);
 }
 
+// ------------------------------------- full reorthogonalisation (reorth = 2)
+// Classical Gram-Schmidt applied twice to the new vector w = u_{j+1} against
+// v_0..v_j (v_i = sigma_i u_i, u_0 = psi): c_i = sigma_i^2 <u_i, w>, then
+// w -= sum_i c_i u_i.  Dot products and coefficients are accumulated in
+// double in a fixed order; the last pass leaves |w|^2 in the update pass's
+// partial sums, so beta_j is the norm of the reorthogonalised vector.
+template <typename T>
+__global__ void __launch_bounds__(kMaxBlock)
+k_reorth_dots(const typename Cx<T>::V* __restrict__ psi, const typename Cx<T>::V* __restrict__ U,
+              const typename Cx<T>::V* __restrict__ w, uint32_t D, int B, int i0, int ni, double* __restrict__ part) {
+  using V = typename Cx<T>::V;
+  __shared__ double red[2 * kReorthChunk * kMaxBlock];
+  const int b = threadIdx.x % B;
+  const uint32_t R = blockDim.x / B, rl = threadIdx.x / B;
+  const uint32_t ntiles = (D + R - 1) / R;
+  const size_t stride = (size_t)D * B;
+  double acc[2 * kReorthChunk];
+#pragma unroll
+  for (int q = 0; q < 2 * kReorthChunk; ++q) acc[q] = 0.0;
+  for (TileWalk tw(ntiles); tw.t < tw.t_end; tw.t += tw.step) {
+    const uint32_t r = tw.t * R + rl;
+    if (r >= D) continue;
+    const size_t i = (size_t)r * B + b;
+    const V wv = w[i];
+#pragma unroll
+    for (int q = 0; q < kReorthChunk; ++q) {
+      if (q < ni) {
+        const int iv = i0 + q;
+        const V u = iv == 0 ? psi[i] : U[(size_t)(iv - 1) * stride + i];
+        acc[2 * q] += (double)u.x * (double)wv.x + (double)u.y * (double)wv.y;   // conj(u) w
+        acc[2 * q + 1] += (double)u.x * (double)wv.y - (double)u.y * (double)wv.x;
+      }
+    }
+  }
+  block_partials<2 * kReorthChunk>(acc, B, red, part + (size_t)blockIdx.x * 2 * kReorthChunk * B);
+}
+
+// c_i for i < nv from the partials of every chunk (one block, fixed order);
+// zero for columns whose recurrence has stopped.
+__global__ void __launch_bounds__(kMaxBlock)
+k_reorth_coef(const double* __restrict__ part, int G, int nv, int B, int j, KState st, double* __restrict__ coef) {
+  for (int idx = threadIdx.x; idx < nv * 2 * B; idx += blockDim.x) {
+    const int i = idx / (2 * B), rem = idx % (2 * B), comp = rem / B, b = rem % B;
+    const int chunk = i / kReorthChunk, q = 2 * (i % kReorthChunk) + comp;
+    const double* pc = part + (size_t)chunk * kReorthGrid * 2 * kReorthChunk * B;
+    double t = 0.0;
+    for (int g = 0; g < G; ++g) t += pc[((size_t)g * 2 * kReorthChunk + q) * B + b];
+    const double sg = st.sigma[i * B + b];
+    coef[idx] = (st.mused[b] > j && st.status[b] == QK_OK) ? sg * sg * t : 0.0;
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kMaxBlock)
+k_reorth_axpy(const typename Cx<T>::V* __restrict__ psi, const typename Cx<T>::V* __restrict__ U,
+              typename Cx<T>::V* __restrict__ w, uint32_t D, int B, int nv, const double* __restrict__ coef,
+              double* __restrict__ partB) {
+  using V = typename Cx<T>::V;
+  __shared__ double red[kMaxBlock];
+  const int b = threadIdx.x % B;
+  const uint32_t R = blockDim.x / B, rl = threadIdx.x / B;
+  const uint32_t ntiles = (D + R - 1) / R;
+  const size_t stride = (size_t)D * B;
+  double s = 0.0;
+  for (TileWalk tw(ntiles); tw.t < tw.t_end; tw.t += tw.step) {
+    const uint32_t r = tw.t * R + rl;
+    if (r >= D) continue;
+    const size_t i = (size_t)r * B + b;
+    const V wv = w[i];
+    double xr = (double)wv.x, xi = (double)wv.y;
+    for (int iv = 0; iv < nv; ++iv) {
+      const V u = iv == 0 ? psi[i] : U[(size_t)(iv - 1) * stride + i];
+      const double cr = coef[(2 * iv) * B + b], ci = coef[(2 * iv + 1) * B + b];
+      xr -= cr * (double)u.x - ci * (double)u.y;
+      xi -= cr * (double)u.y + ci * (double)u.x;
+    }
+    V o;
+    o.x = (T)xr;
+    o.y = (T)xi;
+    w[i] = o;
+    s += (double)o.x * (double)o.x + (double)o.y * (double)o.y;
+  }
+  double v[1] = {s};
+  block_partials<1>(v, B, red, partB + (size_t)blockIdx.x * B);
+}
+
 // ------------------------------------------ projected exponential (1 wave)
 // ||u_m|| of the last update pass (the norm of the residual after m steps;
 // only meaningful when the recurrence ran all m steps), reduced by one wave.
@@ -681,7 +767,7 @@ static qk_status krylov_step_t(qk_krylov* k, void* psi_v, double dt, hipStream_t
     }                                                          \
   } while (0)
   for (int j = 0; j < m; ++j) {
-    LanczosArgs la{j, m, rtol, k->reorth};
+    LanczosArgs la{j, m, rtol, k->reorth == 1 ? 1 : 0};
     const V* uj = j == 0 ? psi : U + (size_t)(j - 1) * stride;
     const V* ujm1 = j == 0 ? nullptr : (j == 1 ? psi : U + (size_t)(j - 2) * stride);
     V* w = U + (size_t)j * stride;
@@ -703,6 +789,23 @@ static qk_status krylov_step_t(qk_krylov* k, void* psi_v, double dt, hipStream_t
     hipLaunchKernelGGL((k_lanczos_B<T>), dim3(G), dim3(threads), 0, s, uj, ujm1, w, D, B, st, la, k->d_partA, Ga,
                        k->d_partB, j + 1 < m ? 1 : 0);
     QK_HIP(hipGetLastError());
+    if (k->reorth == 2 && j + 1 < m) {
+      // u_{j+1} against v_0..v_j, twice
+      const int nv = j + 1, Gr = G < kReorthGrid ? G : kReorthGrid;
+      for (int pass = 0; pass < 2; ++pass) {
+        for (int c0 = 0; c0 < nv; c0 += kReorthChunk) {
+          const int ni = nv - c0 < kReorthChunk ? nv - c0 : kReorthChunk;
+          hipLaunchKernelGGL((k_reorth_dots<T>), dim3(Gr), dim3(threads), 0, s, psi, U, w, D, B, c0, ni,
+                             k->d_rpart + (size_t)(c0 / kReorthChunk) * kReorthGrid * 2 * kReorthChunk * B);
+          QK_HIP(hipGetLastError());
+        }
+        hipLaunchKernelGGL(k_reorth_coef, dim3(1), dim3(kMaxBlock), 0, s, k->d_rpart, Gr, nv, B, j, st, k->d_rcoef);
+        QK_HIP(hipGetLastError());
+        hipLaunchKernelGGL((k_reorth_axpy<T>), dim3(G), dim3(threads), 0, s, psi, U, w, D, B, nv, k->d_rcoef,
+                           k->d_partB);
+        QK_HIP(hipGetLastError());
+      }
+    }
     QK_MARK(QK_KERNEL_LANCZOS_UPDATE, false);
   }
   if (!combine) return QK_OK;   // only the Krylov basis and coefficients were asked for

@@ -71,6 +71,23 @@ def test_gradient_vs_finite_differences_L20():
     assert F2 == F and np.array_equal(g2, g)   # deterministic
 
 
+def test_checkpoint_stride_gives_identical_results():
+    # states kept every c steps and recomputed per segment: the same kernels on
+    # the same inputs, so F and dF/dh agree bitwise for every stride
+    L, T, n = 12, 5.0, 50
+    b, H, k, hf = _ws(L, True, 1.5, 0.9)
+    r0 = neel_row(L)
+    say("grad checkpoint strides")
+    F1, g1 = qk.qk_grad_return_prob(k, r0, T, n, 1)
+    for c in (3, 7, 50, 80):
+        Fc, gc = qk.qk_grad_return_prob(k, r0, T, n, c)
+        assert Fc == F1 and np.array_equal(gc, g1), c
+    F_ref, g_ref = OG.dF_dh(L, L // 2, True, 1.0, 1.0, hf, r0, T)
+    assert np.max(np.abs(g1 - g_ref)) < 1e-9 * max(1.0, np.max(np.abs(g_ref)))
+    with pytest.raises(qk.QkError):
+        qk.qk_grad_return_prob(k, r0, T, n, 0)
+
+
 def test_autograd_wrapper():
     L, T, n = 10, 2.0, 20
     b, H, k, hf = _ws(L, True, 1.5, 0.2)

@@ -340,3 +340,53 @@ def test_blocked_batched_equals_single(dtype):
         Hc = OH.build_csr(L, L // 2, True, 1.0, 1.0, hs[3])
         F = OMS.survival_probability(Hc, r0, [dt * steps])[0]
         assert abs(Pb[3] - F) < 1e-10
+
+
+@pytest.mark.parametrize("dtype", [torch.complex128, torch.complex64])
+def test_full_reorthogonalisation_matches_arnoldi(dtype):
+    # m = 48 on a 252-dimensional sector: the plain recurrence loses
+    # orthogonality (its coefficients drift from the oracle's Arnoldi with
+    # modified Gram-Schmidt), the fully reorthogonalised one keeps to it
+    L, m = 10, 48
+    b, H, hf = _problem(L, True)
+    Hd = OH.build_dense(L, L // 2, True, 1.0, 1.0, hf)
+    r0 = neel_row(L)
+    e0 = np.zeros(len(Hd), complex)
+    e0[r0] = 1
+    V, A, beta0, hn, mo = OK.arnoldi(lambda v: Hd @ v, e0, m)
+    assert mo == m
+    dev = {}
+    for ro in (0, 2):
+        psi, _ = _neel_psi(b, L, dtype)
+        k = qk.qk_krylov_create(H, m, dtype, reorth=ro)
+        say("full reorth", dtype, ro)
+        qk.qk_krylov_expm_step(k, psi, 0.05)
+        a, be, mu = qk.qk_krylov_coefficients(k)
+        assert mu == m
+        dev[ro] = max(np.max(np.abs(a - np.diag(A).real)), np.max(np.abs(be[:-1] - np.diag(A, -1).real)))
+    say("  max coefficient deviation: plain", dev[0], "full", dev[2])
+    if dtype == torch.complex128:
+        assert dev[2] < 1e-9 and dev[0] > 1e3 * dev[2]
+    else:
+        assert dev[2] < 1e-4 and dev[0] > 10 * dev[2]
+
+
+def test_full_reorthogonalisation_evolution_and_batch():
+    L, Bn = 12, 3
+    b, Hb, hs = _problem(L, True, h=2.0, Bn=Bn)
+    D = qk.qk_basis_dim(b)
+    r0 = neel_row(L)
+    psib = torch.zeros((D, Bn), dtype=torch.complex128, device="cuda")
+    psib[r0] = 1.0
+    kb = qk.qk_krylov_create(Hb, 20, reorth=2)
+    say("full reorth batch")
+    for _ in range(10):
+        qk.qk_krylov_expm_step(kb, psib, 0.1)
+    for i in range(Bn):
+        Hd = OH.build_dense(L, L // 2, True, 1.0, 1.0, hs[i])
+        e0 = np.zeros(D, complex)
+        e0[r0] = 1
+        ref = OX.evolve(Hd, e0, [1.0])[0]
+        assert np.linalg.norm(to_host(psib[:, i].contiguous()) - ref) < 1e-10
+    with pytest.raises(qk.QkError):
+        qk.qk_krylov_create(Hb, 20, reorth=3)
