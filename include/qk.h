@@ -47,7 +47,7 @@ extern "C" {
 #endif
 
 #define QK_ABI_VERSION 1
-#define QK_MAX_L 32          /* states are 32-bit integers */
+#define QK_MAX_L 64          /* states are 32-bit integers for L <= 32, 64-bit above */
 #define QK_MAX_M 64          /* Krylov dimension limit (one wavefront per projected problem) */
 #define QK_MAX_BATCH 64      /* problems per batched handle */
 
@@ -86,8 +86,12 @@ typedef struct qk_basis qk_basis;
  * Builds the sorted sector basis on the device (Sec. 3, Algorithms 2 and 3:
  * every chunk of rows starts from the unranked first state of its section
  * and advances by the next-bit-permutation), plus the binomial rank table.
- * 2 <= L <= QK_MAX_L, 0 < n_up < L.  *out receives the handle; the build is
- * enqueued on `stream`.  Errors: QK_EINVAL, QK_ENOMEM, QK_EHIP.
+ * 2 <= L <= QK_MAX_L, 0 < n_up < L; the dimension C(L, n_up) must be below
+ * 2^32 - 1 (QK_EUNSUPPORTED otherwise), which for L > 32 means a low density
+ * (the paper's L = 55 runs of Sec. 4).  States are held as 32-bit integers for
+ * L <= 32 and as 64-bit integers above.  *out receives the handle; the build
+ * is enqueued on `stream`.  Errors: QK_EINVAL, QK_EUNSUPPORTED, QK_ENOMEM,
+ * QK_EHIP.
  */
 qk_status qk_basis_build(int32_t L, int32_t n_up, void* stream, qk_basis** out);
 
@@ -97,8 +101,9 @@ qk_status qk_basis_dim(const qk_basis* b, int64_t* D);
 /* L and n_up of a basis (host values). */
 qk_status qk_basis_shape(const qk_basis* b, int32_t* L, int32_t* n_up);
 
-/* Copies the D sorted states (uint32) into caller device memory dst_device. */
-qk_status qk_basis_states(const qk_basis* b, uint32_t* dst_device, void* stream);
+/* Copies the D sorted states into caller device memory dst_device: uint32
+ * values for L <= 32, uint64 values for L > 32. */
+qk_status qk_basis_states(const qk_basis* b, void* dst_device, void* stream);
 
 /*
  * Row index of each of n host states (Sec. 3: lookup of the row of a state;

@@ -8,6 +8,7 @@ the Hamiltonian belongs to the r-th integer of that list.
 """
 from __future__ import annotations
 
+from itertools import combinations
 from math import comb
 
 import numpy as np
@@ -21,11 +22,19 @@ def sector_dim(L: int, N: int) -> int:
 def sector_states(L: int, N: int) -> np.ndarray:
     """All integers in [0, 2^L) with exactly N set bits, ascending (int64).
 
-    This is the plain definition of the basis; it scans the full 2^L range in
-    chunks and keeps the integers whose popcount is N.
+    This is the plain definition of the basis.  Up to L = 30 it scans the full
+    2^L range in chunks and keeps the integers whose popcount is N; above, it
+    forms the integer of every N-subset of the L bit positions and sorts them
+    (the same set, for sectors too large to scan; L <= 63 so that int64 holds
+    every state).
     """
-    if not (0 <= N <= L <= 40):
-        raise ValueError("need 0 <= N <= L <= 40")
+    if not (0 <= N <= L <= 63):
+        raise ValueError("need 0 <= N <= L <= 63")
+    if L > 30:
+        if comb(L, N) > 50_000_000:
+            raise ValueError("sector too large for the oracle")
+        vals = sorted(sum(1 << p for p in c) for c in combinations(range(L), N))
+        return np.array(vals, dtype=np.int64)
     chunk = 1 << 22
     parts = []
     for lo in range(0, 1 << L, chunk):

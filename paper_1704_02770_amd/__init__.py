@@ -125,12 +125,15 @@ def qk_basis_shape(b: Basis) -> tuple[int, int]:
 
 
 def qk_basis_states(b: Basis, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
-    """The sorted states as a device int32 tensor holding the uint32 bit patterns."""
+    """The sorted states as a device tensor holding their bit patterns: int32
+    (uint32 patterns) for L <= 32, int64 (uint64 patterns) for L > 32."""
     D = qk_basis_dim(b)
+    L, _ = qk_basis_shape(b)
+    width = 8 if L > 32 else 4
     if out is None:
-        out = torch.empty(D, dtype=torch.int32, device="cuda")
-    if out.numel() != D or out.element_size() != 4:
-        raise ValueError("out must hold D 32-bit integers")
+        out = torch.empty(D, dtype=torch.int64 if width == 8 else torch.int32, device="cuda")
+    if out.numel() != D or out.element_size() != width:
+        raise ValueError(f"out must hold D {8 * width}-bit integers")
     _check(lib.qk_basis_states(b.ptr, _dptr(out), _stream(stream)), "qk_basis_states")
     return out
 

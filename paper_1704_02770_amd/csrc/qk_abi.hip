@@ -72,25 +72,32 @@ QK_API qk_status qk_fields_quasiperiodic(int32_t L, double h, double beta, const
 // ------------------------------------------------------------------- basis
 static int64_t binom64(int n, int k) {
   if (k < 0 || k > n) return 0;
-  int64_t r = 1;
-  for (int i = 1; i <= k; ++i) r = r * (n - k + i) / i;
-  return r;
+  unsigned __int128 r = 1;
+  for (int i = 1; i <= k; ++i) r = r * (unsigned)(n - k + i) / (unsigned)i;   // exact at every step
+  return r > (unsigned __int128)INT64_MAX ? INT64_MAX : (int64_t)r;
 }
 
 QK_API qk_status qk_basis_build(int32_t L, int32_t n_up, void* stream, qk_basis** out) {
   g_err.clear();
   if (!out) return inval("NULL out");
   *out = nullptr;
-  if (L < 2 || L > QK_MAX_L) return inval("L must be in [2, 32]");
+  if (L < 2 || L > QK_MAX_L) return inval("L must be in [2, 64]");
   if (n_up <= 0 || n_up >= L) return inval("n_up must be in (0, L)");
+  if (binom64(L, n_up) >= (int64_t)0xffffffffll) {
+    set_error("sector dimension C(L, n_up) must be below 2^32 - 1");
+    return QK_EUNSUPPORTED;
+  }
   qk_basis* b = new (std::nothrow) qk_basis;
   if (!b) return QK_ENOMEM;
   b->L = L;
   b->N = n_up;
   b->D = binom64(L, n_up);
+  b->wide = L > 32;
+  const int K = binom_stride(b);
+  const size_t sbytes = b->wide ? sizeof(uint64_t) : sizeof(uint32_t);
   hipError_t e = hipGetDevice(&b->device);
-  if (e == hipSuccess) e = hipMalloc((void**)&b->d_binom, sizeof(uint32_t) * kBinomStride * kBinomStride);
-  if (e == hipSuccess) e = hipMalloc((void**)&b->d_states, sizeof(uint32_t) * (size_t)b->D);
+  if (e == hipSuccess) e = hipMalloc((void**)&b->d_binom, sizeof(uint32_t) * K * K);
+  if (e == hipSuccess) e = hipMalloc((void**)&b->d_states, sbytes * (size_t)b->D);
   if (e != hipSuccess) {
     qk_status st = hip_fail(e, "qk_basis_build allocation");
     qk_basis_destroy(b);
@@ -120,13 +127,13 @@ QK_API qk_status qk_basis_shape(const qk_basis* b, int32_t* L, int32_t* n_up) {
   return QK_OK;
 }
 
-QK_API qk_status qk_basis_states(const qk_basis* b, uint32_t* dst, void* stream) {
+QK_API qk_status qk_basis_states(const qk_basis* b, void* dst, void* stream) {
   g_err.clear();
   if (!b || !dst) return inval("NULL pointer");
   qk_status st = check_device(b->device);
   if (st != QK_OK) return st;
-  QK_HIP(hipMemcpyAsync(dst, b->d_states, sizeof(uint32_t) * (size_t)b->D, hipMemcpyDeviceToDevice,
-                        (hipStream_t)stream));
+  const size_t sbytes = b->wide ? sizeof(uint64_t) : sizeof(uint32_t);
+  QK_HIP(hipMemcpyAsync(dst, b->d_states, sbytes * (size_t)b->D, hipMemcpyDeviceToDevice, (hipStream_t)stream));
   return QK_OK;
 }
 
@@ -182,6 +189,7 @@ QK_API qk_status qk_ham_create(const qk_basis* b, const qk_ham_params* p, const 
   if (p->mode == QK_CSR && b->D > (1 << 24)) return inval("CSR form limited to D <= 2^24");
   qk_status st = check_fields(h_host, b->L, batch);
   if (st != QK_OK) return st;
+  if (batch * b->L > kFldCap) return inval("batch * L must be at most 2048");
   st = check_device(b->device);
   if (st != QK_OK) return st;
   qk_ham* H = new (std::nothrow) qk_ham;

@@ -192,7 +192,7 @@ k_blk(BlkArgs ba, const typename Cx<T>::V* __restrict__ x, typename Cx<T>::V* __
   uint16_t* lo_rank = lo_state + (1 << LLO);
   __shared__ uint32_t sbin[kBinomStride * kBinomStride];
   __shared__ double flo0[256], flo1[256];
-  __shared__ double fld[QK_MAX_L];
+  __shared__ double fld[StateT<uint32_t>::kMaxL];
   __shared__ double tot[1], sa[1], sb[1];
   __shared__ int act[1];
   __shared__ int hds[2][kMaxHi];   // row shifts of the current and the next block
@@ -564,7 +564,7 @@ static int env_int(const char* name, int dflt) {
 
 int blocked_llo(int L, int N, int B, int mode) {
   (void)N;
-  if (mode != QK_MATFREE || L < 18) return 0;
+  if (mode != QK_MATFREE || L < 18 || L > 32) return 0;   // 32-bit states only
   if (B == 1) {
     int llo = env_int("QK_BLOCKED_LLO", 11);
     if (llo < 9) llo = 9;

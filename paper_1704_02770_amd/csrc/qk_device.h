@@ -12,29 +12,38 @@ template <> struct Cx<double> { using V = double2; };
 template <> struct Cx<float> { using V = float2; };
 
 // ------------------------------------------------------------------ ranking
+__device__ __forceinline__ int popc(uint32_t s) { return __popc(s); }
+__device__ __forceinline__ int popc(uint64_t s) { return __popcll(s); }
+__device__ __forceinline__ int ctz(uint32_t s) { return __builtin_ctz(s); }
+__device__ __forceinline__ int ctz(uint64_t s) { return __builtin_ctzll(s); }
+
 // Position of a state in the sorted basis: with set bits at p_1 < ... < p_N,
 // the number of sector states below it is sum_k C(p_k, k) (the counting that
 // the sorted order of Sec. 2 implies; the paper finds it by binary lookup).
-__device__ __forceinline__ uint32_t cns_rank(uint32_t s, const uint32_t* tab) {
+template <typename S>
+__device__ __forceinline__ uint32_t cns_rank(S s, const uint32_t* tab) {
+  constexpr int K = StateT<S>::kStride;
   uint32_t r = 0;
   int k = 1;
   while (s) {
-    int p = __builtin_ctz(s);
-    r += tab[p * kBinomStride + k];
+    const int p = ctz(s);
+    r += tab[p * K + k];
     ++k;
-    s &= s - 1u;
+    s &= s - (S)1;
   }
   return r;
 }
 
 // The r-th state of the sorted basis (Algorithm 3's first_int()).
-__device__ __forceinline__ uint32_t cns_unrank(uint32_t r, int L, int N, const uint32_t* tab) {
-  uint32_t s = 0;
+template <typename S>
+__device__ __forceinline__ S cns_unrank(uint32_t r, int L, int N, const uint32_t* tab) {
+  constexpr int K = StateT<S>::kStride;
+  S s = 0;
   int k = N;
   for (int p = L - 1; p >= 0 && k > 0; --p) {
-    uint32_t c = tab[p * kBinomStride + k];
+    const uint32_t c = tab[p * K + k];
     if (r >= c) {
-      s |= 1u << p;
+      s |= (S)1 << p;
       r -= c;
       --k;
     }
@@ -44,28 +53,32 @@ __device__ __forceinline__ uint32_t cns_unrank(uint32_t r, int L, int N, const u
 
 // Next larger integer with the same popcount (Algorithm 2).  The paper's
 // exact division of two powers of two is a right shift by ctz(v).
-__device__ __forceinline__ uint32_t next_perm(uint32_t v) {
-  uint32_t t = (v | (v - 1u)) + 1u;
-  return t | ((((t & (0u - t)) >> __builtin_ctz(v)) >> 1) - 1u);
+template <typename S>
+__device__ __forceinline__ S next_perm(S v) {
+  const S t = (v | (v - (S)1)) + (S)1;
+  return t | ((((t & ((S)0 - t)) >> ctz(v)) >> 1) - (S)1);
 }
 
 // ------------------------------------------------------------- model rows
-__device__ __forceinline__ int anti_bonds(uint32_t s, const ModelArgs& a) {
+template <typename S>
+__device__ __forceinline__ int anti_bonds(S s, const ModelArgs& a) {
+  const S mask = (S)a.lmask;
   if (a.pbc) {
-    uint32_t rot = ((s >> 1) | (s << (a.L - 1))) & a.lmask;
-    return __popc((s ^ rot) & a.lmask);
+    const S rot = ((s >> 1) | (s << (a.L - 1))) & mask;
+    return popc((S)((s ^ rot) & mask));
   }
-  return __popc((s ^ (s >> 1)) & (a.lmask >> 1));
+  return popc((S)((s ^ (s >> 1)) & (mask >> 1)));
 }
 
 // Diagonal of Eq. (1): jz/4 * (aligned - anti-aligned bonds) + sum_i h_i (bit_i - 1/2).
-__device__ __forceinline__ double diag_value(uint32_t s, const ModelArgs& a, const double* f, double hhalf) {
+template <typename S>
+__device__ __forceinline__ double diag_value(S s, const ModelArgs& a, const double* f, double hhalf) {
   const int nb = a.pbc ? a.L : a.L - 1;
   double d = 0.25 * a.jz * (double)(nb - 2 * anti_bonds(s, a)) - hhalf;
-  uint32_t t = s;
+  S t = s;
   while (t) {
-    d += f[__builtin_ctz(t)];
-    t &= t - 1u;
+    d += f[ctz(t)];
+    t &= t - (S)1;
   }
   return d;
 }
@@ -74,34 +87,38 @@ __device__ __forceinline__ double diag_value(uint32_t s, const ModelArgs& a, con
 // p -> p+1 raises the rank by C(p, #set bits below p); p+1 -> p lowers it by
 // the same amount.  The ring bond (L-1, 0) renumbers every particle and is
 // ranked in full.
-template <class F>
-__device__ __forceinline__ void for_each_hop(uint32_t s, uint32_t r, const ModelArgs& a, const uint32_t* tab, F&& f) {
+template <typename S, class F>
+__device__ __forceinline__ void for_each_hop(S s, uint32_t r, const ModelArgs& a, const uint32_t* tab, F&& f) {
+  constexpr int K = StateT<S>::kStride;
   int pc = 0;
   for (int p = 0; p < a.L - 1; ++p) {
-    const uint32_t b0 = (s >> p) & 1u;
-    const uint32_t b1 = (s >> (p + 1)) & 1u;
+    const uint32_t b0 = (uint32_t)(s >> p) & 1u;
+    const uint32_t b1 = (uint32_t)(s >> (p + 1)) & 1u;
     if (b0 != b1) {
-      const uint32_t c = tab[p * kBinomStride + pc];
+      const uint32_t c = tab[p * K + pc];
       f(b0 ? r + c : r - c);
     }
     pc += (int)b0;
   }
   if (a.pbc) {
-    const uint32_t b0 = s & 1u, b1 = (s >> (a.L - 1)) & 1u;
-    if (b0 != b1) f(cns_rank(s ^ (1u | (1u << (a.L - 1))), tab));
+    const uint32_t b0 = (uint32_t)s & 1u, b1 = (uint32_t)(s >> (a.L - 1)) & 1u;
+    if (b0 != b1) f(cns_rank<S>(s ^ ((S)1 | ((S)1 << (a.L - 1))), tab));
   }
 }
 
 // Per-block LDS copies of the small tables every row kernel needs.
+template <typename S>
 struct RowShared {
-  uint32_t tab[kBinomStride * kBinomStride];
-  double fld[QK_MAX_BATCH * QK_MAX_L];
+  uint32_t tab[StateT<S>::kStride * StateT<S>::kStride];
+  double fld[kFldCap];
   double hhalf[QK_MAX_BATCH];
 };
 
-__device__ __forceinline__ void load_row_shared(RowShared& sh, const ModelArgs& a, const uint32_t* gtab,
+template <typename S>
+__device__ __forceinline__ void load_row_shared(RowShared<S>& sh, const ModelArgs& a, const uint32_t* gtab,
                                                 const double* gfields) {
-  for (int i = threadIdx.x; i < kBinomStride * kBinomStride; i += blockDim.x) sh.tab[i] = gtab[i];
+  constexpr int K = StateT<S>::kStride;
+  for (int i = threadIdx.x; i < K * K; i += blockDim.x) sh.tab[i] = gtab[i];
   for (int i = threadIdx.x; i < a.B * a.L; i += blockDim.x) sh.fld[i] = gfields[i];
   __syncthreads();
   for (int b = threadIdx.x; b < a.B; b += blockDim.x) {
@@ -112,8 +129,9 @@ __device__ __forceinline__ void load_row_shared(RowShared& sh, const ModelArgs& 
   __syncthreads();
 }
 
+template <typename S>
 struct HamView {
-  const uint32_t* states;
+  const S* states;
   const uint32_t* rowptr;
   const uint32_t* cols;
   const double* diag;
@@ -121,9 +139,9 @@ struct HamView {
 };
 
 // (H x)[r, b] and x[r, b].
-template <typename T, bool CSR>
-__device__ __forceinline__ typename Cx<T>::V h_row(uint32_t r, int b, const ModelArgs& a, const RowShared& sh,
-                                                   const HamView& hv, const typename Cx<T>::V* __restrict__ x,
+template <typename T, bool CSR, typename S>
+__device__ __forceinline__ typename Cx<T>::V h_row(uint32_t r, int b, const ModelArgs& a, const RowShared<S>& sh,
+                                                   const HamView<S>& hv, const typename Cx<T>::V* __restrict__ x,
                                                    typename Cx<T>::V& xr) {
   using V = typename Cx<T>::V;
   const int B = a.B;
@@ -143,12 +161,12 @@ __device__ __forceinline__ typename Cx<T>::V h_row(uint32_t r, int b, const Mode
     acc.x += g * hs.x;
     acc.y += g * hs.y;
   } else {
-    const uint32_t s = hv.states[r];
-    const T d = (T)diag_value(s, a, sh.fld + b * a.L, sh.hhalf[b]);
+    const S s = hv.states[r];
+    const T d = (T)diag_value<S>(s, a, sh.fld + b * a.L, sh.hhalf[b]);
     acc.x = d * xr.x;
     acc.y = d * xr.y;
     V hs = {0, 0};
-    for_each_hop(s, r, a, sh.tab, [&](uint32_t c) {
+    for_each_hop<S>(s, r, a, sh.tab, [&](uint32_t c) {
       const V xc = x[(size_t)c * B + b];
       hs.x += xc.x;
       hs.y += xc.y;

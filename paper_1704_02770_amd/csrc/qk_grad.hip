@@ -124,13 +124,14 @@ k_grad_coeffs(KState fw, KState bw, double dt, GaussRule gr, double* __restrict_
 // (q>>1 == L_max: all rows), so each block writes 2(L_max+1) partial sums.
 constexpr int kGradQ = 2 * (QK_MAX_L + 1);
 
+template <typename S>
 __global__ void __launch_bounds__(256)
-k_grad_contract(const uint32_t* __restrict__ states, uint32_t D, int L, const double2* __restrict__ psi_k,
+k_grad_contract(const S* __restrict__ states, uint32_t D, int L, const double2* __restrict__ psi_k,
                 const double2* __restrict__ Uf, const double2* __restrict__ lam, const double2* __restrict__ Ub,
                 KState fw, KState bw, const double* __restrict__ Ct, double* __restrict__ part) {
   __shared__ double2 C[kGradMaxM * kGradMaxM];
   __shared__ double2 sbuf[256];
-  __shared__ uint32_t sst[256];
+  __shared__ S sst[256];
   const int tid = threadIdx.x;
   for (int i = tid; i < kGradMaxM * kGradMaxM; i += blockDim.x) C[i] = make_double2(Ct[2 * i], Ct[2 * i + 1]);
   __syncthreads();
@@ -142,7 +143,7 @@ k_grad_contract(const uint32_t* __restrict__ states, uint32_t D, int L, const do
   for (uint32_t base = blockIdx.x * 256u; base < D; base += gridDim.x * 256u) {
     const uint32_t r = base + tid;
     double sr = 0.0, si = 0.0;
-    uint32_t stt = 0;
+    S stt = 0;
     if (r < D) {
       double2 u[kGradMaxM];
 #pragma unroll
@@ -167,7 +168,7 @@ k_grad_contract(const uint32_t* __restrict__ states, uint32_t D, int L, const do
     __syncthreads();
     if (tid < kGradQ && (site < L || site == QK_MAX_L)) {
       for (int q = 0; q < 256; ++q) {
-        const bool on = site == QK_MAX_L || ((sst[q] >> site) & 1u);
+        const bool on = site == QK_MAX_L || ((sst[q] >> site) & (S)1);
         const double v = comp ? sbuf[q].y : sbuf[q].x;
         acc += on ? v : 0.0;
       }
@@ -179,7 +180,7 @@ k_grad_contract(const uint32_t* __restrict__ states, uint32_t D, int L, const do
 
 // dA[i] += -i (S_i - S_total / 2) summed over the blocks in a fixed order.
 __global__ void k_grad_accum(const double* __restrict__ part, int G, int L, double* __restrict__ dA) {
-  const int q = threadIdx.x;   // kGradQ threads or more
+  const int q = threadIdx.x;   // kGradQ (<= 256) threads or more
   __shared__ double tot[kGradQ];
   if (q < kGradQ) {
     double t = 0.0;
@@ -292,12 +293,17 @@ qk_status grad_return_prob(qk_krylov* k, int64_t r0, double T, int n_steps, int 
     hipLaunchKernelGGL(k_grad_coeffs, dim3(1), dim3(64), 0, s, fw, bw, dt, gr, Ct);
     chk("k_grad_coeffs");
     if (st != QK_OK) break;
-    hipLaunchKernelGGL(k_grad_contract, dim3(G), dim3(256), 0, s, H->basis->d_states, D, L,
-                       (const double2*)state_at(t), (const double2*)k->d_U, (const double2*)lamp,
-                       (const double2*)kb->d_U, fw, bw, Ct, part);
+    if (H->basis->wide)
+      hipLaunchKernelGGL(k_grad_contract<uint64_t>, dim3(G), dim3(256), 0, s, (const uint64_t*)H->basis->d_states,
+                         D, L, (const double2*)state_at(t), (const double2*)k->d_U, (const double2*)lamp,
+                         (const double2*)kb->d_U, fw, bw, Ct, part);
+    else
+      hipLaunchKernelGGL(k_grad_contract<uint32_t>, dim3(G), dim3(256), 0, s, (const uint32_t*)H->basis->d_states,
+                         D, L, (const double2*)state_at(t), (const double2*)k->d_U, (const double2*)lamp,
+                         (const double2*)kb->d_U, fw, bw, Ct, part);
     chk("k_grad_contract");
     if (st != QK_OK) break;
-    hipLaunchKernelGGL(k_grad_accum, dim3(1), dim3(128), 0, s, part, G, L, dA);
+    hipLaunchKernelGGL(k_grad_accum, dim3(1), dim3(256), 0, s, part, G, L, dA);
     chk("k_grad_accum");
   }
   std::vector<double> dAh(2 * L);

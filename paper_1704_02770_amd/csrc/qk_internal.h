@@ -12,7 +12,21 @@
 
 namespace qk {
 
-constexpr int kBinomStride = 33;        // binom[n * 33 + k] = C(n, k), n, k <= 32
+constexpr int kBinomStride = 33;        // binom[n * 33 + k] = C(n, k), n, k <= 32 (32-bit states)
+constexpr int kFldCap = 2048;           // field values the row kernels stage in LDS: batch * L <= kFldCap
+
+// Sector states are 32-bit integers for L <= 32 and 64-bit integers up to
+// L = 64; the binomial table of a basis has stride kStride (entries C(n, k),
+// n, k < kStride, saturated at 2^32 - 1: every term of a rank is below D).
+template <typename S> struct StateT;
+template <> struct StateT<uint32_t> {
+  static constexpr int kStride = 33;
+  static constexpr int kMaxL = 32;
+};
+template <> struct StateT<uint64_t> {
+  static constexpr int kStride = 65;
+  static constexpr int kMaxL = 64;
+};
 constexpr int kNumXcd = 8;              // MI355X: 8 accelerator complex dies, WGs dealt round-robin
 constexpr int kMaxBlock = 256;
 constexpr int kReorthChunk = 8;         // Krylov vectors per dot-product pass of the full reorthogonalisation
@@ -45,8 +59,9 @@ struct qk_basis {
   int32_t L = 0, N = 0;
   int64_t D = 0;
   int device = 0;
-  uint32_t* d_states = nullptr;   // [D] sorted sector states
-  uint32_t* d_binom = nullptr;    // [33 * 33] C(n, k)
+  bool wide = false;              // L > 32: 64-bit states
+  void* d_states = nullptr;       // [D] sorted sector states (uint32_t, or uint64_t when wide)
+  uint32_t* d_binom = nullptr;    // [33 * 33] C(n, k), or [65 * 65] when wide
 };
 
 struct qk_ham {
@@ -118,7 +133,7 @@ KState make_kstate(const qk_krylov* k);
 struct ModelArgs {
   int32_t L, N, pbc, B;
   double half_jxy, jz;
-  uint32_t lmask;        // low L bits
+  uint64_t lmask;        // low L bits
 };
 ModelArgs model_args(const qk_ham* H);
 
@@ -150,6 +165,7 @@ qk_status profile_mark(qk_krylov* k, int kind, bool begin, hipStream_t s);
 int stream_grid(uint64_t rows, int B, int threads, int blocks_per_cu);
 int krylov_threads(const qk_krylov* k);
 int qk_num_cus();
+int binom_stride(const qk_basis* b);   // stride of the basis's binomial table
 qk_status apply_shape(qk_krylov* k, const qk_launch_shape* sh);
 qk_status krylov_autotune(qk_krylov* k, double dt, const char* cache_path, hipStream_t s, qk_launch_shape* chosen);
 qk_status batch_create(qk_krylov* const* ks, void* const* psi, const int64_t* r0, int n, qk_batch** out);

@@ -19,15 +19,18 @@
 
 namespace qk {
 
+// C(n, k) for n, k < K by Pascal's rule, saturated at 2^32 - 1 (entries that
+// large are never used: every term of a rank is below D < 2^32).
+template <int K>
 __global__ void k_binom_table(uint32_t* tab) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  for (int n = 0; n < kBinomStride; ++n)
-    for (int k = 0; k < kBinomStride; ++k) {
-      uint32_t v;
+  for (int n = 0; n < K; ++n)
+    for (int k = 0; k < K; ++k) {
+      uint64_t v;
       if (k > n) v = 0;
       else if (k == 0 || k == n) v = 1;
-      else v = tab[(n - 1) * kBinomStride + k - 1] + tab[(n - 1) * kBinomStride + k];
-      tab[n * kBinomStride + k] = v;
+      else v = (uint64_t)tab[(n - 1) * K + k - 1] + tab[(n - 1) * K + k];
+      tab[n * K + k] = v > 0xffffffffull ? 0xffffffffu : (uint32_t)v;
     }
 }
 
@@ -37,19 +40,21 @@ constexpr int kBasisThreads = 256;
 // Every thread unranks the first state of its chunk and advances with the
 // next bit permutation; the block stages its 2048 states in LDS and writes
 // them out coalesced.
+template <typename S>
 __global__ void __launch_bounds__(kBasisThreads)
-k_basis_build(uint32_t* __restrict__ states, uint32_t D, int L, int N, const uint32_t* __restrict__ gtab) {
-  __shared__ uint32_t tab[kBinomStride * kBinomStride];
-  __shared__ uint32_t stage[kBasisThreads * kBasisChunk];
-  for (int i = threadIdx.x; i < kBinomStride * kBinomStride; i += kBasisThreads) tab[i] = gtab[i];
+k_basis_build(S* __restrict__ states, uint32_t D, int L, int N, const uint32_t* __restrict__ gtab) {
+  constexpr int K = StateT<S>::kStride;
+  __shared__ uint32_t tab[K * K];
+  __shared__ S stage[kBasisThreads * kBasisChunk];
+  for (int i = threadIdx.x; i < K * K; i += kBasisThreads) tab[i] = gtab[i];
   __syncthreads();
   const uint64_t base = (uint64_t)blockIdx.x * kBasisThreads * kBasisChunk;
   const uint64_t start = base + (uint64_t)threadIdx.x * kBasisChunk;
   if (start < D) {
-    uint32_t s = cns_unrank((uint32_t)start, L, N, tab);
+    S s = cns_unrank<S>((uint32_t)start, L, N, tab);
     for (int i = 0; i < kBasisChunk; ++i) {
       stage[threadIdx.x * kBasisChunk + i] = s;
-      s = next_perm(s);
+      s = next_perm<S>(s);
     }
   }
   __syncthreads();
@@ -59,6 +64,7 @@ k_basis_build(uint32_t* __restrict__ states, uint32_t D, int L, int N, const uin
   }
 }
 
+template <typename S>
 __global__ void k_rank(const uint64_t* __restrict__ in, int64_t n, int64_t* __restrict__ out, int L, int N,
                        const uint32_t* __restrict__ tab) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -68,15 +74,15 @@ __global__ void k_rank(const uint64_t* __restrict__ in, int64_t n, int64_t* __re
     out[i] = -1;
     return;
   }
-  out[i] = (int64_t)cns_rank((uint32_t)s, tab);
+  out[i] = (int64_t)cns_rank<S>((S)s, tab);
 }
 
 // ----------------------------------------------------------- H x kernels
-template <typename T, bool CSR>
+template <typename T, bool CSR, typename S>
 __global__ void __launch_bounds__(kMaxBlock)
-k_apply(const typename Cx<T>::V* __restrict__ x, typename Cx<T>::V* __restrict__ y, ModelArgs a, HamView hv,
+k_apply(const typename Cx<T>::V* __restrict__ x, typename Cx<T>::V* __restrict__ y, ModelArgs a, HamView<S> hv,
         const uint32_t* __restrict__ gtab, const double* __restrict__ gfields) {
-  __shared__ RowShared sh;
+  __shared__ RowShared<S> sh;
   load_row_shared(sh, a, gtab, gfields);
   const int B = a.B, b = threadIdx.x % B;
   const uint32_t R = blockDim.x / B, rl = threadIdx.x / B;
@@ -85,18 +91,18 @@ k_apply(const typename Cx<T>::V* __restrict__ x, typename Cx<T>::V* __restrict__
     const uint32_t r = w.t * R + rl;
     if (r >= hv.D) continue;
     typename Cx<T>::V xr;
-    y[(size_t)r * B + b] = h_row<T, CSR>(r, b, a, sh, hv, x, xr);
+    y[(size_t)r * B + b] = h_row<T, CSR, S>(r, b, a, sh, hv, x, xr);
   }
 }
 
-template <typename T, bool CSR>
+template <typename T, bool CSR, typename S>
 __global__ void __launch_bounds__(kMaxBlock)
 k_lanczos_A(const typename Cx<T>::V* __restrict__ uj, const typename Cx<T>::V* __restrict__ ujm1,
-            typename Cx<T>::V* __restrict__ w, ModelArgs a, HamView hv, const uint32_t* __restrict__ gtab,
+            typename Cx<T>::V* __restrict__ w, ModelArgs a, HamView<S> hv, const uint32_t* __restrict__ gtab,
             const double* __restrict__ gfields, KState st, LanczosArgs la, const double* __restrict__ partB, int Gp,
             double* __restrict__ partA) {
   using V = typename Cx<T>::V;
-  __shared__ RowShared sh;
+  __shared__ RowShared<S> sh;
   __shared__ double red[kQA * kMaxBlock];
   __shared__ double tot[QK_MAX_BATCH];
   __shared__ double sa[QK_MAX_BATCH], sb[QK_MAX_BATCH];
@@ -115,7 +121,7 @@ k_lanczos_A(const typename Cx<T>::V* __restrict__ uj, const typename Cx<T>::V* _
       const uint32_t r = tw.t * R + rl;
       if (r >= hv.D) continue;
       V xr;
-      const V hx = h_row<T, CSR>(r, b, a, sh, hv, uj, xr);
+      const V hx = h_row<T, CSR, S>(r, b, a, sh, hv, uj, xr);
       V wv;
       wv.x = ca * hx.x;
       wv.y = ca * hx.y;
@@ -552,32 +558,36 @@ k_overlap_final(const double* __restrict__ part, int G, int B, double* P, const 
 
 // ------------------------------------------------------------- CSR form
 // Counting pass = the exact preallocation of Sec. 3.
+template <typename S>
 __global__ void __launch_bounds__(kMaxBlock)
-k_csr_count(const uint32_t* __restrict__ states, uint32_t D, ModelArgs a, uint32_t* __restrict__ cnt) {
+k_csr_count(const S* __restrict__ states, uint32_t D, ModelArgs a, uint32_t* __restrict__ cnt) {
   const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= D) return;
-  const uint32_t s = states[r];
-  uint32_t n = (uint32_t)__popc((s ^ (s >> 1)) & (a.lmask >> 1));
-  if (a.pbc) n += ((s ^ (s >> (a.L - 1))) & 1u);
+  const S s = states[r];
+  uint32_t n = (uint32_t)popc((S)((s ^ (s >> 1)) & ((S)a.lmask >> 1)));
+  if (a.pbc) n += (uint32_t)((s ^ (s >> (a.L - 1))) & (S)1);
   cnt[r] = n;
 }
 
+template <typename S>
 __global__ void __launch_bounds__(kMaxBlock)
-k_csr_fill(const uint32_t* __restrict__ states, uint32_t D, ModelArgs a, const uint32_t* __restrict__ gtab,
+k_csr_fill(const S* __restrict__ states, uint32_t D, ModelArgs a, const uint32_t* __restrict__ gtab,
            const uint32_t* __restrict__ rowptr, uint32_t* __restrict__ cols) {
-  __shared__ uint32_t tab[kBinomStride * kBinomStride];
-  for (int i = threadIdx.x; i < kBinomStride * kBinomStride; i += blockDim.x) tab[i] = gtab[i];
+  constexpr int K = StateT<S>::kStride;
+  __shared__ uint32_t tab[K * K];
+  for (int i = threadIdx.x; i < K * K; i += blockDim.x) tab[i] = gtab[i];
   __syncthreads();
   const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= D) return;
   uint32_t k = rowptr[r];
-  for_each_hop(states[r], r, a, tab, [&](uint32_t c) { cols[k++] = c; });
+  for_each_hop<S>(states[r], r, a, tab, [&](uint32_t c) { cols[k++] = c; });
 }
 
+template <typename S>
 __global__ void __launch_bounds__(kMaxBlock)
-k_csr_diag(const uint32_t* __restrict__ states, uint32_t D, ModelArgs a, const double* __restrict__ gfields,
+k_csr_diag(const S* __restrict__ states, uint32_t D, ModelArgs a, const double* __restrict__ gfields,
            double* __restrict__ diag) {
-  __shared__ double fld[QK_MAX_BATCH * QK_MAX_L];
+  __shared__ double fld[kFldCap];
   __shared__ double hh[QK_MAX_BATCH];
   for (int i = threadIdx.x; i < a.B * a.L; i += blockDim.x) fld[i] = gfields[i];
   __syncthreads();
@@ -589,8 +599,8 @@ k_csr_diag(const uint32_t* __restrict__ states, uint32_t D, ModelArgs a, const d
   __syncthreads();
   const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= D) return;
-  const uint32_t s = states[r];
-  for (int b = 0; b < a.B; ++b) diag[(size_t)r * a.B + b] = diag_value(s, a, fld + b * a.L, hh[b]);
+  const S s = states[r];
+  for (int b = 0; b < a.B; ++b) diag[(size_t)r * a.B + b] = diag_value<S>(s, a, fld + b * a.L, hh[b]);
 }
 
 // ================================================================ launchers
@@ -621,9 +631,10 @@ int stream_grid(uint64_t rows, int B, int threads, int blocks_per_cu) {
   return (int)g;
 }
 
-static HamView ham_view(const qk_ham* H) {
-  HamView v;
-  v.states = H->basis->d_states;
+template <typename S>
+static HamView<S> ham_view(const qk_ham* H) {
+  HamView<S> v;
+  v.states = (const S*)H->basis->d_states;
   v.rowptr = H->d_rowptr;
   v.cols = H->d_cols;
   v.diag = H->d_diag;
@@ -639,7 +650,7 @@ ModelArgs model_args(const qk_ham* H) {
   a.B = H->batch;
   a.half_jxy = 0.5 * H->p.jxy;
   a.jz = H->p.jz;
-  a.lmask = a.L >= 32 ? 0xffffffffu : ((1u << a.L) - 1u);
+  a.lmask = a.L >= 64 ? ~0ull : ((1ull << a.L) - 1ull);
   return a;
 }
 
@@ -660,13 +671,22 @@ KState make_kstate(const qk_krylov* k) {
   return s;
 }
 
+int binom_stride(const qk_basis* b) { return b->wide ? StateT<uint64_t>::kStride : StateT<uint32_t>::kStride; }
+
 qk_status launch_basis_build(qk_basis* b, hipStream_t s) {
-  hipLaunchKernelGGL(k_binom_table, dim3(1), dim3(1), 0, s, b->d_binom);
-  QK_HIP(hipGetLastError());
   const uint64_t per = (uint64_t)kBasisThreads * kBasisChunk;
   const uint64_t blocks = ((uint64_t)b->D + per - 1) / per;
-  hipLaunchKernelGGL(k_basis_build, dim3((unsigned)blocks), dim3(kBasisThreads), 0, s, b->d_states,
-                     (uint32_t)b->D, b->L, b->N, b->d_binom);
+  if (b->wide) {
+    hipLaunchKernelGGL(k_binom_table<StateT<uint64_t>::kStride>, dim3(1), dim3(1), 0, s, b->d_binom);
+    QK_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_basis_build<uint64_t>, dim3((unsigned)blocks), dim3(kBasisThreads), 0, s,
+                       (uint64_t*)b->d_states, (uint32_t)b->D, b->L, b->N, b->d_binom);
+  } else {
+    hipLaunchKernelGGL(k_binom_table<StateT<uint32_t>::kStride>, dim3(1), dim3(1), 0, s, b->d_binom);
+    QK_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_basis_build<uint32_t>, dim3((unsigned)blocks), dim3(kBasisThreads), 0, s,
+                       (uint32_t*)b->d_states, (uint32_t)b->D, b->L, b->N, b->d_binom);
+  }
   QK_HIP(hipGetLastError());
   return QK_OK;
 }
@@ -674,7 +694,12 @@ qk_status launch_basis_build(qk_basis* b, hipStream_t s) {
 qk_status launch_rank(const qk_basis* b, const uint64_t* d_in, int64_t n, int64_t* d_out, hipStream_t s) {
   if (n == 0) return QK_OK;
   const int64_t blocks = (n + 255) / 256;
-  hipLaunchKernelGGL(k_rank, dim3((unsigned)blocks), dim3(256), 0, s, d_in, n, d_out, b->L, b->N, b->d_binom);
+  if (b->wide)
+    hipLaunchKernelGGL(k_rank<uint64_t>, dim3((unsigned)blocks), dim3(256), 0, s, d_in, n, d_out, b->L, b->N,
+                       b->d_binom);
+  else
+    hipLaunchKernelGGL(k_rank<uint32_t>, dim3((unsigned)blocks), dim3(256), 0, s, d_in, n, d_out, b->L, b->N,
+                       b->d_binom);
   QK_HIP(hipGetLastError());
   return QK_OK;
 }
@@ -682,8 +707,12 @@ qk_status launch_rank(const qk_basis* b, const uint64_t* d_in, int64_t n, int64_
 qk_status launch_csr_diag(qk_ham* H, hipStream_t s) {
   const ModelArgs a = model_args(H);
   const uint32_t D = (uint32_t)H->basis->D;
-  hipLaunchKernelGGL(k_csr_diag, dim3((D + 255) / 256), dim3(256), 0, s, H->basis->d_states, D, a, H->d_fields,
-                     H->d_diag);
+  if (H->basis->wide)
+    hipLaunchKernelGGL(k_csr_diag<uint64_t>, dim3((D + 255) / 256), dim3(256), 0, s,
+                       (const uint64_t*)H->basis->d_states, D, a, H->d_fields, H->d_diag);
+  else
+    hipLaunchKernelGGL(k_csr_diag<uint32_t>, dim3((D + 255) / 256), dim3(256), 0, s,
+                       (const uint32_t*)H->basis->d_states, D, a, H->d_fields, H->d_diag);
   QK_HIP(hipGetLastError());
   return QK_OK;
 }
@@ -693,7 +722,12 @@ qk_status launch_csr_build(qk_ham* H, hipStream_t s) {
   const uint32_t D = (uint32_t)H->basis->D;
   // count into rowptr[1..D], then an inclusive scan in place gives the row pointers
   QK_HIP(hipMemsetAsync(H->d_rowptr, 0, sizeof(uint32_t), s));
-  hipLaunchKernelGGL(k_csr_count, dim3((D + 255) / 256), dim3(256), 0, s, H->basis->d_states, D, a, H->d_rowptr + 1);
+  if (H->basis->wide)
+    hipLaunchKernelGGL(k_csr_count<uint64_t>, dim3((D + 255) / 256), dim3(256), 0, s,
+                       (const uint64_t*)H->basis->d_states, D, a, H->d_rowptr + 1);
+  else
+    hipLaunchKernelGGL(k_csr_count<uint32_t>, dim3((D + 255) / 256), dim3(256), 0, s,
+                       (const uint32_t*)H->basis->d_states, D, a, H->d_rowptr + 1);
   QK_HIP(hipGetLastError());
   size_t tmp_bytes = 0;
   QK_HIP(hipcub::DeviceScan::InclusiveSum(nullptr, tmp_bytes, H->d_rowptr + 1, H->d_rowptr + 1, (int)D, s));
@@ -707,36 +741,58 @@ qk_status launch_csr_build(qk_ham* H, hipStream_t s) {
   QK_HIP(hipStreamSynchronize(s));
   H->nnz = nnz;
   QK_HIP(hipMalloc(&H->d_cols, sizeof(uint32_t) * (size_t)(nnz > 0 ? nnz : 1)));
-  hipLaunchKernelGGL(k_csr_fill, dim3((D + 255) / 256), dim3(256), 0, s, H->basis->d_states, D, a, H->basis->d_binom,
-                     H->d_rowptr, H->d_cols);
+  if (H->basis->wide)
+    hipLaunchKernelGGL(k_csr_fill<uint64_t>, dim3((D + 255) / 256), dim3(256), 0, s,
+                       (const uint64_t*)H->basis->d_states, D, a, H->basis->d_binom, H->d_rowptr, H->d_cols);
+  else
+    hipLaunchKernelGGL(k_csr_fill<uint32_t>, dim3((D + 255) / 256), dim3(256), 0, s,
+                       (const uint32_t*)H->basis->d_states, D, a, H->basis->d_binom, H->d_rowptr, H->d_cols);
   QK_HIP(hipGetLastError());
   return launch_csr_diag(H, s);
 }
 
-qk_status launch_ham_apply(const qk_ham* H, const void* x, void* y, int dtype, hipStream_t s) {
-  if (blocked_usable(H, dtype)) return launch_blocked_apply(H, x, y, dtype, s);
+template <typename T, typename S>
+static void launch_apply_rows(const qk_ham* H, const void* x, void* y, hipStream_t s) {
+  using V = typename Cx<T>::V;
   const ModelArgs a = model_args(H);
-  const HamView hv = ham_view(H);
+  const HamView<S> hv = ham_view<S>(H);
   const int threads = block_threads(a.B);
   const int grid = stream_grid(hv.D, a.B, threads, 0);
-  const bool csr = H->p.mode == QK_CSR;
+  if (H->p.mode == QK_CSR)
+    hipLaunchKernelGGL((k_apply<T, true, S>), dim3(grid), dim3(threads), 0, s, (const V*)x, (V*)y, a, hv,
+                       H->basis->d_binom, H->d_fields);
+  else
+    hipLaunchKernelGGL((k_apply<T, false, S>), dim3(grid), dim3(threads), 0, s, (const V*)x, (V*)y, a, hv,
+                       H->basis->d_binom, H->d_fields);
+}
+
+qk_status launch_ham_apply(const qk_ham* H, const void* x, void* y, int dtype, hipStream_t s) {
+  if (blocked_usable(H, dtype)) return launch_blocked_apply(H, x, y, dtype, s);
+  const bool wide = H->basis->wide;
   if (dtype == QK_C128) {
-    if (csr)
-      hipLaunchKernelGGL((k_apply<double, true>), dim3(grid), dim3(threads), 0, s, (const double2*)x, (double2*)y, a,
-                         hv, H->basis->d_binom, H->d_fields);
-    else
-      hipLaunchKernelGGL((k_apply<double, false>), dim3(grid), dim3(threads), 0, s, (const double2*)x, (double2*)y,
-                         a, hv, H->basis->d_binom, H->d_fields);
+    if (wide) launch_apply_rows<double, uint64_t>(H, x, y, s);
+    else launch_apply_rows<double, uint32_t>(H, x, y, s);
   } else {
-    if (csr)
-      hipLaunchKernelGGL((k_apply<float, true>), dim3(grid), dim3(threads), 0, s, (const float2*)x, (float2*)y, a,
-                         hv, H->basis->d_binom, H->d_fields);
-    else
-      hipLaunchKernelGGL((k_apply<float, false>), dim3(grid), dim3(threads), 0, s, (const float2*)x, (float2*)y, a,
-                         hv, H->basis->d_binom, H->d_fields);
+    if (wide) launch_apply_rows<float, uint64_t>(H, x, y, s);
+    else launch_apply_rows<float, uint32_t>(H, x, y, s);
   }
   QK_HIP(hipGetLastError());
   return QK_OK;
+}
+
+// H-pass of Lanczos iteration j through the row kernels (CSR or matrix-free rows).
+template <typename T, typename S>
+static void launch_lanczos_rows(const qk_ham* H, const typename Cx<T>::V* uj, const typename Cx<T>::V* ujm1,
+                                typename Cx<T>::V* w, const KState& st, const LanczosArgs& la, const double* partB,
+                                int G, int threads, double* partA, hipStream_t s) {
+  const ModelArgs a = model_args(H);
+  const HamView<S> hv = ham_view<S>(H);
+  if (H->p.mode == QK_CSR)
+    hipLaunchKernelGGL((k_lanczos_A<T, true, S>), dim3(G), dim3(threads), 0, s, uj, ujm1, w, a, hv,
+                       H->basis->d_binom, H->d_fields, st, la, partB, G, partA);
+  else
+    hipLaunchKernelGGL((k_lanczos_A<T, false, S>), dim3(G), dim3(threads), 0, s, uj, ujm1, w, a, hv,
+                       H->basis->d_binom, H->d_fields, st, la, partB, G, partA);
 }
 
 struct AdaptiveStep {
@@ -748,15 +804,12 @@ static qk_status krylov_step_t(qk_krylov* k, void* psi_v, double dt, hipStream_t
                                const AdaptiveStep* ad = nullptr) {
   using V = typename Cx<T>::V;
   const qk_ham* H = k->H;
-  const ModelArgs a = model_args(H);
-  const HamView hv = ham_view(H);
-  const int B = a.B, threads = krylov_threads(k), G = k->grid, m = k->m;
-  const uint32_t D = hv.D;
+  const int B = H->batch, threads = krylov_threads(k), G = k->grid, m = k->m;
+  const uint32_t D = (uint32_t)H->basis->D;
   const size_t stride = (size_t)D * B;
   V* psi = (V*)psi_v;
   V* U = (V*)k->d_U;
   const KState st = make_kstate(k);
-  const bool csr = H->p.mode == QK_CSR;
   // breakdown threshold relative to the largest coefficient so far
   const double rtol = std::is_same<T, double>::value ? 1e-12 : 1e-5;
 #define QK_MARK(kind, begin)                                   \
@@ -777,12 +830,11 @@ static qk_status krylov_step_t(qk_krylov* k, void* psi_v, double dt, hipStream_t
       qk_status bs = launch_blocked_lanczos_h(H, k->dtype, uj, ujm1, w, st, la, k->d_partB, G, k->d_partA, &Ga,
                                               k->blocked_wgs, s);
       if (bs != QK_OK) return bs;
-    } else if (csr)
-      hipLaunchKernelGGL((k_lanczos_A<T, true>), dim3(G), dim3(threads), 0, s, uj, ujm1, w, a, hv,
-                         H->basis->d_binom, H->d_fields, st, la, k->d_partB, G, k->d_partA);
-    else
-      hipLaunchKernelGGL((k_lanczos_A<T, false>), dim3(G), dim3(threads), 0, s, uj, ujm1, w, a, hv,
-                         H->basis->d_binom, H->d_fields, st, la, k->d_partB, G, k->d_partA);
+    } else if (H->basis->wide) {
+      launch_lanczos_rows<T, uint64_t>(H, uj, ujm1, w, st, la, k->d_partB, G, threads, k->d_partA, s);
+    } else {
+      launch_lanczos_rows<T, uint32_t>(H, uj, ujm1, w, st, la, k->d_partB, G, threads, k->d_partA, s);
+    }
     QK_HIP(hipGetLastError());
     QK_MARK(QK_KERNEL_LANCZOS_H, false);
     QK_MARK(QK_KERNEL_LANCZOS_UPDATE, true);

@@ -51,8 +51,11 @@ def test_version_and_validation_without_device():
     from paper_1704_02770_amd._native import lib
     assert qk.qk_abi_version() == 1
     out = C.c_void_p()
-    assert lib.qk_basis_build(40, 20, None, C.byref(out)) == qk.QK_EINVAL
+    assert lib.qk_basis_build(65, 2, None, C.byref(out)) == qk.QK_EINVAL
     assert b"L must be" in lib.qk_last_error()
+    # C(40, 20) > 2^32: 64-bit states are supported, but not sectors that large
+    assert lib.qk_basis_build(40, 20, None, C.byref(out)) == qk.QK_EUNSUPPORTED
+    assert b"below 2^32" in lib.qk_last_error()
     assert lib.qk_basis_build(1, 1, None, C.byref(out)) == qk.QK_EINVAL
     assert lib.qk_basis_build(8, 0, None, C.byref(out)) == qk.QK_EINVAL
     assert lib.qk_basis_build(8, 8, None, C.byref(out)) == qk.QK_EINVAL

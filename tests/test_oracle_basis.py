@@ -105,3 +105,23 @@ def test_fields_special_beta():
     assert np.allclose(f, 2.0 * np.cos(0.3) * np.array([-1, 1, -1, 1, -1, 1]))
     # beta = 1 makes it uniform
     assert np.allclose(M.fields(5, 1.5, 1.0, 0.7), 1.5 * np.cos(0.7))
+
+
+def test_large_sector_enumeration():
+    # the subset route used above L = 30 against the full scan on sectors both
+    # can list, then the count and order at L = 55 and L = 63
+    from itertools import combinations
+    for L, N in [(20, 3), (22, 11), (24, 1), (24, 23)]:
+        scan = B.sector_states(L, N)
+        sub = np.array(sorted(sum(1 << p for p in c) for c in combinations(range(L), N)), dtype=np.int64)
+        assert np.array_equal(scan, sub)
+    for L, N in [(55, 3), (63, 2), (40, 5)]:
+        st = B.sector_states(L, N)
+        assert len(st) == B.sector_dim(L, N)
+        assert np.all(np.diff(st) > 0)
+        assert np.all(np.bitwise_count(st) == N)
+        assert st[0] == (1 << N) - 1 and st[-1] == ((1 << N) - 1) << (L - N)
+        # Alg. 3's first_int and Alg. 2's walk agree with the list
+        for r in (0, 1, len(st) // 3, len(st) - 1):
+            assert B.first_int(L, N, r) == st[r]
+        assert B.basis_alg2(L, N, start_state=int(st[5]), count=50) == [int(v) for v in st[5:55]]
