@@ -9,6 +9,7 @@ import test_oracle_hamiltonian as TH
 import test_oracle_propagation as TP
 from oracle import basis as B
 from oracle import exact as X
+from oracle import gradient as G
 from oracle import hamiltonian as Hm
 from oracle import krylov as K
 from oracle import model as M
@@ -21,6 +22,9 @@ _orig_evolve = X.evolve
 _orig_amp = X.survival_amplitude
 _orig_nbp = B.next_bit_permutation
 _orig_first = B.first_int
+_orig_states = B.sector_states
+_orig_acx = X.autocorrelation_exact
+_orig_dF = G.dF_dh
 
 
 def _fails(*checks):
@@ -70,6 +74,39 @@ def _bad_first(L, N, start):
     return _orig_first(L, N, max(start - 1, 0)) if start == 3 else _orig_first(L, N, start)
 
 
+def _sinc_without_time(H, psi0, times, eigsys=None):
+    # the time average taken as sin(dE t) / dE instead of sin(dE t) / (dE t)
+    t = np.atleast_1d(np.asarray(times, dtype=float))
+    return _orig_acx(H, psi0, times, eigsys) * np.where(t > 1.0, t, 1.0)
+
+
+def _acx_diagonal_only(H, psi0, times, eigsys=None):
+    # only the n == m terms: the long-time limit at every time
+    w, U = X.eig(H) if eigsys is None else eigsys
+    wn = np.abs(U.T @ np.asarray(psi0, dtype=np.complex128)) ** 2
+    return np.full(len(np.atleast_1d(times)), float(np.sum(wn ** 2)))
+
+
+def _subsets_shifted(L, N):
+    # bit positions 1..L instead of 0..L-1 above the scan range
+    if L <= 30:
+        return _orig_states(L, N)
+    from itertools import combinations
+    return np.array(sorted(sum(1 << p for p in c) for c in combinations(range(1, L + 1), N)), dtype=np.int64)
+
+
+def _dF_half(*args, **kw):
+    # 2 Re(conj(A) dA) taken without the factor 2
+    F, g = _orig_dF(*args, **kw)
+    return F, 0.5 * g
+
+
+def _dF_sites_reversed(*args, **kw):
+    # derivative assigned to the mirrored site
+    F, g = _orig_dF(*args, **kw)
+    return F, g[::-1].copy()
+
+
 def _hop_full(jxy):
     return jxy
 
@@ -89,6 +126,11 @@ PLANTS = {
     "transposed eigenvectors": [(X, "evolve", _transposed_U)],
     "wrong refill shift in Algorithm 2": [(B, "next_bit_permutation", _bad_nbp)],
     "off-by-one section start": [(B, "first_int", _bad_first)],
+    "autocorrelation without the 1/t": [(X, "autocorrelation_exact", _sinc_without_time)],
+    "autocorrelation keeps only n == m": [(X, "autocorrelation_exact", _acx_diagonal_only)],
+    "large sectors on shifted bits": [(B, "sector_states", _subsets_shifted)],
+    "gradient without the factor 2": [(G, "dF_dh", _dF_half)],
+    "gradient on mirrored sites": [(G, "dF_dh", _dF_sites_reversed)],
 }
 
 CHECKS = [
@@ -101,6 +143,9 @@ CHECKS = [
     TP.test_norm_energy_conservation_and_time_reversal, TP.test_expm_multiply_matches_dense,
     TP.test_krylov_converged_matches_exact,
     lambda: TB.test_fields_special_beta(),
+    TP.test_autocorrelation_exact_two_level_closed_form, TP.test_autocorrelation_exact_limits_and_trapezoid,
+    TB.test_large_sector_enumeration,
+    lambda: TG.test_daleckii_krein_vs_finite_differences(True), TG.test_gradient_sums_to_zero,
 ]
 
 
