@@ -717,12 +717,12 @@ static qk_status launch_blk_t(const qk_ham* H, const void* x, void* y, const voi
   BlkArgs ba = blk_args(H);
   const size_t dyn = blk_xbytes<T, LLO>() + 2 * sizeof(uint16_t) * ((size_t)1 << LLO);
   auto kern = k_blk<T, LLO, LANCZOS>;
-  static int occ = 0;
-  if (occ == 0) {
+  // work-groups per CU the kernel can hold (queried once per instantiation; thread-safe static init)
+  static const int occ = [&]() {
     int n = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, kern, kBlkThreads, dyn) != hipSuccess || n < 1) n = 1;
-    occ = n;
-  }
+    return n;
+  }();
   const int cus = qk_num_cus();
   int wgs = wgs_req > 0 ? wgs_req : env_int("QK_BLOCKED_WGS_PER_CU", occ);
   if (wgs > occ) wgs = occ;

@@ -605,14 +605,14 @@ k_csr_diag(const S* __restrict__ states, uint32_t D, ModelArgs a, const double* 
 
 // ================================================================ launchers
 int qk_num_cus() {
-  static int n = 0;
-  if (n == 0) {
-    int dev = 0;
+  // compute units of the current device, queried once (thread-safe static init)
+  static const int n = []() {
+    int dev = 0, c = 0;
     hipDeviceProp_t prop;
     if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
-      n = prop.multiProcessorCount;
-    if (n <= 0) n = 256;
-  }
+      c = prop.multiProcessorCount;
+    return c > 0 ? c : 256;
+  }();
   return n;
 }
 
