@@ -1,9 +1,10 @@
-"""GPU parity at full size, in the launch configuration the benchmark times
-(blocked matrix-free H-pass, B = 1): the mid-size L=24 chain against exact
+"""GPU parity at full size, in the launch configurations the benchmark times
+(blocked matrix-free H-pass for one phase and for 8 phases): the mid-size L=24 chain against exact
 propagation at short times and against the free-fermion closed form at all
 200 output times; the L=28 and L=30 chains against the free-fermion closed
 form (zz coupling 0, same kernels); and, where no exact reference exists
-(L=28/30 with zz coupling), the invariants and the FP64/FP32 agreement."""
+(L=28/30 with zz coupling), the invariants and the FP64/FP32 agreement; the
+8-phase complex64 form at L=28 against the oracle's rows and single-phase runs."""
 import math
 import os
 
@@ -159,3 +160,53 @@ def test_l30_fp64_vs_fp32(h):
     err = np.max(np.abs(P32 - P64))
     say("  complex64 vs complex128 max |dP| =", err)
     assert err < 1e-5
+
+
+def test_l28_batched_form_at_full_size():
+    # the benchmark's batched form: 8 phases of the L=28 ring in complex64
+    # ([D][8], batched blocked H-pass).  Sampled rows of H x against the
+    # oracle row by row, then three Krylov steps against each phase run alone
+    # in complex64 and in complex128.
+    from oracle import basis as OB2
+    L, Bn, N = 28, 8, 14
+    b = qk.qk_basis_build(L, N)
+    D = qk.qk_basis_dim(b)
+    hs = np.stack([OM.fields(L, 1.5, BETA_GOLDEN, p) for p in phases(Bn, 0)])
+    H = qk.qk_ham_create(b, 1.0, 1.0, True, hs)
+    say("L28 batched hv")
+    rng = np.random.default_rng(3)
+    X = (rng.standard_normal((D, Bn)) + 1j * rng.standard_normal((D, Bn))).astype(np.complex64)
+    xd = torch.from_numpy(X).to("cuda")
+    y = qk.qk_ham_apply(H, xd)
+    rows = np.unique(np.concatenate([rng.integers(0, D, 2000), [0, D - 1]]))
+    yr = y[torch.from_numpy(rows).to("cuda")].cpu().numpy()
+    basis = OB2.sector_states(L, N)
+    ref = OH.apply_rows(L, N, True, 1.0, 1.0, hs, X.astype(np.complex128), rows, basis=basis)
+    assert np.max(np.abs(yr - ref)) / np.max(np.abs(ref)) < 2e-6
+    del y, xd
+    r0 = _neel_row(b, L)
+    psib = torch.zeros((D, Bn), dtype=torch.complex64, device="cuda")
+    psib[r0] = 1.0
+    kb = qk.qk_krylov_create(H, 30, torch.complex64)
+    say("L28 batched steps")
+    for _ in range(3):
+        qk.qk_krylov_expm_step(kb, psib, 0.1)
+    Pb = to_host(qk.qk_return_prob(b, psib, r0=r0, batch=Bn))
+    del kb
+    torch.cuda.empty_cache()
+    for i in (0, 5):
+        H1 = qk.qk_ham_create(b, 1.0, 1.0, True, hs[i])
+        for dtype, tol in ((torch.complex64, 2e-6), (torch.complex128, 1e-5)):
+            p1 = torch.zeros(D, dtype=dtype, device="cuda")
+            p1[r0] = 1.0
+            k1 = qk.qk_krylov_create(H1, 30, dtype)
+            for _ in range(3):
+                qk.qk_krylov_expm_step(k1, p1, 0.1)
+            P1 = abs(p1[r0].item()) ** 2
+            say("  phase", i, dtype, "batched P", Pb[i], "single P", P1)
+            assert abs(Pb[i] - P1) < tol
+            if dtype == torch.complex64:
+                d = (psib[:, i] - p1).abs().max().item() / p1.abs().max().item()
+                assert d < 2e-5
+            del k1, p1
+            torch.cuda.empty_cache()
