@@ -30,7 +30,7 @@
  *     untouched.  qk_last_error() returns a thread-local text for the last
  *     failing call on the calling thread.  Nothing aborts or throws across
  *     this boundary.
- *   - Handles (qk_basis, qk_ham, qk_krylov) are created on the current HIP
+ *   - Handles (qk_basis, qk_ham, qk_krylov, qk_batch) are created on the current HIP
  *     device, own their device memory, and are released only by the matching
  *     *_destroy (which accepts NULL and synchronises the device first).  A
  *     handle may be used by one stream at a time; calls on a handle from
@@ -57,7 +57,7 @@ typedef enum {
   QK_ENOMEM = 2,        /* device allocation failed */
   QK_EHIP = 3,          /* a HIP runtime call failed (text in qk_last_error) */
   QK_EUNSUPPORTED = 4,  /* valid request outside what this build implements */
-  QK_ENUMERIC = 5       /* non-finite Lanczos coefficient detected */
+  QK_ENUMERIC = 5       /* non-finite Lanczos coefficient, or an adaptive evolution that could not reach t */
 } qk_status;
 
 typedef enum { QK_C128 = 0, QK_C64 = 1 } qk_dtype;
@@ -208,7 +208,8 @@ qk_status qk_krylov_expm_step(qk_krylov* k, void* psi, double dt, void* stream, 
  * below about tol * t.  All batch items advance by the smallest accepted
  * step.  t >= 0; tol > 0; dt_init > 0 (first trial step); dt_max > 0;
  * max_steps >= 1 bounds the accepted steps (QK_ENUMERIC with a message when
- * t is not reached).  Synchronous (one small read-back per step).  info_host
+ * t is not reached; psi then holds the state after the last accepted step).
+ * Synchronous (one small read-back per step).  info_host
  * (may be NULL) receives the number of steps, the smallest and largest
  * accepted step and the sum of the error estimates of batch item 0.
  */
