@@ -263,25 +263,31 @@ def main():
 
     if not res:
         raise SystemExit("at least one of the forms fp64, fp32, batched is needed")
-    head = res.get("fp64") or next(iter(res.values()))
+    head_form = "fp64" if "fp64" in res else next(iter(res))
+    head = res[head_form]
     steps = args.steps
     value = steps / head["sec"]
-    s_bytes = 16
+    # element bytes and phases of the head form (the roofline's kernel)
+    s_bytes = 16 if head_form == "fp64" else 8
+    B_head = args.batch if head_form == "batched" else 1
     # dominant kernel: the H-pass of each Lanczos iteration.  Algorithmic
     # bytes per step: iteration 0 reads u_0 and writes w (2 vectors), later
     # iterations also read u_{j-1} (3 vectors).
     ms_h, n_h = head["prof"]["lanczos_h"]
-    bytes_h_step = (3 * m - 1) * s_bytes * D
+    bytes_h_step = (3 * m - 1) * s_bytes * D * B_head
     achieved = bytes_h_step * steps / (ms_h / 1e3) / 1e9
     traffic = None
-    if os.path.exists(TRAFFIC_FILE):
+    if head_form == "fp64" and os.path.exists(TRAFFIC_FILE):
         tr = json.load(open(TRAFFIC_FILE))
         if tr.get("kernel_source_sha256") == source_sha() and tr.get("m") == m and tr.get("L") == L:
             traffic = tr.get("bytes_per_launch")
     roof = dict(bound="hbm", achieved=round(achieved, 1), peak=PEAK_HBM_GBS, unit="GB/s",
                 frac=round(achieved / PEAK_HBM_GBS, 4), traffic=traffic,
                 kernel=("H-pass of the Lanczos iteration, w = a H u_j - b u_{j-1} with its dot products "
-                        "(k_blk<double,11,true>, the blocked matrix-free kernel used for L >= 18)"),
+                        + {"fp64": "(k_blk<double,11,true>, the blocked matrix-free kernel used for L >= 18)",
+                           "fp32": "(k_blk<float,11,true>, complex64 storage)",
+                           "batched": f"(k_blkb<float,true>, {args.batch} phases in complex64)"}[head_form]),
+                form=head_form,
                 bytes_per_launch_avg=bytes_h_step / m, ms_per_launch_avg=ms_h / max(n_h, 1))
 
     def form_summary(r, B, s):
