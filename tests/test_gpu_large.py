@@ -210,3 +210,28 @@ def test_l28_batched_form_at_full_size():
                 assert d < 2e-5
             del k1, p1
             torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("pbc,h", [(False, 1.0), (True, 3.0)])
+def test_l24_long_times_invariants(pbc, h):
+    # the mid-size workload with zz coupling to t = 100 (200 log-spaced
+    # outputs), where no exact reference is computed: the norm and the energy
+    # <psi|H|psi> are conserved, P stays in [0, 1], halving the step changes
+    # nothing beyond rounding, and complex64 storage agrees with complex128
+    times = log_times()
+    b = qk.qk_basis_build(24, 12)
+    hf = OM.fields(24, h, BETA_GOLDEN, PHI)
+    H = qk.qk_ham_create(b, 1.0, 1.0, pbc, hf)
+    say("L24 long times", pbc, h)
+    P, psi, r0 = _evolve(b, H, 24, times, 30, 0.1)
+    assert np.all(P >= 0.0) and np.all(P <= 1.0 + 1e-12)
+    assert abs(torch.linalg.vector_norm(psi).item() - 1.0) < 1e-11
+    E0 = float(OH.diagonal(np.array([OM.neel_state(24)]), 24, pbc, 1.0, hf)[0])
+    E = torch.vdot(psi, qk.qk_ham_apply(H, psi)).real.item()
+    assert abs(E - E0) < 1e-9 * max(1.0, abs(E0))
+    P_half, _, _ = _evolve(b, H, 24, times, 30, 0.05)
+    say("  step halving max |dP| =", np.max(np.abs(P - P_half)))
+    assert np.max(np.abs(P - P_half)) < 1e-10
+    P32, _, _ = _evolve(b, H, 24, times, 30, 0.1, torch.complex64)
+    say("  complex64 vs complex128 max |dP| =", np.max(np.abs(P32 - P)))
+    assert np.max(np.abs(P32 - P)) < 1e-5
