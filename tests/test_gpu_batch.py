@@ -82,10 +82,11 @@ def test_graph_replays_with_eager_work_between():
 
 def test_mixed_lengths_fp32_vs_fp64_workload():
     # 64 phases at L=20 plus single chains L=16, 18, 20, 22 (h=2, m=30,
-    # dt=0.1), complex64 vectors with FP64 Lanczos coefficients, against the
-    # same problems in complex128; the FP32 error is reported and bounded.
+    # dt=0.1 to t=50), complex64 vectors with FP64 Lanczos coefficients,
+    # against the same problems in complex128; the FP32 error is reported and
+    # bounded.
     spec = [(20, 64), (16, 1), (18, 1), (20, 1), (22, 1)]
-    steps, dt = 20, 0.1
+    steps, dt = 500, 0.1
     res = {}
     for dtype in (torch.complex128, torch.complex64):
         ws = [_ws(L, Bn, dtype, seed=i) for i, (L, Bn) in enumerate(spec)]
