@@ -12,7 +12,7 @@ from paper_1704_02770_amd.autograd import survival_probability
 from gpu_util import neel_row, say
 from oracle import gradient as OG
 from oracle import model as OM
-from workloads import BETA_GOLDEN
+from workloads import BETA_GOLDEN, WORKLOADS
 
 pytestmark = pytest.mark.gpu
 
@@ -42,10 +42,12 @@ def test_gradient_vs_daleckii_krein(L, pbc, h, jz, T, n_steps):
 
 
 def test_gradient_vs_finite_differences_L20():
-    # T = 5, dt = 0.1: 50 steps, central differences with eps = 1e-6 of the
-    # library's own F(T), each one a fresh forward propagation.
-    L, T, n_steps, eps = 20, 5.0, 50, 1e-6
-    b, H, k, hf = _ws(L, True, 2.0, 1.1, m=24)
+    # the gradient workload: L = 20 ring, h = 1.5, phase from seed 0, Neel
+    # state, T = 5, dt = 0.1 (50 steps), m = 30; central differences with
+    # eps = 1e-6 of the library's own F(T), each a fresh forward propagation
+    w = WORKLOADS["xxz_L20_grad"]
+    L, T, n_steps, eps = w.L, w.t_end, int(round(w.t_end / w.dt)), 1e-6
+    b, H, k, hf = _ws(L, w.pbc, w.h, float(w.phis()[0]), m=w.m)
     r0 = neel_row(L)
     say("grad L20 adjoint")
     F, g = qk.qk_grad_return_prob(k, r0, T, n_steps)
