@@ -12,7 +12,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "qk.h")
 LIB = os.path.join(ROOT, "paper_1704_02770_amd", "libqkrylov.so")
 
-pytestmark = pytest.mark.skipif(not os.path.exists(LIB), reason="libqkrylov.so not built (run __graft_entry__.build())")
+pytestmark = pytest.mark.skipif(not os.path.exists(LIB), reason="libqkrylov.so not built (run python paper_1704_02770_amd/build.py)")
 
 
 def header_symbols():
@@ -21,7 +21,7 @@ def header_symbols():
     return sorted(set(re.findall(r"\b(qk_[a-z0-9_]+)\s*\(", txt)))
 
 
-def test_header_declares_north_star_calls():
+def test_header_declares_core_calls():
     syms = header_symbols()
     for name in ["qk_basis_build", "qk_ham_apply", "qk_krylov_expm_step", "qk_return_prob"]:
         assert name in syms
