@@ -390,3 +390,33 @@ def test_full_reorthogonalisation_evolution_and_batch():
         assert np.linalg.norm(to_host(psib[:, i].contiguous()) - ref) < 1e-10
     with pytest.raises(qk.QkError):
         qk.qk_krylov_create(Hb, 20, reorth=3)
+
+
+def test_two_workspaces_on_two_streams():
+    # every launch of a call goes to the caller's stream: two workspaces
+    # (blocked L=20 and row-form L=14) stepped on two streams at once give
+    # the same bits as the same steps run one after the other
+    cases = []
+    for L in (20, 14):
+        b, H, hf = _problem(L, True, h=1.2)
+        cases.append((b, H, L))
+    def run(streams):
+        outs = []
+        ks, psis = [], []
+        for (b, H, L) in cases:
+            psi, r0 = _neel_psi(b, L)
+            ks.append(qk.qk_krylov_create(H, 30))
+            psis.append((psi, r0, b))
+        torch.cuda.synchronize()
+        for step in range(8):
+            for i, (psi, r0, b) in enumerate(psis):
+                s = streams[i] if streams else torch.cuda.current_stream()
+                with torch.cuda.stream(s):
+                    qk.qk_krylov_expm_step(ks[i], psi, 0.1, stream=s)
+        torch.cuda.synchronize()
+        return [to_host(p).copy() for p, _, _ in psis]
+    say("two streams")
+    seq = run(None)
+    par = run([torch.cuda.Stream(), torch.cuda.Stream()])
+    for a, c in zip(seq, par):
+        assert np.array_equal(a, c)
