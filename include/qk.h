@@ -66,6 +66,26 @@ typedef enum { QK_MATFREE = 0, QK_CSR = 1, QK_MATFREE_ROWS = 2 } qk_ham_mode;
 /* Version of this header the library was built from (QK_ABI_VERSION). */
 int qk_abi_version(void);
 
+/*
+ * Device memory of the handles created from now on (their tables and
+ * workspaces, and the temporaries of calls on them) comes from alloc(bytes,
+ * stream, ctx) and goes back through release(ptr, stream, ctx) -- for
+ * instance a framework's caching allocator.  alloc returns NULL on failure
+ * (reported as QK_ENOMEM).  stream NULL: the block may be used on any stream,
+ * and release comes only once no device work uses it any more.  stream
+ * non-NULL (small temporaries of one call): only work queued on that stream
+ * uses the block, and release(ptr, stream) comes right after the last of it
+ * is queued, as with hipFreeAsync -- the block may then be reused by later
+ * work on that stream, or elsewhere once that stream has reached this point.
+ * Each handle keeps the pair it was created with, so changing it later does
+ * not affect existing handles.  Both NULL restores hipMalloc /
+ * hipFree.  Process-wide; safe to call from any thread.  Errors: QK_EINVAL
+ * when exactly one of alloc, release is NULL.
+ */
+typedef void* (*qk_alloc_fn)(size_t bytes, void* stream, void* ctx);
+typedef void (*qk_release_fn)(void* ptr, void* stream, void* ctx);
+qk_status qk_set_allocator(qk_alloc_fn alloc, qk_release_fn release, void* ctx);
+
 /* Thread-local text of the last error on this thread ("" if none).  The
  * pointer stays valid until the next qk_* call on the same thread. */
 const char* qk_last_error(void);

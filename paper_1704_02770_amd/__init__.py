@@ -93,6 +93,53 @@ class Batch(_Handle):
     _destroy = staticmethod(lib.qk_batch_destroy)
 
 
+# every callback pair ever registered stays referenced: handles created with
+# it keep calling it until they are destroyed
+_allocator_refs = []
+
+
+def qk_set_allocator(alloc=None, release=None) -> None:
+    """Device memory of handles created from now on comes from
+    alloc(nbytes, stream) -> int pointer (0 on failure) and returns through
+    release(pointer, stream); stream is the raw HIP stream (an int) a
+    temporary is ordered on, or 0 for memory that may be used on any stream
+    (released only after the device work on it has finished).  Both None
+    restores hipMalloc / hipFree.  Existing handles keep their allocator."""
+    if alloc is None and release is None:
+        _check(lib.qk_set_allocator(C.cast(None, _native.ALLOC_FN), C.cast(None, _native.RELEASE_FN), None),
+               "qk_set_allocator")
+        return
+    if alloc is None or release is None:
+        raise ValueError("alloc and release must both be given")
+
+    def _alloc(nbytes, stream, ctx):
+        try:
+            return int(alloc(int(nbytes), int(stream or 0))) or None
+        except Exception:   # reported by the library as QK_ENOMEM
+            return None
+
+    def _release(ptr, stream, ctx):
+        try:
+            release(int(ptr), int(stream or 0))
+        except Exception:
+            pass
+
+    fa, fr = _native.ALLOC_FN(_alloc), _native.RELEASE_FN(_release)
+    _allocator_refs.append((fa, fr))
+    _check(lib.qk_set_allocator(fa, fr, None), "qk_set_allocator")
+
+
+def use_torch_allocator() -> None:
+    """Handles created from now on take their device memory from torch's
+    caching allocator (torch.cuda.memory_allocated counts it)."""
+    def alloc(n, stream):
+        # a block used on any stream is released after a synchronisation, so
+        # the stream torch files it under does not matter
+        return torch.cuda.caching_allocator_alloc(n, stream=stream or None)
+
+    qk_set_allocator(alloc, lambda p, stream: torch.cuda.caching_allocator_delete(p))
+
+
 def qk_abi_version() -> int:
     return int(lib.qk_abi_version())
 
@@ -361,4 +408,4 @@ def qk_return_prob(b: Basis, psi: torch.Tensor, r0: int = -1, psi0: torch.Tensor
     return out
 
 
-__all__ = [n for n in dir() if n.startswith("qk_")] + ["QkError", "Basis", "Ham", "Krylov", "Batch"]
+__all__ = [n for n in dir() if n.startswith("qk_")] + ["QkError", "Basis", "Ham", "Krylov", "Batch", "use_torch_allocator"]

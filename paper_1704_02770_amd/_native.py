@@ -48,9 +48,14 @@ class StepInfo(C.Structure):
     _fields_ = [("m_used", i32), ("status", i32), ("err_est", f64), ("beta0", f64)]
 
 
+# device-memory callbacks of qk_set_allocator
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
+RELEASE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p, C.c_void_p)
+
 # name -> (restype, argtypes); every symbol include/qk.h declares
 SIGNATURES = {
     "qk_abi_version": (C.c_int, []),
+    "qk_set_allocator": (i32, [ALLOC_FN, RELEASE_FN, vp]),
     "qk_last_error": (C.c_char_p, []),
     "qk_fields_quasiperiodic": (i32, [i32, f64, f64, P(f64), i32, P(f64)]),
     "qk_basis_build": (i32, [i32, i32, vp, P(vp)]),

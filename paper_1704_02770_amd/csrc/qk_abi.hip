@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -20,6 +21,42 @@ void set_error(const std::string& msg) { g_err = msg; }
 qk_status hip_fail(hipError_t e, const char* what) {
   g_err = std::string(what) + ": " + hipGetErrorString(e);
   return e == hipErrorOutOfMemory ? QK_ENOMEM : QK_EHIP;
+}
+
+// ---------------------------------------------------------- device memory
+static std::mutex g_alloc_mu;
+static qk_allocator g_alloc;
+
+qk_allocator current_allocator() {
+  std::lock_guard<std::mutex> lk(g_alloc_mu);
+  return g_alloc;
+}
+
+hipError_t dev_alloc(const qk_allocator& a, void** p, size_t bytes) {
+  if (!a.alloc) return hipMalloc(p, bytes);
+  *p = a.alloc(bytes, nullptr, a.ctx);
+  return *p ? hipSuccess : hipErrorOutOfMemory;
+}
+
+void dev_free(const qk_allocator& a, void* p) {
+  if (!p) return;
+  if (a.release) a.release(p, nullptr, a.ctx);
+  else hipFree(p);
+}
+
+hipError_t dev_alloc_async(const qk_allocator& a, void** p, size_t bytes, hipStream_t s) {
+  if (!a.alloc) return hipMallocAsync(p, bytes, s);
+  *p = a.alloc(bytes, (void*)s, a.ctx);
+  return *p ? hipSuccess : hipErrorOutOfMemory;
+}
+
+hipError_t dev_free_async(const qk_allocator& a, void* p, hipStream_t s) {
+  if (!p) return hipSuccess;
+  if (!a.release) return hipFreeAsync(p, s);
+  // a NULL stream tells the callback that no queued work uses the block
+  hipError_t e = s ? hipSuccess : hipStreamSynchronize(s);
+  a.release(p, (void*)s, a.ctx);
+  return e;
 }
 
 static qk_status inval(const std::string& msg) {
@@ -54,6 +91,16 @@ using namespace qk;
 QK_API int qk_abi_version(void) { return QK_ABI_VERSION; }
 
 QK_API const char* qk_last_error(void) { return g_err.c_str(); }
+
+QK_API qk_status qk_set_allocator(qk_alloc_fn alloc, qk_release_fn release, void* ctx) {
+  g_err.clear();
+  if ((alloc == nullptr) != (release == nullptr)) return inval("alloc and release must both be set or both be NULL");
+  std::lock_guard<std::mutex> lk(g_alloc_mu);
+  g_alloc.alloc = alloc;
+  g_alloc.release = release;
+  g_alloc.ctx = alloc ? ctx : nullptr;
+  return QK_OK;
+}
 
 QK_API qk_status qk_fields_quasiperiodic(int32_t L, double h, double beta, const double* phi, int32_t batch,
                                          double* h_out) {
@@ -95,9 +142,10 @@ QK_API qk_status qk_basis_build(int32_t L, int32_t n_up, void* stream, qk_basis*
   b->wide = L > 32;
   const int K = binom_stride(b);
   const size_t sbytes = b->wide ? sizeof(uint64_t) : sizeof(uint32_t);
+  b->al = current_allocator();
   hipError_t e = hipGetDevice(&b->device);
-  if (e == hipSuccess) e = hipMalloc((void**)&b->d_binom, sizeof(uint32_t) * K * K);
-  if (e == hipSuccess) e = hipMalloc((void**)&b->d_states, sbytes * (size_t)b->D);
+  if (e == hipSuccess) e = dev_alloc(b->al, (void**)&b->d_binom, sizeof(uint32_t) * K * K);
+  if (e == hipSuccess) e = dev_alloc(b->al, (void**)&b->d_states, sbytes * (size_t)b->D);
   if (e != hipSuccess) {
     qk_status st = hip_fail(e, "qk_basis_build allocation");
     qk_basis_destroy(b);
@@ -147,15 +195,15 @@ QK_API qk_status qk_basis_rank(const qk_basis* b, const uint64_t* states_host, i
   if (st != QK_OK) return st;
   uint64_t* d_in = nullptr;
   int64_t* d_out = nullptr;
-  hipError_t e = hipMalloc((void**)&d_in, sizeof(uint64_t) * (size_t)n);
-  if (e == hipSuccess) e = hipMalloc((void**)&d_out, sizeof(int64_t) * (size_t)n);
+  hipError_t e = dev_alloc(b->al, (void**)&d_in, sizeof(uint64_t) * (size_t)n);
+  if (e == hipSuccess) e = dev_alloc(b->al, (void**)&d_out, sizeof(int64_t) * (size_t)n);
   if (e == hipSuccess) e = hipMemcpy(d_in, states_host, sizeof(uint64_t) * (size_t)n, hipMemcpyHostToDevice);
   if (e == hipSuccess) {
     st = launch_rank(b, d_in, n, d_out, nullptr);
     if (st == QK_OK) e = hipMemcpy(idx_host, d_out, sizeof(int64_t) * (size_t)n, hipMemcpyDeviceToHost);
   }
-  hipFree(d_in);
-  hipFree(d_out);
+  dev_free(b->al, d_in);
+  dev_free(b->al, d_out);
   if (e != hipSuccess) return hip_fail(e, "qk_basis_rank");
   return st;
 }
@@ -163,8 +211,8 @@ QK_API qk_status qk_basis_rank(const qk_basis* b, const uint64_t* states_host, i
 QK_API void qk_basis_destroy(qk_basis* b) {
   if (!b) return;
   hipDeviceSynchronize();
-  if (b->d_states) hipFree(b->d_states);
-  if (b->d_binom) hipFree(b->d_binom);
+  dev_free(b->al, b->d_states);
+  dev_free(b->al, b->d_binom);
   delete b;
 }
 
@@ -201,7 +249,8 @@ QK_API qk_status qk_ham_create(const qk_basis* b, const qk_ham_params* p, const 
   H->h_host.assign(h_host, h_host + (size_t)b->L * batch);
   hipStream_t s = (hipStream_t)stream;
   const size_t fbytes = sizeof(double) * (size_t)b->L * batch;
-  hipError_t e = hipMalloc((void**)&H->d_fields, fbytes);
+  H->al = current_allocator();
+  hipError_t e = dev_alloc(H->al, (void**)&H->d_fields, fbytes);
   if (e == hipSuccess) e = hipMemcpyAsync(H->d_fields, h_host, fbytes, hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);   // h_host may be freed by the caller after return
   if (e != hipSuccess) {
@@ -210,8 +259,8 @@ QK_API qk_status qk_ham_create(const qk_basis* b, const qk_ham_params* p, const 
     return st;
   }
   if (p->mode == QK_CSR) {
-    e = hipMalloc((void**)&H->d_rowptr, sizeof(uint32_t) * ((size_t)b->D + 1));
-    if (e == hipSuccess) e = hipMalloc((void**)&H->d_diag, sizeof(double) * (size_t)b->D * batch);
+    e = dev_alloc(H->al, (void**)&H->d_rowptr, sizeof(uint32_t) * ((size_t)b->D + 1));
+    if (e == hipSuccess) e = dev_alloc(H->al, (void**)&H->d_diag, sizeof(double) * (size_t)b->D * batch);
     if (e != hipSuccess) {
       st = hip_fail(e, "qk_ham_create CSR allocation");
       qk_ham_destroy(H);
@@ -280,19 +329,24 @@ QK_API qk_status qk_ham_apply(const qk_ham* H, const void* x, void* y, int32_t d
 QK_API void qk_ham_destroy(qk_ham* H) {
   if (!H) return;
   hipDeviceSynchronize();
-  if (H->d_fields) hipFree(H->d_fields);
-  if (H->d_rowptr) hipFree(H->d_rowptr);
-  if (H->d_cols) hipFree(H->d_cols);
-  if (H->d_diag) hipFree(H->d_diag);
-  if (H->d_lo_state) hipFree(H->d_lo_state);
-  if (H->d_lo_rank) hipFree(H->d_lo_rank);
-  if (H->d_blk) hipFree(H->d_blk);
+  dev_free(H->al, H->d_fields);
+  dev_free(H->al, H->d_rowptr);
+  dev_free(H->al, H->d_cols);
+  dev_free(H->al, H->d_diag);
+  dev_free(H->al, H->d_lo_state);
+  dev_free(H->al, H->d_lo_rank);
+  dev_free(H->al, H->d_blk);
   delete H;
 }
 
 // ------------------------------------------------------------------ Krylov
 QK_API qk_status qk_krylov_create(const qk_ham* H, int32_t m, int32_t dtype, int32_t reorth, qk_krylov** out) {
   g_err.clear();
+  return krylov_create(H, m, dtype, reorth, current_allocator(), out);
+}
+
+qk_status qk::krylov_create(const qk_ham* H, int32_t m, int32_t dtype, int32_t reorth, const qk_allocator& al,
+                              qk_krylov** out) {
   if (!out) return inval("NULL out");
   *out = nullptr;
   if (!H) return inval("NULL Hamiltonian");
@@ -312,17 +366,19 @@ QK_API qk_status qk_krylov_create(const qk_ham* H, int32_t m, int32_t dtype, int
   k->device = H->device;
   k->grid = krylov_grid((uint64_t)k->D, k->batch);
   const size_t vec = elem_bytes(dtype) * (size_t)k->D * k->batch;
-  hipError_t e = hipMalloc(&k->d_U, vec * (size_t)m);
-  if (e == hipSuccess) e = hipMalloc((void**)&k->d_partA, sizeof(double) * (size_t)kMaxPartialBlocks * kQA * k->batch);
-  if (e == hipSuccess) e = hipMalloc((void**)&k->d_partB, sizeof(double) * (size_t)kMaxPartialBlocks * k->batch);
-  if (e == hipSuccess) e = hipMalloc((void**)&k->d_coef, sizeof(double) * kstate_doubles(m, k->batch));
-  if (e == hipSuccess) e = hipMalloc((void**)&k->d_int, sizeof(int32_t) * 2 * k->batch);
+  k->al = al;
+  hipError_t e = dev_alloc(k->al, &k->d_U, vec * (size_t)m);
+  if (e == hipSuccess)
+    e = dev_alloc(k->al, (void**)&k->d_partA, sizeof(double) * (size_t)kMaxPartialBlocks * kQA * k->batch);
+  if (e == hipSuccess) e = dev_alloc(k->al, (void**)&k->d_partB, sizeof(double) * (size_t)kMaxPartialBlocks * k->batch);
+  if (e == hipSuccess) e = dev_alloc(k->al, (void**)&k->d_coef, sizeof(double) * kstate_doubles(m, k->batch));
+  if (e == hipSuccess) e = dev_alloc(k->al, (void**)&k->d_int, sizeof(int32_t) * 2 * k->batch);
   if (e == hipSuccess) e = hipMemset(k->d_coef, 0, sizeof(double) * kstate_doubles(m, k->batch));
   if (e == hipSuccess) e = hipMemset(k->d_int, 0, sizeof(int32_t) * 2 * k->batch);
   if (e == hipSuccess && reorth == 2) {
     const size_t chunks = (size_t)(m + kReorthChunk - 1) / kReorthChunk;
-    e = hipMalloc((void**)&k->d_rpart, sizeof(double) * chunks * kReorthGrid * 2 * kReorthChunk * k->batch);
-    if (e == hipSuccess) e = hipMalloc((void**)&k->d_rcoef, sizeof(double) * (size_t)m * 2 * k->batch);
+    e = dev_alloc(k->al, (void**)&k->d_rpart, sizeof(double) * chunks * kReorthGrid * 2 * kReorthChunk * k->batch);
+    if (e == hipSuccess) e = dev_alloc(k->al, (void**)&k->d_rcoef, sizeof(double) * (size_t)m * 2 * k->batch);
   }
   if (e != hipSuccess) {
     st = hip_fail(e, "qk_krylov_create allocation");
@@ -493,13 +549,13 @@ QK_API void qk_krylov_destroy(qk_krylov* k) {
     if (p.end) hipEventDestroy(p.end);
   }
   for (auto e : k->spare) hipEventDestroy(e);
-  if (k->d_U) hipFree(k->d_U);
-  if (k->d_partA) hipFree(k->d_partA);
-  if (k->d_partB) hipFree(k->d_partB);
-  if (k->d_rpart) hipFree(k->d_rpart);
-  if (k->d_rcoef) hipFree(k->d_rcoef);
-  if (k->d_coef) hipFree(k->d_coef);
-  if (k->d_int) hipFree(k->d_int);
+  dev_free(k->al, k->d_U);
+  dev_free(k->al, k->d_partA);
+  dev_free(k->al, k->d_partB);
+  dev_free(k->al, k->d_rpart);
+  dev_free(k->al, k->d_rcoef);
+  dev_free(k->al, k->d_coef);
+  dev_free(k->al, k->d_int);
   delete k;
 }
 

@@ -210,7 +210,7 @@ qk_status krylov_autotune(qk_krylov* k, double dt, const char* cache_path, hipSt
   const uint64_t n = (uint64_t)k->D * k->batch;
   const size_t bytes = n * (k->dtype == QK_C128 ? 16 : 8);
   void* v = nullptr;
-  QK_HIP(hipMalloc(&v, bytes));
+  QK_HIP(dev_alloc(k->al, &v, bytes));
   hipEvent_t e0 = nullptr, e1 = nullptr;
   hipError_t he = hipEventCreate(&e0);
   if (he == hipSuccess) he = hipEventCreate(&e1);
@@ -250,7 +250,7 @@ qk_status krylov_autotune(qk_krylov* k, double dt, const char* cache_path, hipSt
   k->profiling = prof;
   if (e0) hipEventDestroy(e0);
   if (e1) hipEventDestroy(e1);
-  hipFree(v);
+  dev_free(k->al, v);
   if (st != QK_OK) return st;
   st = apply_shape(k, &best);
   if (st != QK_OK) return st;
@@ -273,6 +273,7 @@ qk_status krylov_autotune(qk_krylov* k, double dt, const char* cache_path, hipSt
 
 // ------------------------------------------------------------ batched driver
 struct qk_batch {
+  qk_allocator al;
   std::vector<qk_krylov*> ks;
   std::vector<void*> psi;
   std::vector<int64_t> r0;
@@ -330,8 +331,9 @@ qk_status batch_create(qk_krylov* const* ks, void* const* psi, const int64_t* r0
     off += ks[i]->batch;
   }
   b->items = off;
-  hipError_t e = hipMalloc((void**)&b->d_counter, sizeof(int));
-  if (e == hipSuccess) e = hipMalloc((void**)&b->d_state, sizeof(double) * (2 * (size_t)off + 1));
+  b->al = current_allocator();
+  hipError_t e = dev_alloc(b->al, (void**)&b->d_counter, sizeof(int));
+  if (e == hipSuccess) e = dev_alloc(b->al, (void**)&b->d_state, sizeof(double) * (2 * (size_t)off + 1));
   for (int i = 0; i < n; ++i) {
     void* p0 = nullptr;
     double* pa = nullptr;
@@ -339,8 +341,8 @@ qk_status batch_create(qk_krylov* const* ks, void* const* psi, const int64_t* r0
     if (e == hipSuccess && r0[i] < 0) {
       const size_t vec = (ks[i]->dtype == QK_C128 ? 16 : 8) * (size_t)ks[i]->D * ks[i]->batch;
       G = overlap_grid((uint32_t)ks[i]->D, ks[i]->batch);
-      e = hipMalloc(&p0, vec);
-      if (e == hipSuccess) e = hipMalloc((void**)&pa, sizeof(double) * (size_t)G * 2 * ks[i]->batch);
+      e = dev_alloc(b->al, &p0, vec);
+      if (e == hipSuccess) e = dev_alloc(b->al, (void**)&pa, sizeof(double) * (size_t)G * 2 * ks[i]->batch);
       if (e == hipSuccess) e = hipMemcpy(p0, psi[i], vec, hipMemcpyDeviceToDevice);
     }
     b->psi0.push_back(p0);
@@ -389,12 +391,10 @@ void batch_destroy(qk_batch* b) {
   for (auto e : b->joins) hipEventDestroy(e);
   if (b->fork) hipEventDestroy(b->fork);
   if (b->cap) hipStreamDestroy(b->cap);
-  if (b->d_counter) hipFree(b->d_counter);
-  if (b->d_state) hipFree(b->d_state);
-  for (auto p : b->psi0)
-    if (p) hipFree(p);
-  for (auto p : b->part)
-    if (p) hipFree(p);
+  dev_free(b->al, b->d_counter);
+  dev_free(b->al, b->d_state);
+  for (auto p : b->psi0) dev_free(b->al, p);
+  for (auto p : b->part) dev_free(b->al, p);
   delete b;
 }
 

@@ -624,8 +624,8 @@ qk_status launch_blocked_build(qk_ham* H, hipStream_t s) {
   const qk_basis* b = H->basis;
   const int llo = H->llo, lhi = b->L - llo;
   const uint32_t nlo = 1u << llo, nhi = 1u << lhi;
-  QK_HIP(hipMalloc((void**)&H->d_lo_state, sizeof(uint16_t) * nlo));
-  QK_HIP(hipMalloc((void**)&H->d_lo_rank, sizeof(uint16_t) * nlo));
+  QK_HIP(dev_alloc(H->al, (void**)&H->d_lo_state, sizeof(uint16_t) * nlo));
+  QK_HIP(dev_alloc(H->al, (void**)&H->d_lo_rank, sizeof(uint16_t) * nlo));
   BlkArgs ba = blk_args(H);
   hipLaunchKernelGGL(k_lo_tables, dim3((nlo + 255) / 256), dim3(256), 0, s, llo, b->d_binom, ba, H->d_lo_state,
                      H->d_lo_rank);
@@ -633,14 +633,14 @@ qk_status launch_blocked_build(qk_ham* H, hipStream_t s) {
   uint32_t *flag = nullptr, *idx = nullptr;
   void* tmp = nullptr;
   size_t tmp_bytes = 0;
-  QK_HIP(hipMalloc((void**)&flag, sizeof(uint32_t) * nhi));
-  hipError_t e = hipMalloc((void**)&idx, sizeof(uint32_t) * nhi);
+  QK_HIP(dev_alloc(H->al, (void**)&flag, sizeof(uint32_t) * nhi));
+  hipError_t e = dev_alloc(H->al, (void**)&idx, sizeof(uint32_t) * nhi);
   if (e == hipSuccess) {
     hipLaunchKernelGGL(k_block_flags, dim3((nhi + 255) / 256), dim3(256), 0, s, lhi, llo, b->N, flag);
     e = hipGetLastError();
   }
   if (e == hipSuccess) e = hipcub::DeviceScan::ExclusiveSum(nullptr, tmp_bytes, flag, idx, (int)nhi, s);
-  if (e == hipSuccess) e = hipMalloc(&tmp, tmp_bytes + 16);
+  if (e == hipSuccess) e = dev_alloc(H->al, &tmp, tmp_bytes + 16);
   if (e == hipSuccess) e = hipcub::DeviceScan::ExclusiveSum(tmp, tmp_bytes, flag, idx, (int)nhi, s);
   uint32_t last_idx = 0, last_flag = 0;
   if (e == hipSuccess) e = hipMemcpyAsync(&last_idx, idx + nhi - 1, 4, hipMemcpyDeviceToHost, s);
@@ -648,7 +648,7 @@ qk_status launch_blocked_build(qk_ham* H, hipStream_t s) {
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e == hipSuccess) {
     H->nblk = (int)(last_idx + last_flag);
-    e = hipMalloc((void**)&H->d_blk, sizeof(BlkEntry) * (size_t)(H->nblk > 0 ? H->nblk : 1));
+    e = dev_alloc(H->al, (void**)&H->d_blk, sizeof(BlkEntry) * (size_t)(H->nblk > 0 ? H->nblk : 1));
   }
   if (e == hipSuccess) {
     hipLaunchKernelGGL(k_block_fill, dim3((nhi + 255) / 256), dim3(256), 0, s, lhi, llo, b->N, flag, idx,
@@ -661,9 +661,10 @@ qk_status launch_blocked_build(qk_ham* H, hipStream_t s) {
     e = hipGetLastError();
   }
   if (e == hipSuccess) e = hipStreamSynchronize(s);
-  hipFree(tmp);
-  hipFree(flag);
-  hipFree(idx);
+  else hipStreamSynchronize(s);   // nothing queued may still use the temporaries
+  dev_free(H->al, tmp);
+  dev_free(H->al, flag);
+  dev_free(H->al, idx);
   QK_HIP(e);
   return QK_OK;
 }

@@ -218,20 +218,20 @@ qk_status grad_return_prob(qk_krylov* k, int64_t r0, double T, int n_steps, int 
   double2* lam = nullptr;    // lambda_k
   double2* lamp = nullptr;   // lambda_{k+1}
   double *Ct = nullptr, *part = nullptr, *dA = nullptr;
-  qk_status st = qk_krylov_create(H, k->m, QK_C128, k->reorth, &kb);
+  qk_status st = krylov_create(H, k->m, QK_C128, k->reorth, k->al, &kb);
   if (st != QK_OK) return st;
   kb->threads = k->threads;
   kb->blocks_per_cu = k->blocks_per_cu;
   kb->blocked_wgs = k->blocked_wgs;
   kb->grid = k->grid;
-  hipError_t e = hipMalloc((void**)&ck, vbytes * (size_t)nck);
-  if (e == hipSuccess && c > 1) e = hipMalloc((void**)&seg, vbytes * (size_t)(c - 1));
-  if (e == hipSuccess) e = hipMalloc((void**)&cur, vbytes);
-  if (e == hipSuccess) e = hipMalloc((void**)&lam, vbytes);
-  if (e == hipSuccess) e = hipMalloc((void**)&lamp, vbytes);
-  if (e == hipSuccess) e = hipMalloc((void**)&Ct, sizeof(double) * 2 * kGradMaxM * kGradMaxM);
-  if (e == hipSuccess) e = hipMalloc((void**)&part, sizeof(double) * (size_t)G * kGradQ);
-  if (e == hipSuccess) e = hipMalloc((void**)&dA, sizeof(double) * 2 * L);
+  hipError_t e = dev_alloc(k->al, (void**)&ck, vbytes * (size_t)nck);
+  if (e == hipSuccess && c > 1) e = dev_alloc(k->al, (void**)&seg, vbytes * (size_t)(c - 1));
+  if (e == hipSuccess) e = dev_alloc(k->al, (void**)&cur, vbytes);
+  if (e == hipSuccess) e = dev_alloc(k->al, (void**)&lam, vbytes);
+  if (e == hipSuccess) e = dev_alloc(k->al, (void**)&lamp, vbytes);
+  if (e == hipSuccess) e = dev_alloc(k->al, (void**)&Ct, sizeof(double) * 2 * kGradMaxM * kGradMaxM);
+  if (e == hipSuccess) e = dev_alloc(k->al, (void**)&part, sizeof(double) * (size_t)G * kGradQ);
+  if (e == hipSuccess) e = dev_alloc(k->al, (void**)&dA, sizeof(double) * 2 * L);
   if (e == hipSuccess) e = hipMemsetAsync(dA, 0, sizeof(double) * 2 * L, s);
   const KState fw = make_kstate(k), bw = make_kstate(kb);
   const GaussRule gr = gauss_legendre();
@@ -317,14 +317,14 @@ qk_status grad_return_prob(qk_krylov* k, int64_t r0, double T, int n_steps, int 
     for (int i = 0; i < L; ++i) dFdh[i] = 2.0 * (A.x * dAh[2 * i] + A.y * dAh[2 * i + 1]);
   }
   hipStreamSynchronize(s);
-  hipFree(ck);
-  hipFree(seg);
-  hipFree(cur);
-  hipFree(lam);
-  hipFree(lamp);
-  hipFree(Ct);
-  hipFree(part);
-  hipFree(dA);
+  dev_free(k->al, ck);
+  dev_free(k->al, seg);
+  dev_free(k->al, cur);
+  dev_free(k->al, lam);
+  dev_free(k->al, lamp);
+  dev_free(k->al, Ct);
+  dev_free(k->al, part);
+  dev_free(k->al, dA);
   qk_krylov_destroy(kb);
   return st;
 }

@@ -55,7 +55,28 @@ inline int block_threads(int B, int cap = kMaxBlock) {
 
 }  // namespace qk
 
+// Allocator of a handle's device memory (qk_set_allocator); all NULL means
+// hipMalloc / hipFree.
+struct qk_allocator {
+  qk_alloc_fn alloc = nullptr;
+  qk_release_fn release = nullptr;
+  void* ctx = nullptr;
+};
+
+namespace qk {
+qk_allocator current_allocator();
+// memory used on any stream; released only once the device work using it has
+// been waited for
+hipError_t dev_alloc(const qk_allocator& a, void** p, size_t bytes);
+void dev_free(const qk_allocator& a, void* p);
+// stream-ordered temporary: used by work queued on s and released right after
+// the last of it is queued (hipMallocAsync / hipFreeAsync semantics)
+hipError_t dev_alloc_async(const qk_allocator& a, void** p, size_t bytes, hipStream_t s);
+hipError_t dev_free_async(const qk_allocator& a, void* p, hipStream_t s);
+}  // namespace qk
+
 struct qk_basis {
+  qk_allocator al;
   int32_t L = 0, N = 0;
   int64_t D = 0;
   int device = 0;
@@ -65,6 +86,7 @@ struct qk_basis {
 };
 
 struct qk_ham {
+  qk_allocator al;
   const qk_basis* basis = nullptr;
   qk_ham_params p{};
   int32_t batch = 1;
@@ -85,6 +107,7 @@ struct qk_ham {
 };
 
 struct qk_krylov {
+  qk_allocator al;
   const qk_ham* H = nullptr;
   int32_t m = 0, dtype = 0, reorth = 0, batch = 1;
   int64_t D = 0;
@@ -148,6 +171,9 @@ qk_status launch_blocked_build(qk_ham* H, hipStream_t s);
 qk_status launch_blocked_apply(const qk_ham* H, const void* x, void* y, int dtype, hipStream_t s);
 qk_status launch_blocked_fields(qk_ham* H, hipStream_t s);
 bool blocked_usable(const qk_ham* H, int dtype);
+// qk_krylov_create with the device memory of the workspace from `al`
+qk_status krylov_create(const qk_ham* H, int32_t m, int32_t dtype, int32_t reorth, const qk_allocator& al,
+                        qk_krylov** out);
 qk_status launch_krylov_step(qk_krylov* k, void* psi, double dt, hipStream_t s, bool combine = true);
 // One step of at most tau_max whose length the device chooses from the error
 // estimate: st.tau[b] receives the accepted step of column b, st.tau[B + b] a

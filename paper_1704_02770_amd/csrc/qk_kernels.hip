@@ -732,15 +732,15 @@ qk_status launch_csr_build(qk_ham* H, hipStream_t s) {
   size_t tmp_bytes = 0;
   QK_HIP(hipcub::DeviceScan::InclusiveSum(nullptr, tmp_bytes, H->d_rowptr + 1, H->d_rowptr + 1, (int)D, s));
   void* tmp = nullptr;
-  QK_HIP(hipMallocAsync(&tmp, tmp_bytes + 16, s));
+  QK_HIP(dev_alloc_async(H->al, &tmp, tmp_bytes + 16, s));
   hipError_t e = hipcub::DeviceScan::InclusiveSum(tmp, tmp_bytes, H->d_rowptr + 1, H->d_rowptr + 1, (int)D, s);
-  QK_HIP(hipFreeAsync(tmp, s));
+  QK_HIP(dev_free_async(H->al, tmp, s));
   QK_HIP(e);
   uint32_t nnz = 0;
   QK_HIP(hipMemcpyAsync(&nnz, H->d_rowptr + D, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
   QK_HIP(hipStreamSynchronize(s));
   H->nnz = nnz;
-  QK_HIP(hipMalloc(&H->d_cols, sizeof(uint32_t) * (size_t)(nnz > 0 ? nnz : 1)));
+  QK_HIP(dev_alloc(H->al, (void**)&H->d_cols, sizeof(uint32_t) * (size_t)(nnz > 0 ? nnz : 1)));
   if (H->basis->wide)
     hipLaunchKernelGGL(k_csr_fill<uint64_t>, dim3((D + 255) / 256), dim3(256), 0, s,
                        (const uint64_t*)H->basis->d_states, D, a, H->basis->d_binom, H->d_rowptr, H->d_cols);
@@ -952,7 +952,7 @@ qk_status launch_return_prob(const qk_basis* b, int64_t r0, const void* psi0, co
   const int threads = block_threads(B);
   const int G = stream_grid(D, B, threads, 0);
   double* part = nullptr;
-  QK_HIP(hipMallocAsync((void**)&part, sizeof(double) * (size_t)G * 2 * B, s));
+  QK_HIP(dev_alloc_async(b->al, (void**)&part, sizeof(double) * (size_t)G * 2 * B, s));
   if (dtype == QK_C128)
     hipLaunchKernelGGL(k_overlap_partial<double>, dim3(G), dim3(threads), 0, s, (const double2*)psi0,
                        (const double2*)psi, D, B, part);
@@ -964,7 +964,7 @@ qk_status launch_return_prob(const qk_basis* b, int64_t r0, const void* psi0, co
     hipLaunchKernelGGL(k_overlap_final, dim3(1), dim3(kMaxBlock), 0, s, part, G, B, P, (const int*)nullptr, 0, 0);
     e = hipGetLastError();
   }
-  QK_HIP(hipFreeAsync(part, s));
+  QK_HIP(dev_free_async(b->al, part, s));
   QK_HIP(e);
   return QK_OK;
 }

@@ -84,3 +84,25 @@ def test_fields_host_function():
         qk.qk_fields_quasiperiodic(0, 1.0, 0.5, [0.0])
     with pytest.raises(qk.QkError):
         qk.qk_fields_quasiperiodic(8, float("nan"), 0.5, [0.0])
+
+
+def test_set_allocator_validation():
+    import paper_1704_02770_amd as qk
+    from paper_1704_02770_amd import _native
+    from paper_1704_02770_amd._native import lib
+    calls = []
+    fa = _native.ALLOC_FN(lambda n, s, c: calls.append(n))
+    fr = _native.RELEASE_FN(lambda p, s, c: calls.append(p))
+    none_a, none_r = C.cast(None, _native.ALLOC_FN), C.cast(None, _native.RELEASE_FN)
+    assert lib.qk_set_allocator(fa, none_r, None) == qk.QK_EINVAL
+    assert b"both" in lib.qk_last_error()
+    assert lib.qk_set_allocator(none_a, fr, None) == qk.QK_EINVAL
+    assert lib.qk_set_allocator(fa, fr, None) == qk.QK_OK
+    # a rejected create allocates nothing
+    out = C.c_void_p()
+    assert lib.qk_basis_build(65, 2, None, C.byref(out)) == qk.QK_EINVAL
+    assert lib.qk_set_allocator(none_a, none_r, None) == qk.QK_OK
+    assert calls == []
+    with pytest.raises(ValueError):
+        qk.qk_set_allocator(alloc=lambda n, s: 0)
+    qk.qk_set_allocator()
