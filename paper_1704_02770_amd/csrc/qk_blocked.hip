@@ -290,26 +290,29 @@ k_blk(BlkArgs ba, const typename Cx<T>::V* __restrict__ x, typename Cx<T>::V* __
       const uint32_t b = lo_state[base + j];
       const uint32_t r = off + j;
       // global gathers first, so that their latencies overlap: the previous
-      // Lanczos vector, the bond joining the halves and the ring bond
-      // (inactive ones read x[r] and are discarded)
-      V um = {0, 0};
+      // Lanczos vector, the bond joining the halves and the ring bond.  Lanes
+      // whose bond is inactive issue no load (their value stays zero), so they
+      // add no cache lines to the wave's request.
+      const V z = {0, 0};
+      V um = z;
       if (prev) um = ld32_stream(ujm1, r);
       const uint32_t bl = (b >> (LLO - 1)) & 1u;
       const bool cx = (bl ^ (a & 1u)) != 0u;
       const uint32_t pcl = (uint32_t)__popc(b & ((1u << (LLO - 1)) - 1u));
       const uint32_t cc = sbin[(LLO - 1) * kBinomStride + pcl];
-      const V vc = ld32(x, cx ? (bl ? r + cc : r - cc) : r);
+      V vc = z;
+      if (cx) vc = ld32(x, bl ? r + cc : r - cc);
       const bool wx = ba.pbc && ((b & 1u) != top);
-      const V vw = ld32(x, wx ? offw + lo_rank[b ^ 1u] : r);
+      V vw = z;
+      if (wx) vw = ld32(x, offw + lo_rank[b ^ 1u]);
       // high bonds: uniform row shifts, contiguous runs of the partner blocks,
-      // four unconditional loads at a time (zero shifts pad the last group and
-      // are weighted out with uniform 0/1 factors, so no branch separates the
-      // loads).  The first group is issued before the in-block LDS work and
-      // consumed after it.
-      const V q0 = ld32(x, r + (uint32_t)hd[0]);
-      const V q1 = ld32(x, r + (uint32_t)hd[1]);
-      const V q2 = ld32(x, r + (uint32_t)hd[2]);
-      const V q3 = ld32(x, r + (uint32_t)hd[3]);
+      // four loads at a time; slots beyond the block's active bonds are skipped
+      // by a uniform test and contribute zero.  The first group is issued
+      // before the in-block LDS work and consumed after it.
+      const V q0 = (0 < nact) ? ld32(x, r + (uint32_t)hd[0]) : z;
+      const V q1 = (1 < nact) ? ld32(x, r + (uint32_t)hd[1]) : z;
+      const V q2 = (2 < nact) ? ld32(x, r + (uint32_t)hd[2]) : z;
+      const V q3 = (3 < nact) ? ld32(x, r + (uint32_t)hd[3]) : z;
       // in-block work from LDS
       const V xr = xs[j];
       const int anti = __popc((b ^ (b >> 1)) & ((1u << (LLO - 1)) - 1u)) + (cx ? 1 : 0) + (wx ? 1 : 0);
@@ -335,9 +338,9 @@ k_blk(BlkArgs ba, const typename Cx<T>::V* __restrict__ x, typename Cx<T>::V* __
       }
       for (int g0 = 4; g0 < nact; g0 += 4) {
         const V v0 = ld32(x, r + (uint32_t)hd[g0]);
-        const V v1 = ld32(x, r + (uint32_t)hd[g0 + 1]);
-        const V v2 = ld32(x, r + (uint32_t)hd[g0 + 2]);
-        const V v3 = ld32(x, r + (uint32_t)hd[g0 + 3]);
+        const V v1 = (g0 + 1 < nact) ? ld32(x, r + (uint32_t)hd[g0 + 1]) : z;
+        const V v2 = (g0 + 2 < nact) ? ld32(x, r + (uint32_t)hd[g0 + 2]) : z;
+        const V v3 = (g0 + 3 < nact) ? ld32(x, r + (uint32_t)hd[g0 + 3]) : z;
         const T w1 = (g0 + 1 < nact) ? (T)1 : (T)0;
         const T w2 = (g0 + 2 < nact) ? (T)1 : (T)0;
         const T w3 = (g0 + 3 < nact) ? (T)1 : (T)0;
