@@ -31,7 +31,8 @@
  *     failing call on the calling thread.  Nothing aborts or throws across
  *     this boundary.
  *   - Handles (qk_basis, qk_ham, qk_krylov, qk_batch) are created on the current HIP
- *     device, own their device memory, and are released only by the matching
+ *     device, own their device memory (from the allocator registered with
+ *     qk_set_allocator, hipMalloc by default), and are released only by the matching
  *     *_destroy (which accepts NULL and synchronises the device first).  A
  *     handle may be used by one stream at a time; calls on a handle from
  *     another device return QK_EINVAL.
@@ -371,7 +372,9 @@ qk_status qk_grad_return_prob(qk_krylov* k, int64_t r0, double T, int32_t n_step
  * batch item: P_device[k] (device double array of B entries).  With
  * psi0 == NULL the initial state is the basis state of row r0 and
  * F = |psi[r0]|^2; otherwise psi0 is a [D][B] array of `dtype` and the
- * overlap is reduced in double precision.  Asynchronous.
+ * overlap is reduced in double precision through a small stream-ordered
+ * temporary.  Asynchronous, except that with a caller allocator and stream
+ * NULL the call waits for its own work before handing the temporary back.
  */
 qk_status qk_return_prob(const qk_basis* b, int64_t r0, const void* psi0, const void* psi,
                          int32_t dtype, int32_t batch, double* P_device, void* stream);
