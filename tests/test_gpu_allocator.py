@@ -5,6 +5,8 @@ accounting sees the workspaces and gets them back on destroy; an allocator
 that runs dry is reported as QK_ENOMEM and every block it did hand out comes
 back (no leak on any failure point).
 """
+import gc
+
 import numpy as np
 import pytest
 import torch
@@ -133,3 +135,70 @@ def test_exhausted_allocator_reports_enomem_without_leak():
     assert abs(float(torch.linalg.vector_norm(psi)) - 1.0) < 1e-12
     _close(k, H, b)
     assert not live
+
+
+def _batch_run(dt=0.1, steps=5):
+    """Two workspaces (L = 20 complex64 with two phases, L = 18 complex128) in one
+    graph-driven batch; returns P and the handles to close."""
+    hs = []
+    b1 = qk.qk_basis_build(20, 10)
+    H1 = qk.qk_ham_create(b1, 1.0, 1.0, True, qk.qk_fields_quasiperiodic(20, 2.0, BETA_GOLDEN, phases(2, 3)))
+    k1 = qk.qk_krylov_create(H1, 30, torch.complex64)
+    b2 = qk.qk_basis_build(18, 9)
+    H2 = qk.qk_ham_create(b2, 1.0, 1.0, False, qk.qk_fields_quasiperiodic(18, 2.0, BETA_GOLDEN, phases(1, 4)))
+    k2 = qk.qk_krylov_create(H2, 30, torch.complex128)
+    hs += [k1, H1, b1, k2, H2, b2]
+    r1, r2 = neel_row(20), neel_row(18)
+    p1 = torch.zeros(qk.qk_basis_dim(b1) * 2, dtype=torch.complex64, device="cuda")
+    p1[2 * r1] = 1.0
+    p1[2 * r1 + 1] = 1.0
+    p2 = torch.zeros(qk.qk_basis_dim(b2), dtype=torch.complex128, device="cuda")
+    p2[r2] = 1.0
+    bt = qk.qk_batch_create([k1, k2], [p1, p2], [r1, r2])
+    hs.insert(0, bt)
+    P = qk.qk_batch_run(bt, dt, steps, use_graph=True).cpu()
+    torch.cuda.synchronize()
+    return P, hs
+
+
+def test_batch_autotune_and_side_stream_through_torch_allocator(tmp_path):
+    say("allocator batch default")
+    P_ref, hs = _batch_run()
+    _close(*hs)
+    del hs
+    gc.collect()
+    torch.cuda.synchronize()
+    m0 = torch.cuda.memory_allocated()
+    qk.use_torch_allocator()
+    say("allocator batch torch")
+    P, hs = _batch_run()
+    assert torch.equal(P, P_ref)
+    assert torch.cuda.memory_allocated() > m0
+    _close(*hs)
+    del hs                      # the batch wrapper keeps its state vectors alive
+    gc.collect()
+    torch.cuda.synchronize()
+    assert torch.cuda.memory_allocated() == m0
+
+    # autotuner scratch and a stream-ordered temporary on a side stream
+    say("allocator autotune torch")
+    b, H, k = _handles()
+    D = qk.qk_basis_dim(b)
+    psi = _evolve(k, D, neel_row(L), 2)
+    psi0 = torch.roll(psi, 3).contiguous()
+    P_cur = qk.qk_return_prob(b, psi, psi0=psi0).cpu()
+    torch.cuda.synchronize()
+    m1 = torch.cuda.memory_allocated()
+    shape = qk.qk_krylov_autotune(k, 0.1, cache_path=str(tmp_path / "shapes.json"))
+    assert shape["blocked_wgs_per_cu"] >= 0
+    torch.cuda.synchronize()
+    assert torch.cuda.memory_allocated() == m1
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        out = torch.empty(1, dtype=torch.float64, device="cuda")
+        qk.qk_return_prob(b, psi, psi0=psi0, out=out, stream=side)
+    side.synchronize()
+    assert torch.equal(out.cpu(), P_cur)
+    del out
+    _close(k, H, b)
