@@ -60,6 +60,8 @@ def parse():
     ap.add_argument("--hv-reps", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU time of the oracle sample")
+    ap.add_argument("--cpu-table", action="store_true",
+                    help="time the CPU oracle at several sizes on this host (no GPU) and print one JSON line")
     return ap.parse_args()
 
 
@@ -218,8 +220,80 @@ def cpu_baseline(L, m, fields, pbc, target_s):
                 t_hv_s=t_hv, t_vec_s=dict(dot=t_dot, axpy=t_axpy, norm=t_norm))
 
 
+def cpu_table(h):
+    """The oracle timed on this host at the sizes of the workloads: dense
+    eigendecomposition (L = 12, 14 on one thread and on all cores; L = 16 on
+    all cores), the CSR H*x of the oracle's H (L = 20, 24 in full; L = 28 on
+    a row sample), expm_multiply propagation of the L = 16 workload to t = 10,
+    and the equivalent Krylov-step rate at L = 20/24/28 (m = 30)."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    from oracle import basis as OB
+    from oracle import exact as OX
+    from oracle import hamiltonian as OH
+    from oracle import midsize as OM
+    from oracle import model as OMo
+    from workloads import BETA_GOLDEN, phases
+
+    cores = os.cpu_count() or 1
+    phi = float(phases(1, 0)[0])
+    out = dict(cores_available=cores, dense_eigh_s={}, csr_hx_s={}, krylov_steps_per_s={})
+    for L, threads in ((12, 1), (12, cores), (14, 1), (14, cores), (16, cores)):
+        f = OMo.fields(L, h, BETA_GOLDEN, phi)
+        Hd = OH.build_dense(L, L // 2, True, 1.0, 1.0, f)
+        with threadpool_limits(limits=threads):
+            t0 = time.perf_counter()
+            OX.eig(Hd)
+            out["dense_eigh_s"][f"L{L}_threads{threads}"] = round(time.perf_counter() - t0, 3)
+        log("dense", L, threads, out["dense_eigh_s"][f"L{L}_threads{threads}"])
+    with threadpool_limits(limits=1):
+        for L in (20, 24):
+            f = OMo.fields(L, h, BETA_GOLDEN, phi)
+            t0 = time.perf_counter()
+            Hc = OH.build_csr(L, L // 2, True, 1.0, 1.0, f).astype(np.complex128)
+            t_build = time.perf_counter() - t0
+            x = np.random.default_rng(0).standard_normal(Hc.shape[0]).astype(np.complex128)
+            Hc @ x
+            t0 = time.perf_counter()
+            for _ in range(3):
+                Hc @ x
+            t_hv = (time.perf_counter() - t0) / 3
+            out["csr_hx_s"][f"L{L}"] = dict(build=round(t_build, 3), hx=round(t_hv, 4), D=int(Hc.shape[0]))
+            log("csr", L, t_build, t_hv)
+        f16 = OMo.fields(16, h, BETA_GOLDEN, phi)
+        H16 = OH.build_csr(16, 8, True, 1.0, 1.0, f16)
+        r0 = int(OB.lookup(OB.sector_states(16, 8), [OMo.neel_state(16)])[0])
+        t0 = time.perf_counter()
+        OM.survival_probability(H16, r0, np.linspace(0.0, 10.0, 101))
+        out["expm_multiply_L16_t10_s"] = round(time.perf_counter() - t0, 3)
+    # a Krylov step as the oracle runs it: m matvecs; at iteration j, j + 1
+    # (vdot + axpy) pairs of the Gram-Schmidt, a norm and a scaling; the
+    # combination about m more axpys (vector passes timed on one thread)
+    m = 30
+    with threadpool_limits(limits=1):
+        for L in (20, 24):
+            c = out["csr_hx_s"][f"L{L}"]
+            x = np.ones(c["D"], dtype=np.complex128)
+            y = x.copy()
+            t0 = time.perf_counter()
+            for _ in range(5):
+                np.vdot(x, y)
+                np.subtract(y, 0.5 * x, out=y)
+            t_pair = (time.perf_counter() - t0) / 5
+            t_step = m * c["hx"] + sum(j + 1 for j in range(m)) * t_pair + 2 * m * t_pair
+            out["krylov_steps_per_s"][f"L{L}"] = round(1.0 / t_step, 3)
+    b28 = cpu_baseline(28, 30, OMo.fields(28, h, BETA_GOLDEN, phi), True, 15.0)
+    out["csr_hx_s"]["L28_sampled"] = dict(hx=round(b28["t_hv_s"], 3), D=40116600)
+    out["krylov_steps_per_s"]["L28"] = round(b28["value"], 5)
+    return out
+
+
 def main():
     args = parse()
+    if args.cpu_table:
+        print(json.dumps(dict(kind="oracle", host_cpu_table=cpu_table(args.h))), flush=True)
+        return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus > 1 or world > 1:
         print("bench.py runs on one GPU only: the library has no multi-GPU path "
