@@ -57,7 +57,7 @@ def parse():
     ap.add_argument("--forms", default="fp64,fp32,batched,adaptive")
     ap.add_argument("--adaptive-t", type=float, default=100.0)
     ap.add_argument("--adaptive-tol", type=float, default=1e-7)
-    ap.add_argument("--hv-reps", type=int, default=20)
+    ap.add_argument("--hv-reps", type=int, default=100)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU time of the oracle sample")
     ap.add_argument("--cpu-table", action="store_true",
