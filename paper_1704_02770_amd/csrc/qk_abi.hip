@@ -41,7 +41,7 @@ hipError_t dev_alloc(const qk_allocator& a, void** p, size_t bytes) {
 void dev_free(const qk_allocator& a, void* p) {
   if (!p) return;
   if (a.release) a.release(p, nullptr, a.ctx);
-  else hipFree(p);
+  else (void)hipFree(p);
 }
 
 hipError_t dev_alloc_async(const qk_allocator& a, void** p, size_t bytes, hipStream_t s) {
@@ -210,7 +210,7 @@ QK_API qk_status qk_basis_rank(const qk_basis* b, const uint64_t* states_host, i
 
 QK_API void qk_basis_destroy(qk_basis* b) {
   if (!b) return;
-  hipDeviceSynchronize();
+  (void)hipDeviceSynchronize();
   dev_free(b->al, b->d_states);
   dev_free(b->al, b->d_binom);
   delete b;
@@ -328,7 +328,7 @@ QK_API qk_status qk_ham_apply(const qk_ham* H, const void* x, void* y, int32_t d
 
 QK_API void qk_ham_destroy(qk_ham* H) {
   if (!H) return;
-  hipDeviceSynchronize();
+  (void)hipDeviceSynchronize();
   dev_free(H->al, H->d_fields);
   dev_free(H->al, H->d_rowptr);
   dev_free(H->al, H->d_cols);
@@ -543,12 +543,12 @@ QK_API qk_status qk_krylov_profile_read(qk_krylov* k, qk_kernel_time* out) {
 
 QK_API void qk_krylov_destroy(qk_krylov* k) {
   if (!k) return;
-  hipDeviceSynchronize();
+  (void)hipDeviceSynchronize();
   for (auto& p : k->pending) {
-    if (p.start) hipEventDestroy(p.start);
-    if (p.end) hipEventDestroy(p.end);
+    if (p.start) (void)hipEventDestroy(p.start);
+    if (p.end) (void)hipEventDestroy(p.end);
   }
-  for (auto e : k->spare) hipEventDestroy(e);
+  for (auto e : k->spare) (void)hipEventDestroy(e);
   dev_free(k->al, k->d_U);
   dev_free(k->al, k->d_partA);
   dev_free(k->al, k->d_partB);

@@ -248,8 +248,8 @@ qk_status krylov_autotune(qk_krylov* k, double dt, const char* cache_path, hipSt
       trial(cur);
     }
   k->profiling = prof;
-  if (e0) hipEventDestroy(e0);
-  if (e1) hipEventDestroy(e1);
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
   dev_free(k->al, v);
   if (st != QK_OK) return st;
   st = apply_shape(k, &best);
@@ -312,8 +312,8 @@ static qk_status record_item(qk_batch* b, int i, double* P, hipStream_t s) {
 int batch_device(const qk_batch* b) { return b->device; }
 
 void batch_release(qk_batch* b) {
-  if (b->exec) hipGraphExecDestroy(b->exec);
-  if (b->graph) hipGraphDestroy(b->graph);
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
   b->exec = nullptr;
   b->graph = nullptr;
 }
@@ -385,12 +385,12 @@ qk_status batch_create(qk_krylov* const* ks, void* const* psi, const int64_t* r0
 
 void batch_destroy(qk_batch* b) {
   if (!b) return;
-  hipDeviceSynchronize();
+  (void)hipDeviceSynchronize();
   batch_release(b);
-  for (auto s : b->streams) hipStreamDestroy(s);
-  for (auto e : b->joins) hipEventDestroy(e);
-  if (b->fork) hipEventDestroy(b->fork);
-  if (b->cap) hipStreamDestroy(b->cap);
+  for (auto s : b->streams) (void)hipStreamDestroy(s);
+  for (auto e : b->joins) (void)hipEventDestroy(e);
+  if (b->fork) (void)hipEventDestroy(b->fork);
+  if (b->cap) (void)hipStreamDestroy(b->cap);
   dev_free(b->al, b->d_counter);
   dev_free(b->al, b->d_state);
   for (auto p : b->psi0) dev_free(b->al, p);
@@ -451,7 +451,7 @@ qk_status batch_run(qk_batch* b, double dt, int n_steps, int use_graph, double* 
     hipGraph_t g = nullptr;
     e = hipStreamEndCapture(b->cap, &g);
     if (st != QK_OK || e != hipSuccess) {
-      if (g) hipGraphDestroy(g);
+      if (g) (void)hipGraphDestroy(g);
       restore();
       return st != QK_OK ? st : hip_fail(e, "hipStreamEndCapture");
     }

@@ -316,7 +316,7 @@ qk_status grad_return_prob(qk_krylov* k, int64_t r0, double T, int n_steps, int 
     *F = A.x * A.x + A.y * A.y;
     for (int i = 0; i < L; ++i) dFdh[i] = 2.0 * (A.x * dAh[2 * i] + A.y * dAh[2 * i + 1]);
   }
-  hipStreamSynchronize(s);
+  (void)hipStreamSynchronize(s);
   dev_free(k->al, ck);
   dev_free(k->al, seg);
   dev_free(k->al, cur);
