@@ -3,8 +3,9 @@
 propagation at short times and against the free-fermion closed form at all
 200 output times; the L=28 and L=30 chains against the free-fermion closed
 form (zz coupling 0, same kernels); and, where no exact reference exists
-(L=28/30 with zz coupling), the invariants and the FP64/FP32 agreement; the
-8-phase complex64 form at L=28 against the oracle's rows and single-phase runs."""
+(L=28/30 with zz coupling), short-time amplitudes against the Taylor series
+of the oracle's H, the invariants and the FP64/FP32 agreement; the 8-phase
+complex64 form at L=28 against the oracle's rows and single-phase runs."""
 import math
 import os
 
@@ -12,6 +13,7 @@ import numpy as np
 import pytest
 import torch
 
+import moments as MO
 import paper_1704_02770_amd as qk
 from gpu_util import say, to_host
 from oracle import basis as OB
@@ -235,3 +237,42 @@ def test_l24_long_times_invariants(pbc, h):
     P32, _, _ = _evolve(b, H, 24, times, 30, 0.1, torch.complex64)
     say("  complex64 vs complex128 max |dP| =", np.max(np.abs(P32 - P)))
     assert np.max(np.abs(P32 - P)) < 1e-5
+
+
+# ---------------------------------------------------------------------------
+# Short-time amplitudes of the zz-coupled chains at full size, against the
+# Taylor series of exp(-iHt) built from the oracle's H on the states reached
+# from each end (tests/moments.py).  This pins every Krylov direction that
+# contributes at time t on the very chain the benchmark runs (L = 28,
+# h = 1.5, zz coupling 1).
+
+@pytest.mark.parametrize("L,m,t", [(28, 30, 0.04), (30, 20, 0.03)])
+def test_zz_chain_short_time_amplitudes_vs_moments(L, m, t):
+    N, pbc, jxy, jz = L // 2, True, 1.0, 1.0
+    h = OM.fields(L, 1.5, BETA_GOLDEN, PHI)
+    K = 18
+    rem = MO.remainder_bound(L, pbc, jxy, jz, h, t, K)
+    assert rem < 1e-12, rem
+    neel = OM.neel_state(L)
+    # a few other states: one, two and three hops away along different bonds
+    others = [neel ^ 0b11, neel ^ (0b11 << 6) ^ (0b11 << 12), neel ^ (0b11 << 2) ^ (0b11 << 10) ^ (0b11 << 20)]
+    pn = MO.powers(neel, K // 2, L, pbc, jxy, jz, h)
+    want = {neel: MO.taylor_amplitude(pn, pn, t, K)}
+    for s in others:
+        want[s] = MO.taylor_amplitude(MO.powers(s, K // 2, L, pbc, jxy, jz, h), pn, t, K)
+
+    b = qk.qk_basis_build(L, N)
+    H = qk.qk_ham_create(b, jxy, jz, pbc, h)
+    rows = qk.qk_basis_rank(b, list(want))
+    for dtype, tol in ((torch.complex128, 1e-10), (torch.complex64, 2e-6)):
+        say("moments", L, m, t, dtype)
+        k = qk.qk_krylov_create(H, m, dtype)
+        psi = torch.zeros(qk.qk_basis_dim(b), dtype=dtype, device="cuda")
+        psi[int(rows[0])] = 1.0
+        qk.qk_krylov_expm_step(k, psi, t)
+        got = to_host(psi[torch.as_tensor(rows, device="cuda")]).astype(np.complex128)
+        say("max abs amplitude error", float(np.max(np.abs(got - np.array(list(want.values()))))))
+        for (s, w), g in zip(want.items(), got):
+            assert abs(g - w) < tol, (L, dtype, s, g, w)
+        del k, psi
+        torch.cuda.empty_cache()

@@ -208,3 +208,32 @@ def test_autocorrelation_exact_limits_and_trapezoid():
         Ct = X.autocorrelation(t, P)
         errs.append(abs(Ct[-1] - X.autocorrelation_exact(Hd, psi0, [3.0], eig)[0]))
     assert errs[0] < 1e-4 and 3.0 < errs[0] / errs[1] < 5.0
+
+
+@pytest.mark.parametrize("L,pbc,jz", [(10, True, 1.0), (12, False, 0.7)])
+def test_moment_expansion_matches_dense(L, pbc, jz):
+    # the short-time expansion used at full size (tests/moments.py) against
+    # the dense exact propagation, for the Neel amplitude and states 1-3 hops away
+    import moments as MO
+    N = L // 2
+    h = M.fields(L, 1.5, BETA_GOLDEN, 0.4)
+    Hd = Hm.build_dense(L, N, pbc, 1.0, jz, h)
+    states = B.sector_states(L, N)
+    neel = M.neel_state(L)
+    r0 = int(B.lookup(states, [neel])[0])
+    e0 = np.zeros(len(states))
+    e0[r0] = 1.0
+    others = [neel ^ 0b11, neel ^ 0b1100 ^ (0b11 << 6), neel ^ (0b11 << 2) ^ (0b11 << 4) ^ (0b11 << 8)]
+    for t in (0.04, 0.1):
+        K = 18
+        assert MO.remainder_bound(L, pbc, 1.0, jz, h, t, K) < 1e-13
+        psi = X.evolve(Hd, e0, [t])[0]
+        pn = MO.powers(neel, K // 2, L, pbc, 1.0, jz, h)
+        assert abs(MO.taylor_amplitude(pn, pn, t, K) - psi[r0]) < 1e-13
+        for s in others:
+            ps = MO.powers(s, K // 2, L, pbc, 1.0, jz, h)
+            got = MO.taylor_amplitude(ps, pn, t, K)
+            assert abs(got - psi[int(B.lookup(states, [s])[0])]) < 1e-13, (L, t, s)
+    # too few powers for the order is refused
+    with pytest.raises(ValueError):
+        MO.taylor_amplitude(pn[:3], pn[:3], 0.1, 5)
