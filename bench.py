@@ -59,6 +59,8 @@ def parse():
     ap.add_argument("--adaptive-tol", type=float, default=1e-7)
     ap.add_argument("--hv-reps", type=int, default=100)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-aux", action="store_true", help="skip the set-up, CSR and overlap timings")
+    ap.add_argument("--csr-L", type=int, default=22, help="chain length of the CSR-versus-matrix-free H x timing")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU time of the oracle sample")
     ap.add_argument("--cpu-table", action="store_true",
                     help="time the CPU oracle at several sizes on this host (no GPU) and print one JSON line")
@@ -168,6 +170,75 @@ def hv_throughput(qk, torch, b, fields, dtype, reps):
     del H, x, y
     torch.cuda.empty_cache()
     return dict(ms=ms, GBps=2 * s * D / ms / 1e6, copy_GBps=2 * s * D / cms / 1e6)
+
+
+def _apply_ms(qk, torch, H, D, dtype, reps):
+    g = torch.Generator(device="cuda").manual_seed(1)
+    x = torch.randn(D, dtype=dtype, device="cuda", generator=g)
+    y = torch.empty_like(x)
+    qk.qk_ham_apply(H, x, y)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        qk.qk_ham_apply(H, x, y)
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def aux_timings(qk, torch, L, fields1, b, csr_L, h):
+    """Outside the timed steps: building the sector basis and the blocked
+    Hamiltonian tables at L (wall clock, both calls are synchronous); y = H x
+    through the CSR variant against the matrix-free kernel at csr_L; the
+    survival probability of a general (dense) initial state at L."""
+    from workloads import BETA_GOLDEN, phases
+    out = {}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b2 = qk.qk_basis_build(L, L // 2)
+    torch.cuda.synchronize()
+    out["basis_build_ms"] = round((time.perf_counter() - t0) * 1e3, 2)
+    b2.close()
+    t0 = time.perf_counter()
+    H = qk.qk_ham_create(b, 1.0, 1.0, True, fields1)
+    torch.cuda.synchronize()
+    out["ham_create_ms"] = round((time.perf_counter() - t0) * 1e3, 2)
+    H.close()
+    bc = qk.qk_basis_build(csr_L, csr_L // 2)
+    Dc = qk.qk_basis_dim(bc)
+    fc = qk.qk_fields_quasiperiodic(csr_L, h, BETA_GOLDEN, phases(1, 0))
+    t0 = time.perf_counter()
+    Hc = qk.qk_ham_create(bc, 1.0, 1.0, True, fc, mode=qk.QK_CSR)
+    torch.cuda.synchronize()
+    csr_build = (time.perf_counter() - t0) * 1e3
+    Hm = qk.qk_ham_create(bc, 1.0, 1.0, True, fc)
+    ms_csr = _apply_ms(qk, torch, Hc, Dc, torch.complex128, 50)
+    ms_mf = _apply_ms(qk, torch, Hm, Dc, torch.complex128, 50)
+    out["csr_vs_matfree"] = dict(L=csr_L, D=Dc, csr_build_ms=round(csr_build, 2), csr_hx_ms=round(ms_csr, 4),
+                                 matfree_hx_ms=round(ms_mf, 4),
+                                 csr_hx_GBps_algorithmic=round(32 * Dc / ms_csr / 1e6, 1))
+    Hc.close()
+    Hm.close()
+    bc.close()
+    D = qk.qk_basis_dim(b)
+    g = torch.Generator(device="cuda").manual_seed(2)
+    psi0 = torch.randn(D, dtype=torch.complex128, device="cuda", generator=g)
+    psi = torch.randn(D, dtype=torch.complex128, device="cuda", generator=g)
+    P = torch.empty(1, dtype=torch.float64, device="cuda")
+    qk.qk_return_prob(b, psi, psi0=psi0, out=P)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(20):
+        qk.qk_return_prob(b, psi, psi0=psi0, out=P)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / 20
+    out["return_prob_general_state"] = dict(ms=round(ms, 4), GBps_algorithmic=round(32 * D / ms / 1e6, 1))
+    del psi0, psi, P
+    torch.cuda.empty_cache()
+    return out
 
 
 def cpu_baseline(L, m, fields, pbc, target_s):
@@ -321,6 +392,10 @@ def main():
     log("H*x throughput")
     hv["fp64"] = hv_throughput(qk, torch, b, fields1, torch.complex128, args.hv_reps)
     hv["fp32"] = hv_throughput(qk, torch, b, fields1, torch.complex64, args.hv_reps)
+    aux = None
+    if not args.no_aux:
+        log("set-up, CSR and overlap timings")
+        aux = aux_timings(qk, torch, L, fields1, b, args.csr_L, args.h)
     for f in forms:
         log("form", f)
         if f == "fp64":
@@ -402,6 +477,8 @@ def main():
         out["forms"][f] = form_summary(r, B, s)
     if adaptive is not None:
         out["adaptive"] = adaptive
+    if aux is not None:
+        out["aux"] = aux
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         cb = cpu_baseline(L, m, fields1[0], True, args.cpu_seconds)

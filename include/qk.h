@@ -111,8 +111,9 @@ typedef struct qk_basis qk_basis;
  * 2^32 - 1 (QK_EUNSUPPORTED otherwise), which for L > 32 means a low density
  * (the paper's L = 55 runs of Sec. 4).  States are held as 32-bit integers for
  * L <= 32 and as 64-bit integers above.  *out receives the handle; the build
- * is enqueued on `stream`.  Errors: QK_EINVAL, QK_EUNSUPPORTED, QK_ENOMEM,
- * QK_EHIP.
+ * runs on `stream` and the call waits for it, so the handle is ready for use
+ * on any stream when it returns.  Errors: QK_EINVAL, QK_EUNSUPPORTED,
+ * QK_ENOMEM, QK_EHIP.
  */
 qk_status qk_basis_build(int32_t L, int32_t n_up, void* stream, qk_basis** out);
 
@@ -157,7 +158,9 @@ typedef struct qk_ham qk_ham;
  * one-row-per-thread form (an independent second formulation).  QK_CSR
  * stores the column indices of the off-diagonal entries after an exact
  * counting pass (the exact preallocation of Sec. 3); allowed for D <= 2^24.
- * The basis must outlive the Hamiltonian.
+ * The tables are built on `stream` and the call waits for them, so the
+ * handle is ready for use on any stream when it returns.  The basis must
+ * outlive the Hamiltonian.
  * Errors: QK_EINVAL (NULL, batch outside [1, QK_MAX_BATCH], non-finite
  * parameters, CSR too large), QK_ENOMEM, QK_EHIP.
  */

@@ -152,6 +152,12 @@ QK_API qk_status qk_basis_build(int32_t L, int32_t n_up, void* stream, qk_basis*
     return st;
   }
   qk_status st = launch_basis_build(b, (hipStream_t)stream);
+  // the handle is complete on return, so calls on any stream (and the
+  // stream-less qk_basis_rank) may use its tables at once
+  if (st == QK_OK) {
+    const hipError_t se = hipStreamSynchronize((hipStream_t)stream);
+    if (se != hipSuccess) st = hip_fail(se, "qk_basis_build");
+  }
   if (st != QK_OK) {
     qk_basis_destroy(b);
     return st;
@@ -279,6 +285,13 @@ QK_API qk_status qk_ham_create(const qk_basis* b, const qk_ham_params* p, const 
       qk_ham_destroy(H);
       return st;
     }
+  }
+  // complete on return, like the basis (the CSR fill is still in flight here)
+  e = hipStreamSynchronize(s);
+  if (e != hipSuccess) {
+    st = hip_fail(e, "qk_ham_create");
+    qk_ham_destroy(H);
+    return st;
   }
   *out = H;
   return QK_OK;
