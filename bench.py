@@ -238,6 +238,25 @@ def aux_timings(qk, torch, L, fields1, b, csr_L, h):
     out["return_prob_general_state"] = dict(ms=round(ms, 4), GBps_algorithmic=round(32 * D / ms / 1e6, 1))
     del psi0, psi, P
     torch.cuda.empty_cache()
+    # adjoint gradient dF/dh_i: the gradient workload (L = 20, T = 5 in 50
+    # steps, m = 30) and five steps of the L chain
+    for Lg, T, n in ((20, 5.0, 50), (L, 0.5, 5)):
+        bg = qk.qk_basis_build(Lg, Lg // 2)
+        fg = qk.qk_fields_quasiperiodic(Lg, 1.5, BETA_GOLDEN, phases(1, 0))
+        Hg = qk.qk_ham_create(bg, 1.0, 1.0, True, fg)
+        kg = qk.qk_krylov_create(Hg, 30, torch.complex128)
+        rg = int(qk.qk_basis_rank(bg, [sum(1 << i for i in range(0, Lg, 2))])[0])
+        qk.qk_grad_return_prob(kg, rg, T / n, 1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        F, dF = qk.qk_grad_return_prob(kg, rg, T, n)
+        sec = time.perf_counter() - t0
+        out[f"gradient_L{Lg}"] = dict(T=T, steps=n, m=30, seconds=round(sec, 4), ms_per_step=round(1e3 * sec / n, 3),
+                                       F=round(F, 12), max_abs_dFdh=round(float(max(abs(dF))), 9))
+        kg.close()
+        Hg.close()
+        bg.close()
+        torch.cuda.empty_cache()
     return out
 
 
