@@ -1,0 +1,37 @@
+"""Host-side logic of bench.py that needs no GPU: the one-GPU limit and the
+rule that stored counter traffic is reported only for the kernel sources it
+was measured on."""
+import json
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+
+def _run(args, env_extra=None):
+    env = dict(os.environ)
+    env.update(env_extra or {})
+    return subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), *args], capture_output=True, text=True,
+                          env=env, timeout=120)
+
+
+def test_more_than_one_gpu_is_refused():
+    r = _run(["--gpus", "2"])
+    assert r.returncode != 0 and "one GPU" in r.stderr
+    r = _run([], {"WORLD_SIZE": "2"})
+    assert r.returncode != 0 and "one GPU" in r.stderr
+
+
+def test_stored_traffic_matches_the_kernel_sources():
+    import bench
+    tr = json.load(open(bench.TRAFFIC_FILE))
+    if tr["kernel_source_sha256"] != bench.source_sha():
+        # bench.py then reports traffic as null until the counters are taken again
+        pytest.skip("the stored counters predate the current blocked-kernel sources")
+    assert tr["bytes_per_launch"] == tr["fetch_bytes_per_launch"] + tr["write_bytes_per_launch"]
+    assert tr["bytes_per_launch"] > tr["algorithmic_bytes_per_launch"] > 0
+    assert tr["algorithmic_bytes_per_launch"] == round((3 * tr["m"] - 1) * 16 * tr["D"] / tr["m"])
