@@ -9,6 +9,7 @@ kernels of the library.  Failures raise QkError with the library's message.
 from __future__ import annotations
 
 import ctypes as C
+import sys
 
 import numpy as np
 import torch
@@ -71,6 +72,11 @@ class _Handle:
         self.ptr = None
 
     def __del__(self):
+        # at interpreter shutdown the process is about to release the device
+        # anyway, and a destroy could call back into a Python allocator that
+        # is already torn down
+        if sys.is_finalizing():
+            return
         try:
             self.close()
         except Exception:
@@ -121,7 +127,7 @@ def qk_set_allocator(alloc=None, release=None) -> None:
     def _release(ptr, stream, ctx):
         try:
             release(int(ptr), int(stream or 0))
-        except Exception:
+        except Exception:   # nothing can be reported through a release; the block stays allocated
             pass
 
     fa, fr = _native.ALLOC_FN(_alloc), _native.RELEASE_FN(_release)
