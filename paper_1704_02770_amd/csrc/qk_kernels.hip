@@ -141,7 +141,20 @@ k_lanczos_A(const typename Cx<T>::V* __restrict__ uj, const typename Cx<T>::V* _
   block_partials<kQA>(v, B, red, partA + (size_t)blockIdx.x * kQA * B);
 }
 
-template <typename T>
+// Non-temporal load of one complex element, for vectors a pass reads once.
+// Used only for vectors larger than the last-level cache (kNtBytes): there it
+// makes the update pass 9 % and the combination 8 % faster (complex128,
+// L = 28); for vectors that the 256 MB cache can hold (L = 24, 26) it is slower.
+constexpr size_t kNtBytes = (size_t)256 << 20;
+template <typename V>
+__device__ __forceinline__ V ld_nt(const V* p) {
+  using S = decltype(V{}.x);
+  typedef S E __attribute__((ext_vector_type(2)));
+  const E e = __builtin_nontemporal_load(reinterpret_cast<const E*>(p));
+  return V{e.x, e.y};
+}
+
+template <typename T, bool NT>
 __global__ void __launch_bounds__(kMaxBlock)
 k_lanczos_B(const typename Cx<T>::V* __restrict__ uj, const typename Cx<T>::V* __restrict__ ujm1,
             typename Cx<T>::V* __restrict__ w, uint32_t D, int B, KState st, LanczosArgs la,
@@ -210,7 +223,14 @@ k_lanczos_B(const typename Cx<T>::V* __restrict__ uj, const typename Cx<T>::V* _
       const uint32_t r = tw.t * R + rl;
       if (r >= D) continue;
       const size_t i = (size_t)r * B + b;
-      const V wv = w[i], u = uj[i];
+      V wv, u;
+      if (NT) {
+        wv = ld_nt(w + i);
+        u = ld_nt(uj + i);
+      } else {
+        wv = w[i];
+        u = uj[i];
+      }
       double nx = c * ((double)wv.x - d * (double)u.x);
       double ny = c * ((double)wv.y - d * (double)u.y);
       if (ro) {
@@ -438,7 +458,7 @@ k_step_size(KState st, int m, int B, double tau_max, double tol, const double* _
 // unchanged.
 constexpr int kCombineUnroll = 8;
 
-template <typename T, int E, bool ONE>
+template <typename T, int E, bool ONE, bool NT>
 __global__ void __launch_bounds__(kMaxBlock)
 k_combine(typename Cx<T>::V* __restrict__ psi, const typename Cx<T>::V* __restrict__ U, uint32_t D, int B, int m,
           KState st) {
@@ -481,7 +501,18 @@ k_combine(typename Cx<T>::V* __restrict__ psi, const typename Cx<T>::V* __restri
     for (; jj + kCombineUnroll - 1 < mumax; jj += kCombineUnroll) {
       Pack u[kCombineUnroll];
 #pragma unroll
-      for (int k = 0; k < kCombineUnroll; ++k) u[k] = Up[(uint64_t)(jj - 1 + k) * np + p];
+      for (int k = 0; k < kCombineUnroll; ++k) {
+        // the basis vectors are read once per step: non-temporal 16-byte loads
+        // when they exceed the last-level cache
+        const Pack* src = Up + (uint64_t)(jj - 1 + k) * np + p;
+        if constexpr (NT && sizeof(Pack) == 16) {
+          typedef double D2 __attribute__((ext_vector_type(2)));
+          const D2 v = __builtin_nontemporal_load(reinterpret_cast<const D2*>(src));
+          __builtin_memcpy(&u[k], &v, 16);
+        } else {
+          u[k] = *src;
+        }
+      }
 #pragma unroll
       for (int k = 0; k < kCombineUnroll; ++k)
 #pragma unroll
@@ -799,6 +830,22 @@ struct AdaptiveStep {
   double tau_max, tol;
 };
 
+template <typename T, bool NT>
+static void launch_combine(typename Cx<T>::V* psi, const typename Cx<T>::V* U, uint32_t D, int B, int m,
+                           const KState& st, bool pack2, int G, int threads, size_t cfb, hipStream_t s) {
+  if (B == 1) {
+    if (pack2)
+      hipLaunchKernelGGL((k_combine<T, 2, true, NT>), dim3(G), dim3(threads), 0, s, psi, U, D, B, m, st);
+    else
+      hipLaunchKernelGGL((k_combine<T, 1, true, NT>), dim3(G), dim3(threads), 0, s, psi, U, D, B, m, st);
+  } else {
+    if (pack2)
+      hipLaunchKernelGGL((k_combine<T, 2, false, NT>), dim3(G), dim3(threads), cfb, s, psi, U, D, B, m, st);
+    else
+      hipLaunchKernelGGL((k_combine<T, 1, false, NT>), dim3(G), dim3(threads), cfb, s, psi, U, D, B, m, st);
+  }
+}
+
 template <typename T>
 static qk_status krylov_step_t(qk_krylov* k, void* psi_v, double dt, hipStream_t s, bool combine,
                                const AdaptiveStep* ad = nullptr) {
@@ -810,6 +857,8 @@ static qk_status krylov_step_t(qk_krylov* k, void* psi_v, double dt, hipStream_t
   V* psi = (V*)psi_v;
   V* U = (V*)k->d_U;
   const KState st = make_kstate(k);
+  // streaming kernels read with non-temporal loads once a vector outgrows the last-level cache
+  const bool nt = stride * sizeof(V) >= kNtBytes;
   // breakdown threshold relative to the largest coefficient so far
   const double rtol = std::is_same<T, double>::value ? 1e-12 : 1e-5;
 #define QK_MARK(kind, begin)                                   \
@@ -838,7 +887,11 @@ static qk_status krylov_step_t(qk_krylov* k, void* psi_v, double dt, hipStream_t
     QK_HIP(hipGetLastError());
     QK_MARK(QK_KERNEL_LANCZOS_H, false);
     QK_MARK(QK_KERNEL_LANCZOS_UPDATE, true);
-    hipLaunchKernelGGL((k_lanczos_B<T>), dim3(G), dim3(threads), 0, s, uj, ujm1, w, D, B, st, la, k->d_partA, Ga,
+    if (nt)
+      hipLaunchKernelGGL((k_lanczos_B<T, true>), dim3(G), dim3(threads), 0, s, uj, ujm1, w, D, B, st, la, k->d_partA,
+                         Ga, k->d_partB, j + 1 < m ? 1 : 0);
+    else
+      hipLaunchKernelGGL((k_lanczos_B<T, false>), dim3(G), dim3(threads), 0, s, uj, ujm1, w, D, B, st, la, k->d_partA, Ga,
                        k->d_partB, j + 1 < m ? 1 : 0);
     QK_HIP(hipGetLastError());
     if (k->reorth == 2 && j + 1 < m) {
@@ -876,17 +929,10 @@ static qk_status krylov_step_t(qk_krylov* k, void* psi_v, double dt, hipStream_t
   const bool pack2 = sizeof(V) == 8 && ((uint64_t)D * B) % 2 == 0 && ((uintptr_t)psi % 16) == 0 &&
                      ((uintptr_t)U % 16) == 0;
   const size_t cfb = B > 1 ? sizeof(double2) * (size_t)m * B : 0;
-  if (B == 1) {
-    if (pack2)
-      hipLaunchKernelGGL((k_combine<T, 2, true>), dim3(G), dim3(threads), 0, s, psi, U, D, B, m, st);
-    else
-      hipLaunchKernelGGL((k_combine<T, 1, true>), dim3(G), dim3(threads), 0, s, psi, U, D, B, m, st);
-  } else {
-    if (pack2)
-      hipLaunchKernelGGL((k_combine<T, 2, false>), dim3(G), dim3(threads), cfb, s, psi, U, D, B, m, st);
-    else
-      hipLaunchKernelGGL((k_combine<T, 1, false>), dim3(G), dim3(threads), cfb, s, psi, U, D, B, m, st);
-  }
+  if (nt)
+    launch_combine<T, true>(psi, U, D, B, m, st, pack2, G, threads, cfb, s);
+  else
+    launch_combine<T, false>(psi, U, D, B, m, st, pack2, G, threads, cfb, s);
   QK_HIP(hipGetLastError());
   QK_MARK(QK_KERNEL_COMBINE, false);
 #undef QK_MARK
