@@ -390,7 +390,8 @@ k_blk(BlkArgs ba, const typename Cx<T>::V* __restrict__ x, typename Cx<T>::V* __
 // LDS (the block table's constant holds phase 0 only and is not used here).
 // llo is a runtime value chosen so that one block of B phases fits the LDS
 // buffer; the block is staged once (no double buffer).  Each thread keeps the
-// phase tid % B for the whole kernel.
+// phase tid % B for the whole kernel.  The previous Lanczos vector and the
+// result are streamed with non-temporal accesses, as in the one-phase kernel.
 constexpr int kBlkbThreads = 256;
 constexpr uint64_t kBlkbBudget = 32768;   // LDS bytes of one staged block of B phases (complex128)
 
@@ -482,7 +483,7 @@ k_blkb(BlkArgs ba, int B, int lb, const typename Cx<T>::V* __restrict__ x, typen
         const uint32_t bs = lo_state[base + j];
         const uint32_t r = off + j;
         V um = {0, 0};
-        if (prev) um = ujm1[((size_t)r << lb) + bc];
+        if (prev) um = ld32_stream(ujm1 + ((size_t)r << lb), bc);
         const uint32_t bl = (bs >> (llo - 1)) & 1u;
         const bool cx = (bl ^ (a & 1u)) != 0u;
         const uint32_t pcl = (uint32_t)__popc(bs & ((1u << (llo - 1)) - 1u));
@@ -539,13 +540,13 @@ k_blkb(BlkArgs ba, int B, int lb, const typename Cx<T>::V* __restrict__ x, typen
           V wv;
           wv.x = ca * h.x - cb * um.x;
           wv.y = ca * h.y - cb * um.y;
-          y[o] = wv;
+          st32_stream(y + ((size_t)r << lb), bc, wv);
           s1 += (double)xr.x * (double)wv.x + (double)xr.y * (double)wv.y;
           s2 += (double)xr.x * (double)xr.x + (double)xr.y * (double)xr.y;
           s3r += (double)um.x * (double)wv.x + (double)um.y * (double)wv.y;
           s3i += (double)um.x * (double)wv.y - (double)um.y * (double)wv.x;
         } else {
-          y[o] = h;
+          st32_stream(y + ((size_t)r << lb), bc, h);
         }
       }
     }
