@@ -9,7 +9,7 @@ import torch
 
 import paper_1704_02770_amd as qk
 from paper_1704_02770_amd.autograd import survival_probability
-from gpu_util import neel_row, say
+from gpu_util import neel_row, say, to_host
 from oracle import gradient as OG
 from oracle import model as OM
 from workloads import BETA_GOLDEN, WORKLOADS
@@ -121,3 +121,27 @@ def test_gradient_unsupported_and_invalid():
         qk.qk_grad_return_prob(k, 0, float("nan"), 10)
     F, g = qk.qk_grad_return_prob(k, 0, 0.0, 3)   # T = 0: F = 1, no derivative
     assert abs(F - 1.0) < 1e-14 and np.all(g == 0.0)
+
+
+@pytest.mark.parametrize("dtype,tol", [(torch.complex128, 1e-13), (torch.complex64, 1e-6)])
+def test_backward_steps_are_conjugate_forward_steps(dtype, tol):
+    # the backward sweep propagates the costate with steps of -dt; for a real
+    # symmetric H and a real initial vector, exp(+iHt) e = conj(exp(-iHt) e),
+    # so the costate after k backward steps is the conjugate of the state
+    # after k forward steps (blocked H-pass, L = 20)
+    L = 20
+    b = qk.qk_basis_build(L, L // 2)
+    H = qk.qk_ham_create(b, 1.0, 1.0, True, OM.fields(L, 1.5, BETA_GOLDEN, 0.4))
+    r0 = int(qk.qk_basis_rank(b, [OM.neel_state(L)])[0])
+    D = qk.qk_basis_dim(b)
+    out = []
+    for dt in (0.1, -0.1):
+        say("costate identity", dtype, dt)
+        k = qk.qk_krylov_create(H, 30, dtype)
+        psi = torch.zeros(D, dtype=dtype, device="cuda")
+        psi[r0] = 1.0
+        for _ in range(5):
+            qk.qk_krylov_expm_step(k, psi, dt)
+        out.append(to_host(psi).astype(np.complex128))
+    assert np.max(np.abs(out[1] - np.conj(out[0]))) < tol
+    assert abs(np.linalg.norm(out[0]) - 1.0) < 10 * tol

@@ -101,3 +101,30 @@ def test_hopping_sign_on_odd_ring():
     jxy = 1.4
     H = Hm.build_dense(3, 1, True, jxy, 0.0, np.zeros(3))
     assert np.allclose(np.linalg.eigvalsh(H), [-jxy / 2, -jxy / 2, jxy], atol=1e-14)
+
+
+def test_mean_offdiagonal_count_and_table3_memory_law():
+    # Sec. 3's exact preallocation counts, per row, the bonds whose two bits
+    # differ.  At half filling on a ring their mean is L^2 / (2 (L - 1)) (each
+    # of the L bonds differs with probability 2 N (L - N) / (L (L - 1))); the
+    # oracle's counts must reproduce it exactly at small L.
+    from math import comb
+
+    from conftest import read_golden
+    for L in (8, 10, 12, 14, 16):
+        N = L // 2
+        cnt = Hm.nnz_per_row(L, N, True)
+        assert cnt.sum() * 2 * (L - 1) == L * L * comb(L, N)
+        cnt_obc = Hm.nnz_per_row(L, N, False)
+        assert cnt_obc.sum() * 2 * (L - 1) == L * (L - 1) * comb(L, N)
+    # Sec. 5, Table III: the estimated matrix memory grows like the number of
+    # stored entries D (1 + L^2 / (2 (L - 1))): bytes per stored entry stay
+    # within a few per cent of each other from L = 28 to 38 (the table prints
+    # two to four significant figures).
+    per_entry = []
+    for L, D, mem_gb, _ in read_golden("table3_memory.txt"):
+        L = int(L)
+        assert abs(comb(L, L // 2) / float(D) - 1) < 0.006
+        entries = comb(L, L // 2) * (1 + L * L / (2 * (L - 1)))
+        per_entry.append(float(mem_gb) * 1e9 / entries)
+    assert max(per_entry) / min(per_entry) < 1.03, per_entry
