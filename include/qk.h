@@ -286,7 +286,7 @@ qk_status qk_krylov_profile_read(qk_krylov* k, qk_kernel_time* out);
 typedef struct {
   int32_t threads;             /* threads per block of the row-streaming kernels
                                   (rounded down to batch * 2^k); 0 = 256 */
-  int32_t blocks_per_cu;       /* blocks per compute unit of the row-streaming kernels; 0 = 8 */
+  int32_t blocks_per_cu;       /* blocks per compute unit of the row-streaming kernels; 0 = 4 */
   int32_t blocked_wgs_per_cu;  /* work-groups per compute unit of the blocked H-pass;
                                   0 = as many as fit */
 } qk_launch_shape;

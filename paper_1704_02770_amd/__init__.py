@@ -71,11 +71,12 @@ class _Handle:
             type(self)._destroy(self.ptr)
         self.ptr = None
 
-    def __del__(self):
+    def __del__(self, _finalizing=sys.is_finalizing):
         # at interpreter shutdown the process is about to release the device
         # anyway, and a destroy could call back into a Python allocator that
-        # is already torn down
-        if sys.is_finalizing():
+        # is already torn down (the check is bound at definition time, since
+        # module globals may already be cleared then)
+        if _finalizing():
             return
         try:
             self.close()
