@@ -106,3 +106,44 @@ def test_set_allocator_validation():
     with pytest.raises(ValueError):
         qk.qk_set_allocator(alloc=lambda n, s: 0)
     qk.qk_set_allocator()
+
+
+def test_argument_validation_property():
+    # random arguments at the boundary: every call returns a status from the
+    # documented set (no crash, no exception), and invalid shapes are EINVAL
+    # or EUNSUPPORTED before any device work (here there is no device at all)
+    from hypothesis import given, settings
+    from hypothesis import strategies as st
+    import paper_1704_02770_amd as qk
+    from paper_1704_02770_amd._native import lib
+    from math import comb
+
+    @settings(max_examples=300, deadline=None)
+    @given(L=st.integers(-4, 72), n=st.integers(-4, 72))
+    def basis(L, n):
+        out = C.c_void_p()
+        if 2 <= L <= 64 and 0 < n < L and 1e6 < comb(L, n) < 0xFFFFFFFF:
+            return   # a valid sector too large to build in a unit test where a device exists
+        s = lib.qk_basis_build(L, n, None, C.byref(out))
+        if L < 2 or L > 64 or n <= 0 or n >= L:
+            assert s == qk.QK_EINVAL
+        elif comb(L, n) >= 0xFFFFFFFF:
+            assert s == qk.QK_EUNSUPPORTED
+        else:
+            assert s in (qk.QK_OK, qk.QK_EHIP, qk.QK_ENOMEM)
+            if s == qk.QK_OK:
+                lib.qk_basis_destroy(out)
+
+    @settings(max_examples=200, deadline=None)
+    @given(L=st.integers(-2, 70), h=st.floats(allow_nan=True, allow_infinity=True),
+           beta=st.floats(-2, 2), nphi=st.integers(0, 3))
+    def fields(L, h, beta, nphi):
+        phi = np.zeros(max(nphi, 1))
+        out = np.zeros((max(nphi, 1), max(L, 1)))
+        s = lib.qk_fields_quasiperiodic(L, h, beta, phi.ctypes.data_as(C.POINTER(C.c_double)), nphi,
+                                        out.ctypes.data_as(C.POINTER(C.c_double)))
+        ok = 1 <= L <= 64 and nphi >= 1 and np.isfinite(h)
+        assert s == (qk.QK_OK if ok else qk.QK_EINVAL)
+
+    basis()
+    fields()
