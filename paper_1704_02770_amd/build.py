@@ -37,7 +37,29 @@ def build(verbose: bool = False) -> str:
         sys.stderr.write(r.stdout + r.stderr)
         raise RuntimeError("hipcc failed building libqkrylov.so")
     os.replace(tmp, LIB)
+    build_c_demo(verbose)
     return LIB
+
+
+DEMO_SRC = os.path.join(ROOT, "tests", "c_abi", "qk_demo.c")
+DEMO = os.path.join(ROOT, "tests", "c_abi", "qk_demo")
+
+
+def build_c_demo(verbose: bool = False) -> str:
+    """The plain C user of the ABI (tests/c_abi/qk_demo.c), linked against the
+    in-tree library and the HIP runtime with gcc."""
+    rocm = os.path.dirname(os.path.dirname(os.path.realpath(HIPCC)))
+    cmd = ["gcc", "-O2", "-std=c11", "-Wall", "-Wextra", "-D__HIP_PLATFORM_AMD__",
+           "-I", os.path.join(ROOT, "include"), "-I", os.path.join(rocm, "include"), DEMO_SRC,
+           "-L", HERE, "-lqkrylov", "-L", os.path.join(rocm, "lib"), "-lamdhip64", "-lm",
+           "-Wl,-rpath,$ORIGIN/../../paper_1704_02770_amd", "-Wl,-rpath," + os.path.join(rocm, "lib"), "-o", DEMO]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        sys.stderr.write(r.stdout + r.stderr)
+        raise RuntimeError("gcc failed building tests/c_abi/qk_demo")
+    return DEMO
 
 
 if __name__ == "__main__":
