@@ -386,6 +386,7 @@ qk_status qk::krylov_create(const qk_ham* H, int32_t m, int32_t dtype, int32_t r
   if (e == hipSuccess) e = dev_alloc(k->al, (void**)&k->d_partB, sizeof(double) * (size_t)kMaxPartialBlocks * k->batch);
   if (e == hipSuccess) e = dev_alloc(k->al, (void**)&k->d_coef, sizeof(double) * kstate_doubles(m, k->batch));
   if (e == hipSuccess) e = dev_alloc(k->al, (void**)&k->d_int, sizeof(int32_t) * 2 * k->batch);
+  if (e == hipSuccess) e = dev_alloc(k->al, (void**)&k->d_ptot, sizeof(double) * (size_t)(kQA + 1) * k->batch);
   if (e == hipSuccess) e = hipMemset(k->d_coef, 0, sizeof(double) * kstate_doubles(m, k->batch));
   if (e == hipSuccess) e = hipMemset(k->d_int, 0, sizeof(int32_t) * 2 * k->batch);
   if (e == hipSuccess && reorth == 2) {
@@ -569,6 +570,7 @@ QK_API void qk_krylov_destroy(qk_krylov* k) {
   dev_free(k->al, k->d_rcoef);
   dev_free(k->al, k->d_coef);
   dev_free(k->al, k->d_int);
+  dev_free(k->al, k->d_ptot);
   delete k;
 }
 

@@ -120,6 +120,7 @@ struct qk_krylov {
   void* d_U = nullptr;            // m slots of [D][batch] vectors: u_1..u_m
   double* d_partA = nullptr;      // [grid][2][batch] partial sums of the H-pass
   double* d_partB = nullptr;      // [grid][1][batch] partial sums of the update pass
+  double* d_ptot = nullptr;       // [kQA + 1][batch] totals of both (batches of 8 or more)
   double* d_coef = nullptr;       // coefficient block, see qk::KState
   int32_t* d_int = nullptr;       // [2][batch]: m_used, status
   double* d_rpart = nullptr;      // full reorthogonalisation: [chunks][kReorthGrid][2 kReorthChunk][batch] partial dots

@@ -154,6 +154,24 @@ __device__ __forceinline__ V ld_nt(const V* p) {
   return V{e.x, e.y};
 }
 
+// Totals of per-block partial sums part[g][c] (g < G, c < cols) into tot[c],
+// each column summed in a fixed order (four lanes over g, then the lanes in
+// order), so every consumer reads one row instead of reducing G rows itself.
+// Used for batches of kPreReduceBatch items or more, where the G x cols
+// partials make that per-block reduction the longest part of a pass.
+constexpr int kPreReduceBatch = 8;
+__global__ void __launch_bounds__(256) k_partials_total(const double* __restrict__ part, int G, int cols,
+                                                        double* __restrict__ tot) {
+  __shared__ double red[256];
+  const int c = blockIdx.x * 64 + (threadIdx.x & 63), l = threadIdx.x >> 6;
+  double acc = 0.0;
+  if (c < cols)
+    for (int g = l; g < G; g += 4) acc += part[(size_t)g * cols + c];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  if (l == 0 && c < cols) tot[c] = ((red[threadIdx.x] + red[threadIdx.x + 64]) + red[threadIdx.x + 128]) + red[threadIdx.x + 192];
+}
+
 template <typename T, bool NT>
 __global__ void __launch_bounds__(kMaxBlock)
 k_lanczos_B(const typename Cx<T>::V* __restrict__ uj, const typename Cx<T>::V* __restrict__ ujm1,
@@ -870,6 +888,13 @@ static qk_status krylov_step_t(qk_krylov* k, void* psi_v, double dt, hipStream_t
       if (ps_ != QK_OK) return ps_;                            \
     }                                                          \
   } while (0)
+  // large batches: partial sums are totalled once per pass (k_partials_total)
+  // and consumers read the single row of totals
+  const bool pre = B >= kPreReduceBatch;
+  double* totA = k->d_ptot;
+  double* totB = k->d_ptot + (size_t)kQA * B;
+  const double* pB = pre ? totB : k->d_partB;
+  const int GB = pre ? 1 : G;
   for (int j = 0; j < m; ++j) {
     LanczosArgs la{j, m, rtol, k->reorth == 1 ? 1 : 0};
     const V* uj = j == 0 ? psi : U + (size_t)(j - 1) * stride;
@@ -878,23 +903,31 @@ static qk_status krylov_step_t(qk_krylov* k, void* psi_v, double dt, hipStream_t
     QK_MARK(QK_KERNEL_LANCZOS_H, true);
     int Ga = G;
     if (blocked_usable(H, k->dtype)) {
-      qk_status bs = launch_blocked_lanczos_h(H, k->dtype, uj, ujm1, w, st, la, k->d_partB, G, k->d_partA, &Ga,
+      qk_status bs = launch_blocked_lanczos_h(H, k->dtype, uj, ujm1, w, st, la, pB, GB, k->d_partA, &Ga,
                                               k->blocked_wgs, s);
       if (bs != QK_OK) return bs;
     } else if (H->basis->wide) {
-      launch_lanczos_rows<T, uint64_t>(H, uj, ujm1, w, st, la, k->d_partB, G, threads, k->d_partA, s);
+      launch_lanczos_rows<T, uint64_t>(H, uj, ujm1, w, st, la, pB, GB, threads, k->d_partA, s);
     } else {
-      launch_lanczos_rows<T, uint32_t>(H, uj, ujm1, w, st, la, k->d_partB, G, threads, k->d_partA, s);
+      launch_lanczos_rows<T, uint32_t>(H, uj, ujm1, w, st, la, pB, GB, threads, k->d_partA, s);
     }
     QK_HIP(hipGetLastError());
     QK_MARK(QK_KERNEL_LANCZOS_H, false);
     QK_MARK(QK_KERNEL_LANCZOS_UPDATE, true);
+    const double* pA = k->d_partA;
+    int GA = Ga;
+    if (pre) {
+      hipLaunchKernelGGL(k_partials_total, dim3((kQA * B + 63) / 64), dim3(256), 0, s, k->d_partA, Ga, kQA * B, totA);
+      QK_HIP(hipGetLastError());
+      pA = totA;
+      GA = 1;
+    }
     if (nt)
-      hipLaunchKernelGGL((k_lanczos_B<T, true>), dim3(G), dim3(threads), 0, s, uj, ujm1, w, D, B, st, la, k->d_partA,
-                         Ga, k->d_partB, j + 1 < m ? 1 : 0);
+      hipLaunchKernelGGL((k_lanczos_B<T, true>), dim3(G), dim3(threads), 0, s, uj, ujm1, w, D, B, st, la, pA, GA,
+                         k->d_partB, j + 1 < m ? 1 : 0);
     else
-      hipLaunchKernelGGL((k_lanczos_B<T, false>), dim3(G), dim3(threads), 0, s, uj, ujm1, w, D, B, st, la, k->d_partA, Ga,
-                       k->d_partB, j + 1 < m ? 1 : 0);
+      hipLaunchKernelGGL((k_lanczos_B<T, false>), dim3(G), dim3(threads), 0, s, uj, ujm1, w, D, B, st, la, pA, GA,
+                         k->d_partB, j + 1 < m ? 1 : 0);
     QK_HIP(hipGetLastError());
     if (k->reorth == 2 && j + 1 < m) {
       // u_{j+1} against v_0..v_j, twice
@@ -913,16 +946,20 @@ static qk_status krylov_step_t(qk_krylov* k, void* psi_v, double dt, hipStream_t
         QK_HIP(hipGetLastError());
       }
     }
+    if (pre) {
+      hipLaunchKernelGGL(k_partials_total, dim3((B + 63) / 64), dim3(256), 0, s, k->d_partB, G, B, totB);
+      QK_HIP(hipGetLastError());
+    }
     QK_MARK(QK_KERNEL_LANCZOS_UPDATE, false);
   }
   if (!combine) return QK_OK;   // only the Krylov basis and coefficients were asked for
   QK_MARK(QK_KERNEL_SMALL_EXPM, true);
   if (ad) {
-    hipLaunchKernelGGL(k_step_size, dim3(B), dim3(64), 0, s, st, m, B, ad->tau_max, ad->tol, k->d_partB, G);
+    hipLaunchKernelGGL(k_step_size, dim3(B), dim3(64), 0, s, st, m, B, ad->tau_max, ad->tol, pB, GB);
     QK_HIP(hipGetLastError());
   }
   hipLaunchKernelGGL(k_small_expm, dim3(B), dim3(64), 0, s, st, m, B, dt, ad ? (const double*)st.tau : nullptr,
-                     k->d_partB, G);
+                     pB, GB);
   QK_HIP(hipGetLastError());
   QK_MARK(QK_KERNEL_SMALL_EXPM, false);
   QK_MARK(QK_KERNEL_COMBINE, true);
