@@ -155,21 +155,28 @@ __device__ __forceinline__ V ld_nt(const V* p) {
 }
 
 // Totals of per-block partial sums part[g][c] (g < G, c < cols) into tot[c],
-// each column summed in a fixed order (four lanes over g, then the lanes in
-// order), so every consumer reads one row instead of reducing G rows itself.
-// Used for batches of kPreReduceBatch items or more, where the G x cols
-// partials make that per-block reduction the longest part of a pass.
+// each column summed in a fixed order (32 lanes over g, then a fixed tree
+// over the lanes), so every consumer reads one row instead of reducing G rows
+// itself.  Used for batches of kPreReduceBatch items or more, where the
+// G x cols partials make that per-block reduction the longest part of a pass.
 constexpr int kPreReduceBatch = 8;
+constexpr int kTotLanes = 32;                  // lanes per column
+constexpr int kTotCols = 256 / kTotLanes;      // columns per block
 __global__ void __launch_bounds__(256) k_partials_total(const double* __restrict__ part, int G, int cols,
                                                         double* __restrict__ tot) {
   __shared__ double red[256];
-  const int c = blockIdx.x * 64 + (threadIdx.x & 63), l = threadIdx.x >> 6;
+  const int tid = threadIdx.x;
+  const int c = blockIdx.x * kTotCols + tid / kTotLanes, l = tid % kTotLanes;
   double acc = 0.0;
   if (c < cols)
-    for (int g = l; g < G; g += 4) acc += part[(size_t)g * cols + c];
-  red[threadIdx.x] = acc;
+    for (int g = l; g < G; g += kTotLanes) acc += part[(size_t)g * cols + c];
+  red[tid] = acc;
   __syncthreads();
-  if (l == 0 && c < cols) tot[c] = ((red[threadIdx.x] + red[threadIdx.x + 64]) + red[threadIdx.x + 128]) + red[threadIdx.x + 192];
+  for (int h = kTotLanes / 2; h > 0; h >>= 1) {
+    if (l < h) red[tid] += red[tid + h];
+    __syncthreads();
+  }
+  if (l == 0 && c < cols) tot[c] = red[tid];
 }
 
 template <typename T, bool NT>
@@ -917,7 +924,8 @@ static qk_status krylov_step_t(qk_krylov* k, void* psi_v, double dt, hipStream_t
     const double* pA = k->d_partA;
     int GA = Ga;
     if (pre) {
-      hipLaunchKernelGGL(k_partials_total, dim3((kQA * B + 63) / 64), dim3(256), 0, s, k->d_partA, Ga, kQA * B, totA);
+      hipLaunchKernelGGL(k_partials_total, dim3((kQA * B + kTotCols - 1) / kTotCols), dim3(256), 0, s, k->d_partA, Ga,
+                         kQA * B, totA);
       QK_HIP(hipGetLastError());
       pA = totA;
       GA = 1;
@@ -947,7 +955,8 @@ static qk_status krylov_step_t(qk_krylov* k, void* psi_v, double dt, hipStream_t
       }
     }
     if (pre) {
-      hipLaunchKernelGGL(k_partials_total, dim3((B + 63) / 64), dim3(256), 0, s, k->d_partB, G, B, totB);
+      hipLaunchKernelGGL(k_partials_total, dim3((B + kTotCols - 1) / kTotCols), dim3(256), 0, s, k->d_partB, G, B,
+                         totB);
       QK_HIP(hipGetLastError());
     }
     QK_MARK(QK_KERNEL_LANCZOS_UPDATE, false);
