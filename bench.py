@@ -64,7 +64,19 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU time of the oracle sample")
     ap.add_argument("--cpu-table", action="store_true",
                     help="time the CPU oracle at several sizes on this host (no GPU) and print one JSON line")
-    return ap.parse_args()
+    args = ap.parse_args()
+    problems = []
+    if args.steps < 1 or args.warmup < 0 or args.hv_reps < 1:
+        problems.append("--steps and --hv-reps must be >= 1 and --warmup >= 0")
+    if args.L < 4 or args.L > 32 or args.L % 2:
+        problems.append("--L must be even, 4 <= L <= 32 (the Sz = 0 sector)")
+    if args.m < 1 or args.m > 64 or not math.isfinite(args.dt) or args.dt <= 0:
+        problems.append("--m must be in [1, 64] and --dt positive")
+    if args.batch < 2 or args.batch > 64 or args.batch & (args.batch - 1):
+        problems.append("--batch must be a power of two in [2, 64]")
+    if problems:
+        ap.error("; ".join(problems))
+    return args
 
 
 def source_sha():

@@ -35,3 +35,9 @@ def test_stored_traffic_matches_the_kernel_sources():
     assert tr["bytes_per_launch"] == tr["fetch_bytes_per_launch"] + tr["write_bytes_per_launch"]
     assert tr["bytes_per_launch"] > tr["algorithmic_bytes_per_launch"] > 0
     assert tr["algorithmic_bytes_per_launch"] == round((3 * tr["m"] - 1) * 16 * tr["D"] / tr["m"])
+
+
+def test_bad_arguments_are_refused_before_any_device_work():
+    for args in (["--steps", "0"], ["--L", "27"], ["--L", "40"], ["--L", "2"], ["--m", "0"], ["--dt", "-1"], ["--batch", "6"]):
+        r = _run(args)
+        assert r.returncode == 2 and "error" in r.stderr, (args, r.stderr)
