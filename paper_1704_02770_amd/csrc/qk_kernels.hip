@@ -70,7 +70,7 @@ __global__ void k_rank(const uint64_t* __restrict__ in, int64_t n, int64_t* __re
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   uint64_t s = in[i];
-  if ((L < 64 && (s >> L) != 0) || __popcll(s) != N) {
+  if ((L < 64 && (s >> L) != 0) || (int)__popcll(s) != N) {
     out[i] = -1;
     return;
   }
