@@ -174,9 +174,13 @@ qk_status qk_ham_set_fields(qk_ham* H, const double* h_host, int32_t batch, void
 qk_status qk_ham_shape(const qk_ham* H, int64_t* D, int32_t* batch, int32_t* mode);
 
 /*
- * y = H x for every batch item (problem k uses field set k): x, y are [D][B]
- * device arrays of `dtype`; x and y must not overlap (QK_EINVAL).  QK_C128
- * accumulates in double, QK_C64 in float.
+ * y = H x with the Hamiltonian of Eq. (1), row by row as Sec. 3
+ * ("Hamiltonian matrix construction") defines it: the diagonal from the zz
+ * bonds and the fields, and jxy/2 in the column of the state with the two
+ * bits of every anti-aligned bond exchanged (no matrix is stored in the
+ * matrix-free modes).  For every batch item (problem k uses field set k):
+ * x, y are [D][B] device arrays of `dtype`; x and y must not overlap
+ * (QK_EINVAL).  QK_C128 accumulates in double, QK_C64 in float.
  */
 qk_status qk_ham_apply(const qk_ham* H, const void* x, void* y, int32_t dtype, void* stream);
 

@@ -102,14 +102,13 @@ def first_int(L: int, N: int, start: int) -> int:
 
 
 def distribution(D: int, nprocs: int, rank: int) -> tuple[int, int, int]:
-    """Algorithm 1: block-row partition (nlocal, start, end) of D rows."""
-    nlocal = D // nprocs
-    rest = D % nprocs
-    if rest and rank < rest:
-        nlocal += 1
-    start = rank * nlocal
-    if rest and rank >= rest:
-        start += rest
+    """Balanced block-row partition of D rows over nprocs ranks, the
+    distribution of Algorithm 1: every rank gets floor(D / nprocs) rows and
+    the first D mod nprocs ranks one more, in rank order.  Returns
+    (nlocal, start, end) of `rank`."""
+    q, r = divmod(D, nprocs)
+    nlocal = q + (1 if rank < r else 0)
+    start = rank * q + min(rank, r)
     return nlocal, start, start + nlocal
 
 

@@ -42,11 +42,13 @@ def dF_dh(L: int, N: int, pbc: bool, jxy: float, jz: float, h: np.ndarray, r0: i
 
 
 def dF_dh_finite_difference(L: int, N: int, pbc: bool, jxy: float, jz: float, h: np.ndarray,
-                            r0: int, T: float, eps: float = 1e-6, propagate=None) -> np.ndarray:
+                            r0: int, T: float, eps: float = 1e-6, propagate=None,
+                            indices=None) -> np.ndarray:
     """Central differences (F(h + eps e_i) - F(h - eps e_i)) / (2 eps).
 
     `propagate(h) -> F(T)` may be supplied (e.g. a mid-size propagator); the
-    default diagonalises the dense H.
+    default diagonalises the dense H.  `indices` restricts the result to the
+    listed fields (in that order); the default is all L of them.
     """
     h = np.asarray(h, dtype=np.float64)
 
@@ -56,9 +58,10 @@ def dF_dh_finite_difference(L: int, N: int, pbc: bool, jxy: float, jz: float, h:
         H = _ham.build_dense(L, N, pbc, jxy, jz, hh)
         return float(_exact.survival_probability(H, r0, [T])[0])
 
-    out = np.empty(L)
-    for i in range(L):
+    idx = list(range(L)) if indices is None else [int(i) for i in indices]
+    out = np.empty(len(idx))
+    for n, i in enumerate(idx):
         hp = h.copy(); hp[i] += eps
         hm = h.copy(); hm[i] -= eps
-        out[i] = (F_of(hp) - F_of(hm)) / (2 * eps)
+        out[n] = (F_of(hp) - F_of(hm)) / (2 * eps)
     return out

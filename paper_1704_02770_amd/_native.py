@@ -16,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libqkrylov.so")
 
 if not os.path.exists(LIB_PATH):
-    raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1704_02770_amd.build`")
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python paper_1704_02770_amd/build.py` (run by path from the repository root)")
 
 lib = C.CDLL(LIB_PATH, mode=C.RTLD_GLOBAL)
 

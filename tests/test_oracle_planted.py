@@ -25,6 +25,7 @@ _orig_first = B.first_int
 _orig_states = B.sector_states
 _orig_acx = X.autocorrelation_exact
 _orig_dF = G.dF_dh
+_orig_bound = K.error_bound
 
 
 def _fails(*checks):
@@ -107,6 +108,22 @@ def _dF_sites_reversed(*args, **kw):
     return F, g[::-1].copy()
 
 
+def _bound_sign_flipped(m, t, normA):
+    # e^(m + x) instead of e^(m - x): an overestimate everywhere
+    x = t * normA
+    return _orig_bound(m, t, normA) * np.exp(2 * x) if x > 0 else 0.0
+
+
+def _bound_extra_e(m, t, normA):
+    return np.e * _orig_bound(m, t, normA)
+
+
+def _bound_power_m_minus_1(m, t, normA):
+    # (x / m)^(m - 1) instead of (x / m)^m
+    x = t * normA
+    return _orig_bound(m, t, normA) * m / x if x > 0 else 0.0
+
+
 def _hop_full(jxy):
     return jxy
 
@@ -131,6 +148,9 @@ PLANTS = {
     "large sectors on shifted bits": [(B, "sector_states", _subsets_shifted)],
     "gradient without the factor 2": [(G, "dF_dh", _dF_half)],
     "gradient on mirrored sites": [(G, "dF_dh", _dF_sites_reversed)],
+    "error bound with the exponent's sign flipped": [(K, "error_bound", _bound_sign_flipped)],
+    "error bound with an extra factor e": [(K, "error_bound", _bound_extra_e)],
+    "error bound with power m - 1": [(K, "error_bound", _bound_power_m_minus_1)],
 }
 
 CHECKS = [
@@ -146,6 +166,7 @@ CHECKS = [
     TP.test_autocorrelation_exact_two_level_closed_form, TP.test_autocorrelation_exact_limits_and_trapezoid,
     TB.test_large_sector_enumeration,
     lambda: TG.test_daleckii_krein_vs_finite_differences(True), TG.test_gradient_sums_to_zero,
+    TP.test_error_bound_is_tight_at_the_edge_of_its_regime,
 ]
 
 
