@@ -386,6 +386,22 @@ qk_status qk_grad_return_prob(qk_krylov* k, int64_t r0, double T, int32_t n_step
 qk_status qk_return_prob(const qk_basis* b, int64_t r0, const void* psi0, const void* psi,
                          int32_t dtype, int32_t batch, double* P_device, void* stream);
 
+/*
+ * For callers that cannot allocate device memory (code under hipGraph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * result as qk_return_prob, from the same kernels, but the partial sums of
+ * the general-state overlap live in a fixed array of the library on each GPU
+ * (4 MiB, held until the process ends) instead of a temporary, and the call
+ * allocates nothing.  Arguments, ownership and errors are those of
+ * qk_return_prob; in addition QK_EINVAL if the overlap's partial sums would
+ * exceed the fixed array (never for batch <= QK_MAX_BATCH on up to 4096
+ * compute units).  All calls on one GPU share that array: calls that overlap
+ * in time on one GPU (other streams, other threads) race and must be
+ * serialised by the caller.  Asynchronous.
+ */
+qk_status qk_return_prob_noalloc(const qk_basis* b, int64_t r0, const void* psi0, const void* psi,
+                                 int32_t dtype, int32_t batch, double* P_device, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

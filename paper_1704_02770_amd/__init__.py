@@ -415,4 +415,17 @@ def qk_return_prob(b: Basis, psi: torch.Tensor, r0: int = -1, psi0: torch.Tensor
     return out
 
 
+def qk_return_prob_noalloc(b: Basis, psi: torch.Tensor, out: torch.Tensor, r0: int = -1,
+                           psi0: torch.Tensor | None = None, batch: int = 1, stream=None) -> torch.Tensor:
+    """qk_return_prob without any device allocation: the caller supplies `out`
+    (float64, `batch` entries); the overlap's partial sums use the library's
+    fixed per-GPU scratch array, so calls overlapping on one GPU race."""
+    p0 = None if psi0 is None else _dptr(psi0)
+    if psi0 is not None and psi0.dtype != psi.dtype:
+        raise ValueError("psi0 and psi dtypes differ")
+    _check(lib.qk_return_prob_noalloc(b.ptr, int(r0), p0, _dptr(psi), dtype_code(psi), batch, _dptr(out),
+                                      _stream(stream)), "qk_return_prob_noalloc")
+    return out
+
+
 __all__ = [n for n in dir() if n.startswith("qk_")] + ["QkError", "Basis", "Ham", "Krylov", "Batch", "use_torch_allocator"]

@@ -86,6 +86,7 @@ SIGNATURES = {
     "qk_batch_destroy": (None, [vp]),
     "qk_grad_return_prob": (i32, [vp, i64, f64, i32, i32, P(f64), P(f64), vp]),
     "qk_return_prob": (i32, [vp, i64, vp, vp, i32, i32, vp, vp]),
+    "qk_return_prob_noalloc": (i32, [vp, i64, vp, vp, i32, i32, vp, vp]),
 }
 
 for _name, (_res, _args) in SIGNATURES.items():

@@ -683,3 +683,15 @@ QK_API qk_status qk_return_prob(const qk_basis* b, int64_t r0, const void* psi0,
   if (st != QK_OK) return st;
   return launch_return_prob(b, r0, psi0, psi, dtype, batch, P_device, (hipStream_t)stream);
 }
+
+QK_API qk_status qk_return_prob_noalloc(const qk_basis* b, int64_t r0, const void* psi0, const void* psi,
+                                        int32_t dtype, int32_t batch, double* P_device, void* stream) {
+  g_err.clear();
+  if (!b || !psi || !P_device) return inval("NULL pointer");
+  if (dtype != QK_C128 && dtype != QK_C64) return inval("unknown dtype");
+  if (batch < 1 || batch > QK_MAX_BATCH) return inval("batch must be in [1, 64]");
+  if (!psi0 && (r0 < 0 || r0 >= b->D)) return inval("r0 out of range");
+  qk_status st = check_device(b->device);
+  if (st != QK_OK) return st;
+  return launch_return_prob_noalloc(b, r0, psi0, psi, dtype, batch, P_device, (hipStream_t)stream);
+}

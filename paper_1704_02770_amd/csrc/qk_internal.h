@@ -203,5 +203,9 @@ int batch_device(const qk_batch* b);
 qk_status profile_collect(qk_krylov* k);
 qk_status launch_return_prob(const qk_basis* b, int64_t r0, const void* psi0, const void* psi, int dtype,
                              int B, double* P, hipStream_t s);
+// qk_return_prob with the overlap partials in the library's fixed per-GPU
+// scratch array instead of a temporary allocation
+qk_status launch_return_prob_noalloc(const qk_basis* b, int64_t r0, const void* psi0, const void* psi, int dtype,
+                                     int B, double* P, hipStream_t s);
 
 }  // namespace qk

@@ -13,6 +13,7 @@
 #include <hipcub/hipcub.hpp>
 
 #include <cmath>
+#include <mutex>
 #include <type_traits>
 
 #include "qk_device.h"
@@ -1060,6 +1061,64 @@ qk_status launch_return_prob(const qk_basis* b, int64_t r0, const void* psi0, co
   }
   QK_HIP(dev_free_async(b->al, part, s));
   QK_HIP(e);
+  return QK_OK;
+}
+
+// --------------------------------------- survival probability without allocation
+// Partial sums of the general-state overlap for callers that cannot allocate
+// (graph capture, serving loops): one file-scope array per GPU, large enough
+// for the widest grid of the overlap pass (kMaxPartialBlocks blocks x 2 x 64
+// batch columns, 4 MiB), held until the process ends.  Host code never uses
+// the array's name as an address: the device address comes from
+// hipGetSymbolAddress, once per device, with that device current.  Every
+// slot the final reduction reads is written by the partial pass of the same
+// call, so nothing has to be cleared; calls that overlap on one GPU share
+// the array and race.
+constexpr size_t kNoAllocScratchDoubles = (size_t)kMaxPartialBlocks * 2 * QK_MAX_BATCH;
+__device__ __align__(256) double scratch[kNoAllocScratchDoubles];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[kMaxDevices] = {};
+
+static qk_status scratch_address(int dev, double** out) {
+  if (dev < 0 || dev >= kMaxDevices) {
+    set_error("device index beyond the scratch table");
+    return QK_EUNSUPPORTED;
+  }
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    QK_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    g_scratch_ptr[dev] = p;
+  }
+  *out = (double*)g_scratch_ptr[dev];
+  return QK_OK;
+}
+
+qk_status launch_return_prob_noalloc(const qk_basis* b, int64_t r0, const void* psi0, const void* psi, int dtype,
+                                     int B, double* P, hipStream_t s) {
+  if (psi0 == nullptr) return launch_return_prob(b, r0, psi0, psi, dtype, B, P, s);   // one element, no scratch
+  const uint32_t D = (uint32_t)b->D;
+  const int threads = block_threads(B);
+  const int G = stream_grid(D, B, threads, 0);
+  const size_t need = (size_t)G * 2 * B;
+  if (need > kNoAllocScratchDoubles) {
+    set_error("overlap partials exceed the fixed scratch of the allocation-free entry point");
+    return QK_EINVAL;
+  }
+  double* part = nullptr;
+  qk_status st = scratch_address(b->device, &part);
+  if (st != QK_OK) return st;
+  if (dtype == QK_C128)
+    hipLaunchKernelGGL(k_overlap_partial<double>, dim3(G), dim3(threads), 0, s, (const double2*)psi0,
+                       (const double2*)psi, D, B, part);
+  else
+    hipLaunchKernelGGL(k_overlap_partial<float>, dim3(G), dim3(threads), 0, s, (const float2*)psi0,
+                       (const float2*)psi, D, B, part);
+  QK_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_overlap_final, dim3(1), dim3(kMaxBlock), 0, s, part, G, B, P, (const int*)nullptr, 0, 0);
+  QK_HIP(hipGetLastError());
   return QK_OK;
 }
 
