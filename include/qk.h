@@ -170,6 +170,10 @@ qk_status qk_ham_create(const qk_basis* b, const qk_ham_params* p, const double*
 /* Replaces the field sets (same batch count).  Enqueued on `stream`. */
 qk_status qk_ham_set_fields(qk_ham* H, const double* h_host, int32_t batch, void* stream);
 
+/* Copies the current field sets into h_host[batch][L] (host doubles); batch
+ * must equal the Hamiltonian's (QK_EINVAL otherwise).  Host only, no device work. */
+qk_status qk_ham_get_fields(const qk_ham* H, double* h_host, int32_t batch);
+
 /* D, batch and mode of a Hamiltonian (host values). */
 qk_status qk_ham_shape(const qk_ham* H, int64_t* D, int32_t* batch, int32_t* mode);
 
@@ -273,11 +277,14 @@ void qk_krylov_destroy(qk_krylov* k);
  * writes, for each kernel kind below, the summed elapsed milliseconds and the
  * number of launches since profiling was enabled (out has QK_NUM_KERNELS
  * entries).  Kernel kinds: the H-pass of a Lanczos iteration (y = H u fused
- * with the three-term update and its dot products), the update pass (new
- * vector and its norm), the projected exponential, the Krylov combination.
+ * with the three-term update and its dot products; in the two-pass split of
+ * large sectors the high-bond pass), the update pass (new vector and its
+ * norm; in the split the low-bond pass that also forms the new vector), the
+ * projected exponential, the Krylov combination, and the split's pre-pass
+ * over a step's initial vector.
  */
 enum { QK_KERNEL_LANCZOS_H = 0, QK_KERNEL_LANCZOS_UPDATE = 1, QK_KERNEL_SMALL_EXPM = 2, QK_KERNEL_COMBINE = 3,
-       QK_NUM_KERNELS = 4 };
+       QK_KERNEL_PREPASS = 4, QK_NUM_KERNELS = 5 };
 typedef struct {
   double ms_total;
   int64_t launches;

@@ -219,6 +219,14 @@ def qk_ham_set_fields(H: Ham, fields, stream=None) -> None:
            "qk_ham_set_fields")
 
 
+def qk_ham_get_fields(H: Ham) -> np.ndarray:
+    """The current field sets, shape (batch, L) (host copy)."""
+    _, Bn, _ = qk_ham_shape(H)
+    out = np.empty((Bn, H.L), dtype=np.float64)
+    _check(lib.qk_ham_get_fields(H.ptr, out.ctypes.data_as(C.POINTER(C.c_double)), Bn), "qk_ham_get_fields")
+    return out
+
+
 def qk_ham_shape(H: Ham) -> tuple[int, int, int]:
     D, Bn, mode = C.c_int64(), C.c_int32(), C.c_int32()
     _check(lib.qk_ham_shape(H.ptr, C.byref(D), C.byref(Bn), C.byref(mode)), "qk_ham_shape")
@@ -297,7 +305,7 @@ def qk_krylov_coefficients(k: Krylov, item: int = 0):
     return a[: mu.value], b[: mu.value], mu.value
 
 
-KERNEL_KINDS = ("lanczos_h", "lanczos_update", "small_expm", "combine")
+KERNEL_KINDS = ("lanczos_h", "lanczos_update", "small_expm", "combine", "prepass")
 
 
 def qk_krylov_profile(k: Krylov, enable: bool = True) -> None:

@@ -66,6 +66,7 @@ SIGNATURES = {
     "qk_basis_destroy": (None, [vp]),
     "qk_ham_create": (i32, [vp, P(HamParams), P(f64), i32, vp, P(vp)]),
     "qk_ham_set_fields": (i32, [vp, P(f64), i32, vp]),
+    "qk_ham_get_fields": (i32, [vp, P(f64), i32]),
     "qk_ham_shape": (i32, [vp, P(i64), P(i32), P(i32)]),
     "qk_ham_apply": (i32, [vp, vp, vp, i32, vp]),
     "qk_ham_destroy": (None, [vp]),

@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libqkrylov.so")
-SOURCES = ["qk_kernels.hip", "qk_blocked.hip", "qk_batch.hip", "qk_grad.hip", "qk_abi.hip"]
+SOURCES = ["qk_kernels.hip", "qk_blocked.hip", "qk_split.hip", "qk_batch.hip", "qk_grad.hip", "qk_abi.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

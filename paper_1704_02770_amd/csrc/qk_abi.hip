@@ -82,6 +82,13 @@ static bool ranges_overlap(const void* a, size_t na, const void* b, size_t nb) {
 
 int krylov_grid(uint64_t D, int B);
 
+// psi (n bytes) intersects the workspace's own vectors (the basis slots, z)
+static bool workspace_overlap(const qk_krylov* k, const void* psi, size_t n) {
+  const size_t slot = elem_bytes(k->dtype) * (size_t)k->ustride;
+  if (ranges_overlap(psi, n, k->d_U, slot * (size_t)k->m)) return true;
+  return k->d_Z && ranges_overlap(psi, n, k->d_Z, slot);
+}
+
 }  // namespace qk
 
 using namespace qk;
@@ -286,6 +293,11 @@ QK_API qk_status qk_ham_create(const qk_basis* b, const qk_ham_params* p, const 
       return st;
     }
   }
+  st = split_build(H, s);
+  if (st != QK_OK) {
+    qk_ham_destroy(H);
+    return st;
+  }
   // complete on return, like the basis (the CSR fill is still in flight here)
   e = hipStreamSynchronize(s);
   if (e != hipSuccess) {
@@ -314,7 +326,17 @@ QK_API qk_status qk_ham_set_fields(qk_ham* H, const double* h_host, int32_t batc
     st = launch_blocked_fields(H, s);
     if (st != QK_OK) return st;
   }
+  st = split_fields(H, s);
+  if (st != QK_OK) return st;
   if (H->p.mode == QK_CSR) return launch_csr_diag(H, s);
+  return QK_OK;
+}
+
+QK_API qk_status qk_ham_get_fields(const qk_ham* H, double* h_host, int32_t batch) {
+  g_err.clear();
+  if (!H || !h_host) return inval("NULL pointer");
+  if (batch != H->batch) return inval("batch differs from the Hamiltonian's");
+  std::copy(H->h_host.begin(), H->h_host.end(), h_host);
   return QK_OK;
 }
 
@@ -349,6 +371,7 @@ QK_API void qk_ham_destroy(qk_ham* H) {
   dev_free(H->al, H->d_lo_state);
   dev_free(H->al, H->d_lo_rank);
   dev_free(H->al, H->d_blk);
+  split_free(H);
   delete H;
 }
 
@@ -378,7 +401,11 @@ qk_status qk::krylov_create(const qk_ham* H, int32_t m, int32_t dtype, int32_t r
   k->D = H->basis->D;
   k->device = H->device;
   k->grid = krylov_grid((uint64_t)k->D, k->batch);
-  const size_t vec = elem_bytes(dtype) * (size_t)k->D * k->batch;
+  // the two-pass split iteration (built with the Hamiltonian when QK_SPLIT=1)
+  // keeps its vectors in the padded layout of the split
+  const bool use_split = split_usable(H) && k->batch == 1 && reorth == 0;
+  k->ustride = use_split ? split_padded_len(H, dtype) : (uint64_t)k->D * k->batch;
+  const size_t vec = elem_bytes(dtype) * (size_t)k->ustride;
   k->al = al;
   hipError_t e = dev_alloc(k->al, &k->d_U, vec * (size_t)m);
   if (e == hipSuccess)
@@ -393,6 +420,10 @@ qk_status qk::krylov_create(const qk_ham* H, int32_t m, int32_t dtype, int32_t r
     const size_t chunks = (size_t)(m + kReorthChunk - 1) / kReorthChunk;
     e = dev_alloc(k->al, (void**)&k->d_rpart, sizeof(double) * chunks * kReorthGrid * 2 * kReorthChunk * k->batch);
     if (e == hipSuccess) e = dev_alloc(k->al, (void**)&k->d_rcoef, sizeof(double) * (size_t)m * 2 * k->batch);
+  }
+  if (e == hipSuccess && use_split) {
+    e = dev_alloc(k->al, &k->d_Z, vec);
+    if (e == hipSuccess) e = dev_alloc(k->al, (void**)&k->d_sp, sizeof(double) * 6 * (size_t)kMaxPartialBlocks);
   }
   if (e != hipSuccess) {
     st = hip_fail(e, "qk_krylov_create allocation");
@@ -411,7 +442,7 @@ QK_API qk_status qk_krylov_expm_step(qk_krylov* k, void* psi, double dt, void* s
   qk_status st = check_device(k->device);
   if (st != QK_OK) return st;
   const size_t vec = elem_bytes(k->dtype) * (size_t)k->D * k->batch;
-  if (ranges_overlap(psi, vec, k->d_U, vec * (size_t)k->m)) return inval("psi overlaps the Krylov workspace");
+  if (workspace_overlap(k, psi, vec)) return inval("psi overlaps the Krylov workspace");
   hipStream_t s = (hipStream_t)stream;
   st = launch_krylov_step(k, psi, dt, s);
   if (st != QK_OK || !info) return st;
@@ -448,7 +479,7 @@ QK_API qk_status qk_krylov_evolve(qk_krylov* k, void* psi, double t, const qk_ad
   qk_status st = check_device(k->device);
   if (st != QK_OK) return st;
   const size_t vec = elem_bytes(k->dtype) * (size_t)k->D * k->batch;
-  if (ranges_overlap(psi, vec, k->d_U, vec * (size_t)k->m)) return inval("psi overlaps the Krylov workspace");
+  if (workspace_overlap(k, psi, vec)) return inval("psi overlaps the Krylov workspace");
   hipStream_t s = (hipStream_t)stream;
   const int B = k->batch;
   const KState ks = make_kstate(k);
@@ -571,6 +602,8 @@ QK_API void qk_krylov_destroy(qk_krylov* k) {
   dev_free(k->al, k->d_coef);
   dev_free(k->al, k->d_int);
   dev_free(k->al, k->d_ptot);
+  dev_free(k->al, k->d_Z);
+  dev_free(k->al, k->d_sp);
   delete k;
 }
 
@@ -617,7 +650,7 @@ QK_API qk_status qk_batch_create(qk_krylov* const* ks, void* const* psi, const i
     for (int j = 0; j < n; ++j) {
       if (j != i && ks[j] == ks[i]) return inval("a workspace appears twice");
       const size_t vj = elem_bytes(ks[j]->dtype) * (size_t)ks[j]->D * ks[j]->batch;
-      if (ranges_overlap(psi[i], vec, ks[j]->d_U, vj * (size_t)ks[j]->m)) return inval("psi overlaps a workspace");
+      if (workspace_overlap(ks[j], psi[i], vec)) return inval("psi overlaps a workspace");
       if (j != i && ranges_overlap(psi[i], vec, psi[j], vj)) return inval("state vectors overlap");
     }
   }

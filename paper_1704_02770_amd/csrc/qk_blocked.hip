@@ -29,24 +29,9 @@
 #include <cstdlib>
 #include <type_traits>
 
-#include "qk_device.h"
+#include "qk_blocked.h"
 
 namespace qk {
-
-constexpr int kMaxHi = 24;   // row shifts per block entry (high bonds <= 21, zero-padded to a multiple of 4)
-
-// One block of the sorted basis.  Everything the rows of the block share is
-// precomputed here and read with scalar loads.
-struct BlkEntry {
-  uint32_t a;               // high bits
-  uint32_t off;             // first row
-  uint32_t offw;            // first row of the ring-partner block (high bits with the top bit flipped)
-  uint32_t nact;            // number of active high bonds (their two bits differ)
-  double dconst;            // block part of the diagonal (high fields, high zz bonds, constants)
-  int32_t delta[kMaxHi];    // row shift of each active high bond, then zeros
-  uint32_t pad[2];
-};
-static_assert(sizeof(BlkEntry) == 128, "block entry is two scalar cache lines");
 
 struct BlkArgs {
   int L, N, pbc, llo, lhi, maxlen;
@@ -128,6 +113,15 @@ __global__ void k_block_consts(int nblk, int llo, int lhi, double zz0, double hh
   for (int t = 0; t < lhi; ++t)
     if ((a >> t) & 1u) f += fields[llo + t];
   blk[i].dconst = zz0 - hhalf + f - 0.5 * jz * (double)blk[i].nact;
+}
+
+qk_status launch_block_consts(BlkEntry* blk, int nblk, int llo, int lhi, double zz0, double hhalf, double jz,
+                              const double* fields, hipStream_t s) {
+  if (nblk <= 0) return QK_OK;
+  hipLaunchKernelGGL(k_block_consts, dim3((nblk + 255) / 256), dim3(256), 0, s, nblk, llo, lhi, zz0, hhalf, jz, fields,
+                     blk);
+  QK_HIP(hipGetLastError());
+  return QK_OK;
 }
 
 // --------------------------------------------------------- blocked rows

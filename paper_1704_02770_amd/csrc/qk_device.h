@@ -184,6 +184,12 @@ __device__ __forceinline__ typename Cx<T>::V h_row(uint32_t r, int b, const Mode
 struct TileWalk {
   uint32_t t, t_end, step;
   __device__ TileWalk(uint32_t ntiles) {
+    if (gridDim.x % kNumXcd) {   // a grid that does not split evenly over the XCDs: plain grid stride
+      t = blockIdx.x;
+      t_end = ntiles;
+      step = gridDim.x;
+      return;
+    }
     const uint32_t x = blockIdx.x % kNumXcd, k = blockIdx.x / kNumXcd, per = gridDim.x / kNumXcd;
     const uint32_t t0 = (uint32_t)(((uint64_t)ntiles * x) / kNumXcd);
     t_end = (uint32_t)(((uint64_t)ntiles * (x + 1)) / kNumXcd);
@@ -366,5 +372,20 @@ __device__ __forceinline__ void lanczos_h_scalars(int B, const KState& st, const
 qk_status launch_blocked_lanczos_h(const qk_ham* H, int dtype, const void* uj, const void* ujm1, void* w,
                                    const KState& st, const LanczosArgs& la, const double* partB, int Gp,
                                    double* partA, int* grid_out, int wgs_per_cu, hipStream_t s);
+
+// Two-pass split iteration (qk_split.hip): the pre-pass partials |x|^2 and
+// Re<x, H_lo x> of a step's initial vector, the high pass
+// z = sigma_j H_hi u_j - beta_{j-1} sigma_{j-1} u_{j-1}, and the low pass
+// u_{j+1} = c (z + s H_lo u_j - d u_j) with the partials of the next iteration.
+qk_status launch_split_form(const qk_ham* H, int dtype, const void* x, double* partB, double* partQ, int* grid,
+                            hipStream_t s);
+qk_status launch_split_hi(const qk_ham* H, int dtype, const void* uj, const void* ujm1, void* z, const KState& st,
+                          const LanczosArgs& la, const double* partB, int GB, double* partA, int* grid, int wgs,
+                          hipStream_t s);
+qk_status launch_split_lo(const qk_ham* H, int dtype, const void* uj, const void* z, void* out, const KState& st,
+                          const LanczosArgs& la, const double* partA, int GA, const double* partBin,
+                          const double* partQin, int GB, double* partBout, double* partQout, int store, int* grid,
+                          hipStream_t s);
+qk_status launch_split_combine(const qk_ham* H, int dtype, void* psi, const void* U, const KState& st, hipStream_t s);
 
 }  // namespace qk

@@ -126,9 +126,13 @@ constexpr int kGradQ = 2 * (QK_MAX_L + 1);
 
 template <typename S>
 __global__ void __launch_bounds__(256)
-k_grad_contract(const S* __restrict__ states, uint32_t D, int L, const double2* __restrict__ psi_k,
+k_grad_contract(const S* __restrict__ states, uint64_t niter, int L, const double2* __restrict__ psi_k,
                 const double2* __restrict__ Uf, const double2* __restrict__ lam, const double2* __restrict__ Ub,
+                size_t stride, const uint32_t* __restrict__ line_r0, const uint8_t* __restrict__ line_n, int pe,
                 KState fw, KState bw, const double* __restrict__ Ct, double* __restrict__ part) {
+  // niter positions of the workspace vectors (stride elements each): rows of
+  // the sorted basis, or, with line tables, elements of the padded layout
+  // whose row comes from their line's entry (unused padding is skipped)
   __shared__ double2 C[kGradMaxM * kGradMaxM];
   __shared__ double2 sbuf[256];
   __shared__ S sst[256];
@@ -137,20 +141,27 @@ k_grad_contract(const S* __restrict__ states, uint32_t D, int L, const double2* 
   __syncthreads();
   const int muf = fw.mused[0] < kGradMaxM ? fw.mused[0] : kGradMaxM;
   const int mub = bw.mused[0] < kGradMaxM ? bw.mused[0] : kGradMaxM;
-  const size_t stride = D;
   const int site = tid >> 1, comp = tid & 1;
   double acc = 0.0;
-  for (uint32_t base = blockIdx.x * 256u; base < D; base += gridDim.x * 256u) {
-    const uint32_t r = base + tid;
+  for (uint64_t base = (uint64_t)blockIdx.x * 256u; base < niter; base += (uint64_t)gridDim.x * 256u) {
+    const uint64_t p = base + tid;
+    bool valid = p < niter;
+    size_t r = (size_t)p;
+    if (valid && line_r0) {
+      const uint64_t ln = p / (uint64_t)pe;
+      const uint32_t e = (uint32_t)(p - ln * (uint64_t)pe);
+      valid = e < line_n[ln];
+      r = (size_t)line_r0[ln] + e;
+    }
     double sr = 0.0, si = 0.0;
     S stt = 0;
-    if (r < D) {
+    if (valid) {
       double2 u[kGradMaxM];
 #pragma unroll
       for (int d = 0; d < kGradMaxM; ++d)
-        u[d] = (d < muf) ? (d == 0 ? psi_k[r] : Uf[(size_t)(d - 1) * stride + r]) : make_double2(0.0, 0.0);
+        u[d] = (d < muf) ? (d == 0 ? psi_k[r] : Uf[(size_t)(d - 1) * stride + p]) : make_double2(0.0, 0.0);
       for (int c = 0; c < mub; ++c) {
-        const double2 w = (c == 0) ? lam[r] : Ub[(size_t)(c - 1) * stride + r];
+        const double2 w = (c == 0) ? lam[r] : Ub[(size_t)(c - 1) * stride + p];
         double tr = 0.0, ti = 0.0;
 #pragma unroll
         for (int d = 0; d < kGradMaxM; ++d) {
@@ -234,6 +245,17 @@ qk_status grad_return_prob(qk_krylov* k, int64_t r0, double T, int n_steps, int 
   if (e == hipSuccess) e = dev_alloc(k->al, (void**)&dA, sizeof(double) * 2 * L);
   if (e == hipSuccess) e = hipMemsetAsync(dA, 0, sizeof(double) * 2 * L, s);
   const KState fw = make_kstate(k), bw = make_kstate(kb);
+  // the workspaces' vectors in the padded layout of the two-pass split: the
+  // contraction walks that layout and finds each element's row in its line
+  const uint32_t* lr0 = nullptr;
+  const uint8_t* lnn = nullptr;
+  int pe = 1;
+  uint64_t niter = D;
+  if (st == QK_OK && (k->d_Z != nullptr) != (kb->d_Z != nullptr)) {
+    set_error("forward and backward workspaces differ in layout");
+    st = QK_EUNSUPPORTED;
+  }
+  if (st == QK_OK && k->d_Z) st = split_line_tables(H, QK_C128, &lr0, &lnn, &niter, &pe);
   const GaussRule gr = gauss_legendre();
   auto chk = [&](const char* what) {
     if (st == QK_OK && e == hipSuccess) e = hipGetLastError();
@@ -295,12 +317,12 @@ qk_status grad_return_prob(qk_krylov* k, int64_t r0, double T, int n_steps, int 
     if (st != QK_OK) break;
     if (H->basis->wide)
       hipLaunchKernelGGL(k_grad_contract<uint64_t>, dim3(G), dim3(256), 0, s, (const uint64_t*)H->basis->d_states,
-                         D, L, (const double2*)state_at(t), (const double2*)k->d_U, (const double2*)lamp,
-                         (const double2*)kb->d_U, fw, bw, Ct, part);
+                         niter, L, (const double2*)state_at(t), (const double2*)k->d_U, (const double2*)lamp,
+                         (const double2*)kb->d_U, (size_t)k->ustride, lr0, lnn, pe, fw, bw, Ct, part);
     else
       hipLaunchKernelGGL(k_grad_contract<uint32_t>, dim3(G), dim3(256), 0, s, (const uint32_t*)H->basis->d_states,
-                         D, L, (const double2*)state_at(t), (const double2*)k->d_U, (const double2*)lamp,
-                         (const double2*)kb->d_U, fw, bw, Ct, part);
+                         niter, L, (const double2*)state_at(t), (const double2*)k->d_U, (const double2*)lamp,
+                         (const double2*)kb->d_U, (size_t)k->ustride, lr0, lnn, pe, fw, bw, Ct, part);
     chk("k_grad_contract");
     if (st != QK_OK) break;
     hipLaunchKernelGGL(k_grad_accum, dim3(1), dim3(256), 0, s, part, G, L, dA);

@@ -104,6 +104,8 @@ struct qk_ham {
   uint16_t* d_lo_rank = nullptr;  // [2^llo]
   void* d_blk = nullptr;          // [nblk] block entries (high bits, first row, ring-partner first row)
   int nblk = 0;
+  // two-pass high/low split (one field set, 18 <= L <= 32): tables of qk_split.hip
+  void* split = nullptr;
 };
 
 struct qk_krylov {
@@ -117,7 +119,8 @@ struct qk_krylov {
   int blocks_per_cu = 0;          // blocks per CU of the row-streaming kernels
   int blocked_wgs = 0;            // work-groups per CU of the blocked H-pass
   int grid = 0;                   // blocks of the streaming kernels (multiple of 8)
-  void* d_U = nullptr;            // m slots of [D][batch] vectors: u_1..u_m
+  void* d_U = nullptr;            // m slots of ustride elements: u_1..u_m
+  uint64_t ustride = 0;           // elements per slot: D * batch, or the padded length of the split layout
   double* d_partA = nullptr;      // [grid][2][batch] partial sums of the H-pass
   double* d_partB = nullptr;      // [grid][1][batch] partial sums of the update pass
   double* d_ptot = nullptr;       // [kQA + 1][batch] totals of both (batches of 8 or more)
@@ -125,13 +128,16 @@ struct qk_krylov {
   int32_t* d_int = nullptr;       // [2][batch]: m_used, status
   double* d_rpart = nullptr;      // full reorthogonalisation: [chunks][kReorthGrid][2 kReorthChunk][batch] partial dots
   double* d_rcoef = nullptr;      // full reorthogonalisation: [m][2][batch] projection coefficients
+  // two-pass split iteration (one field set, no reorthogonalisation)
+  void* d_Z = nullptr;            // [ustride] high-pass result z of the current iteration (padded layout)
+  double* d_sp = nullptr;         // partial sums: high pass [kMaxPartialBlocks][2], low pass 2 x ([kMaxPartialBlocks] norms, [kMaxPartialBlocks] forms)
   // event timing (qk_krylov_profile)
   bool profiling = false;
   struct Pending { int kind; hipEvent_t start, end; };
   std::vector<Pending> pending;
   std::vector<hipEvent_t> spare;
-  double ms_total[QK_NUM_KERNELS] = {0, 0, 0, 0};
-  int64_t launches[QK_NUM_KERNELS] = {0, 0, 0, 0};
+  double ms_total[QK_NUM_KERNELS] = {};
+  int64_t launches[QK_NUM_KERNELS] = {};
 };
 
 namespace qk {
@@ -172,6 +178,16 @@ qk_status launch_blocked_build(qk_ham* H, hipStream_t s);
 qk_status launch_blocked_apply(const qk_ham* H, const void* x, void* y, int dtype, hipStream_t s);
 qk_status launch_blocked_fields(qk_ham* H, hipStream_t s);
 bool blocked_usable(const qk_ham* H, int dtype);
+// two-pass high/low split (qk_split.hip)
+qk_status split_build(qk_ham* H, hipStream_t s);   // no-op unless one field set, matrix-free, 18 <= L <= 32
+qk_status split_fields(qk_ham* H, hipStream_t s);
+void split_free(qk_ham* H);
+bool split_usable(const qk_ham* H);
+int split_llo(int L);
+uint64_t split_padded_len(const qk_ham* H, int dtype);   // elements of one workspace vector (padded layout)
+qk_status split_line_tables(const qk_ham* H, int dtype, const uint32_t** r0, const uint8_t** n, uint64_t* dpad,
+                            int* pe);
+qk_status launch_split_apply(const qk_ham* H, const void* x, void* y, int dtype, hipStream_t s);
 // qk_krylov_create with the device memory of the workspace from `al`
 qk_status krylov_create(const qk_ham* H, int32_t m, int32_t dtype, int32_t reorth, const qk_allocator& al,
                         qk_krylov** out);

@@ -826,6 +826,7 @@ static void launch_apply_rows(const qk_ham* H, const void* x, void* y, hipStream
 }
 
 qk_status launch_ham_apply(const qk_ham* H, const void* x, void* y, int dtype, hipStream_t s) {
+  if (split_usable(H) && H->batch == 1) return launch_split_apply(H, x, y, dtype, s);
   if (blocked_usable(H, dtype)) return launch_blocked_apply(H, x, y, dtype, s);
   const bool wide = H->basis->wide;
   if (dtype == QK_C128) {
@@ -840,18 +841,21 @@ qk_status launch_ham_apply(const qk_ham* H, const void* x, void* y, int dtype, h
 }
 
 // H-pass of Lanczos iteration j through the row kernels (CSR or matrix-free rows).
+// G: launch grid (a multiple of kNumXcd; it also sets the rows of partA the
+// launch writes); Gp: rows of partial sums in partB (1 when they were
+// totalled beforehand).
 template <typename T, typename S>
 static void launch_lanczos_rows(const qk_ham* H, const typename Cx<T>::V* uj, const typename Cx<T>::V* ujm1,
                                 typename Cx<T>::V* w, const KState& st, const LanczosArgs& la, const double* partB,
-                                int G, int threads, double* partA, hipStream_t s) {
+                                int Gp, int G, int threads, double* partA, hipStream_t s) {
   const ModelArgs a = model_args(H);
   const HamView<S> hv = ham_view<S>(H);
   if (H->p.mode == QK_CSR)
     hipLaunchKernelGGL((k_lanczos_A<T, true, S>), dim3(G), dim3(threads), 0, s, uj, ujm1, w, a, hv,
-                       H->basis->d_binom, H->d_fields, st, la, partB, G, partA);
+                       H->basis->d_binom, H->d_fields, st, la, partB, Gp, partA);
   else
     hipLaunchKernelGGL((k_lanczos_A<T, false, S>), dim3(G), dim3(threads), 0, s, uj, ujm1, w, a, hv,
-                       H->basis->d_binom, H->d_fields, st, la, partB, G, partA);
+                       H->basis->d_binom, H->d_fields, st, la, partB, Gp, partA);
 }
 
 struct AdaptiveStep {
@@ -881,7 +885,7 @@ static qk_status krylov_step_t(qk_krylov* k, void* psi_v, double dt, hipStream_t
   const qk_ham* H = k->H;
   const int B = H->batch, threads = krylov_threads(k), G = k->grid, m = k->m;
   const uint32_t D = (uint32_t)H->basis->D;
-  const size_t stride = (size_t)D * B;
+  const size_t stride = (size_t)k->ustride;   // D * B, or the padded length of the split layout
   V* psi = (V*)psi_v;
   V* U = (V*)k->d_U;
   const KState st = make_kstate(k);
@@ -902,8 +906,40 @@ static qk_status krylov_step_t(qk_krylov* k, void* psi_v, double dt, hipStream_t
   double* totA = k->d_ptot;
   double* totB = k->d_ptot + (size_t)kQA * B;
   const double* pB = pre ? totB : k->d_partB;
-  const int GB = pre ? 1 : G;
-  for (int j = 0; j < m; ++j) {
+  int GB = pre ? 1 : G;
+  if (k->d_Z) {
+    // two-pass split: the pre-pass of the initial vector, then per iteration
+    // the high pass (z) and the low pass (u_{j+1}); the low pass's partials
+    // alternate between two buffers (one is read while the other is written)
+    double* spA = k->d_sp;
+    double* spB[2] = {k->d_sp + 2 * (size_t)kMaxPartialBlocks, k->d_sp + 3 * (size_t)kMaxPartialBlocks};
+    double* spQ[2] = {k->d_sp + 4 * (size_t)kMaxPartialBlocks, k->d_sp + 5 * (size_t)kMaxPartialBlocks};
+    int Glo = 0, Ghi = 0;
+    QK_MARK(QK_KERNEL_PREPASS, true);
+    {
+      qk_status ps = launch_split_form(H, k->dtype, psi, spB[0], spQ[0], &Glo, s);
+      if (ps != QK_OK) return ps;
+    }
+    QK_MARK(QK_KERNEL_PREPASS, false);
+    for (int j = 0; j < m; ++j) {
+      LanczosArgs la{j, m, rtol, 0};
+      const V* uj = j == 0 ? psi : U + (size_t)(j - 1) * stride;
+      const V* ujm1 = j == 0 ? nullptr : (j == 1 ? psi : U + (size_t)(j - 2) * stride);
+      QK_MARK(QK_KERNEL_LANCZOS_H, true);
+      qk_status ps = launch_split_hi(H, k->dtype, uj, ujm1, k->d_Z, st, la, spB[j & 1], Glo, spA, &Ghi,
+                                     k->blocked_wgs, s);
+      if (ps != QK_OK) return ps;
+      QK_MARK(QK_KERNEL_LANCZOS_H, false);
+      QK_MARK(QK_KERNEL_LANCZOS_UPDATE, true);
+      ps = launch_split_lo(H, k->dtype, uj, k->d_Z, U + (size_t)j * stride, st, la, spA, Ghi, spB[j & 1], spQ[j & 1],
+                           Glo, spB[(j + 1) & 1], spQ[(j + 1) & 1], j + 1 < m ? 1 : 0, &Glo, s);
+      if (ps != QK_OK) return ps;
+      QK_MARK(QK_KERNEL_LANCZOS_UPDATE, false);
+    }
+    pB = spB[m & 1];
+    GB = Glo;
+  }
+  for (int j = 0; j < (k->d_Z ? 0 : m); ++j) {
     LanczosArgs la{j, m, rtol, k->reorth == 1 ? 1 : 0};
     const V* uj = j == 0 ? psi : U + (size_t)(j - 1) * stride;
     const V* ujm1 = j == 0 ? nullptr : (j == 1 ? psi : U + (size_t)(j - 2) * stride);
@@ -915,9 +951,9 @@ static qk_status krylov_step_t(qk_krylov* k, void* psi_v, double dt, hipStream_t
                                               k->blocked_wgs, s);
       if (bs != QK_OK) return bs;
     } else if (H->basis->wide) {
-      launch_lanczos_rows<T, uint64_t>(H, uj, ujm1, w, st, la, pB, GB, threads, k->d_partA, s);
+      launch_lanczos_rows<T, uint64_t>(H, uj, ujm1, w, st, la, pB, GB, G, threads, k->d_partA, s);
     } else {
-      launch_lanczos_rows<T, uint32_t>(H, uj, ujm1, w, st, la, pB, GB, threads, k->d_partA, s);
+      launch_lanczos_rows<T, uint32_t>(H, uj, ujm1, w, st, la, pB, GB, G, threads, k->d_partA, s);
     }
     QK_HIP(hipGetLastError());
     QK_MARK(QK_KERNEL_LANCZOS_H, false);
@@ -973,6 +1009,12 @@ static qk_status krylov_step_t(qk_krylov* k, void* psi_v, double dt, hipStream_t
   QK_HIP(hipGetLastError());
   QK_MARK(QK_KERNEL_SMALL_EXPM, false);
   QK_MARK(QK_KERNEL_COMBINE, true);
+  if (k->d_Z) {
+    qk_status cs = launch_split_combine(H, k->dtype, psi, U, st, s);
+    if (cs != QK_OK) return cs;
+    QK_MARK(QK_KERNEL_COMBINE, false);
+    return QK_OK;
+  }
   // complex64 elements go two to a 16-byte access when the vector length and
   // both base addresses allow it
   const bool pack2 = sizeof(V) == 8 && ((uint64_t)D * B) % 2 == 0 && ((uintptr_t)psi % 16) == 0 &&
