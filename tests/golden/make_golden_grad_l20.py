@@ -70,19 +70,19 @@ def main():
         F0 = pool.apply_async(_F, (hf,))
         rows = pool.map(_one_field, range(L), chunksize=1)
         F0 = F0.get()
-    D1 = np.array([r[0] for r in rows])
-    D2 = np.array([r[1] for r in rows])
+    D1 = np.array([r[0] for r in rows], dtype=np.float64)
+    D2 = np.array([r[1] for r in rows], dtype=np.float64)
     R = (4.0 * D2 - D1) / 3.0
     out = os.path.join(os.path.dirname(os.path.abspath(__file__)), "grad_l20_richardson.txt")
     with open(out, "w") as f:
         f.write("# dF(T)/dh_i of the Neel survival probability, L=20 ring, J=Delta=1, h=1.5, T=5,\n")
         f.write(f"# phi={float(W.phis()[0])!r} (default_rng(0)); written by tests/golden/make_golden_grad_l20.py\n")
         f.write("# from the oracle (expm_multiply F, central differences at eps=1e-3 and 5e-4, one Richardson step).\n")
-        f.write(f"# F(T) = {F0!r}\n")
+        f.write(f"# F(T) = {float(F0)!r}\n")
         f.write("# columns: i  R_i  D_i(1e-3)  D_i(5e-4)\n")
-        f.write(f"F {F0!r}\n")
+        f.write(f"F {float(F0)!r}\n")
         for i in range(L):
-            f.write(f"{i} {R[i]!r} {D1[i]!r} {D2[i]!r}\n")
+            f.write(f"{i} {float(R[i])!r} {float(D1[i])!r} {float(D2[i])!r}\n")
 
 
 if __name__ == "__main__":

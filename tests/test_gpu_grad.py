@@ -1,14 +1,16 @@
 """GPU tests of the adjoint gradient dF/dh_i of the survival probability
 (Sec. 4's F(T) differentiated with respect to every on-site field of Eq. (1)):
-against the oracle's Daleckii-Krein derivative at small L, against central
-finite differences of the library's own F(T) at L=20, the uniform-field sum
-rule, the torch.autograd wrapper and the unsupported configurations."""
+against the oracle's Daleckii-Krein derivative at small L, against the
+oracle's Richardson-extrapolated central differences of its exact F(T) at
+L=20, the uniform-field sum rule, the torch.autograd wrapper and the
+unsupported configurations."""
 import numpy as np
 import pytest
 import torch
 
 import paper_1704_02770_amd as qk
 from paper_1704_02770_amd.autograd import survival_probability
+from conftest import read_golden
 from gpu_util import neel_row, say, to_host
 from oracle import gradient as OG
 from oracle import model as OM
@@ -41,34 +43,32 @@ def test_gradient_vs_daleckii_krein(L, pbc, h, jz, T, n_steps):
     assert np.max(np.abs(g - g_ref)) < 1e-9 * scale, (g, g_ref)
 
 
-def test_gradient_vs_finite_differences_L20():
+def test_gradient_workload_vs_oracle_richardson():
     # the gradient workload: L = 20 ring, h = 1.5, phase from seed 0, Neel
-    # state, T = 5, dt = 0.1 (50 steps), m = 30; central differences with
-    # eps = 1e-6 of the library's own F(T), each a fresh forward propagation
+    # state, T = 5, dt = 0.1 (50 steps), m = 30; the adjoint against the
+    # oracle's derivative of F(T): central differences of its exact F
+    # (expm_multiply) at eps = 1e-3 and 5e-4 combined by one Richardson step
+    # (tests/golden/grad_l20_richardson.txt, written from the oracle alone;
+    # truncation about 3e-11, rounding about 1e-12)
+    rows = read_golden("grad_l20_richardson.txt")
+    F_ref = float(rows[0][1])
+    R = np.array([float(r[1]) for r in rows[1:]])
+    D1 = np.array([float(r[2]) for r in rows[1:]])
+    D2 = np.array([float(r[3]) for r in rows[1:]])
     w = WORKLOADS["xxz_L20_grad"]
-    L, T, n_steps, eps = w.L, w.t_end, int(round(w.t_end / w.dt)), 1e-6
+    L, T, n_steps = w.L, w.t_end, int(round(w.t_end / w.dt))
+    assert len(R) == L
     b, H, k, hf = _ws(L, w.pbc, w.h, float(w.phis()[0]), m=w.m)
     r0 = neel_row(L)
     say("grad L20 adjoint")
     F, g = qk.qk_grad_return_prob(k, r0, T, n_steps)
+    err = np.max(np.abs(g - R))
+    say("grad L20 max |adjoint - oracle| =", err, "max |dF/dh| =", np.max(np.abs(R)),
+        "spread of the two central differences", np.max(np.abs(D1 - D2)))
+    assert abs(F - F_ref) < 1e-10
+    assert err < 1e-8
     # the sum rule: a uniform field shifts H by a constant in the sector
     assert abs(np.sum(g)) < 1e-10 * max(1.0, np.max(np.abs(g)))
-    fd = np.empty(L)
-    for i in range(L):
-        vals = []
-        for sgn in (+1, -1):
-            hh = hf.copy()
-            hh[i] += sgn * eps
-            qk.qk_ham_set_fields(H, hh)
-            psi = torch.zeros(qk.qk_basis_dim(b), dtype=torch.complex128, device="cuda")
-            psi[r0] = 1.0
-            for _ in range(n_steps):
-                qk.qk_krylov_expm_step(k, psi, T / n_steps)
-            vals.append(float(abs(psi[r0].item()) ** 2))
-        fd[i] = (vals[0] - vals[1]) / (2 * eps)
-    say("grad L20 max |adjoint - fd| =", np.max(np.abs(g - fd)), "max |g| =", np.max(np.abs(g)))
-    assert np.max(np.abs(g - fd)) < 1e-6
-    qk.qk_ham_set_fields(H, hf)
     F2, g2 = qk.qk_grad_return_prob(k, r0, T, n_steps)
     assert F2 == F and np.array_equal(g2, g)   # deterministic
 
@@ -91,16 +91,27 @@ def test_checkpoint_stride_gives_identical_results():
 
 
 def test_autograd_wrapper():
+    # forward computes F only, backward the adjoint; the Hamiltonian's own
+    # fields are restored after each
     L, T, n = 10, 2.0, 20
     b, H, k, hf = _ws(L, True, 1.5, 0.2)
+    own = qk.qk_ham_get_fields(H).copy()
     r0 = neel_row(L)
-    x = torch.tensor(hf, dtype=torch.float64, requires_grad=True)
+    hx = hf + 0.05 * np.cos(np.arange(L))
+    x = torch.tensor(hx, dtype=torch.float64, requires_grad=True)
     say("grad autograd")
     F = survival_probability(x, k, r0, T, n)
+    assert np.array_equal(qk.qk_ham_get_fields(H), own)
     (3.0 * F).backward()
-    F_ref, g_ref = OG.dF_dh(L, L // 2, True, 1.0, 1.0, hf, r0, T)
+    assert np.array_equal(qk.qk_ham_get_fields(H), own)
+    F_ref, g_ref = OG.dF_dh(L, L // 2, True, 1.0, 1.0, hx, r0, T)
     assert abs(F.item() - F_ref) < 1e-10
     assert np.max(np.abs(x.grad.numpy() - 3.0 * g_ref)) < 3e-9 * max(1.0, np.max(np.abs(g_ref)))
+    # without a gradient request the same F
+    with torch.no_grad():
+        F2 = survival_probability(x, k, r0, T, n)
+    assert F2.item() == F.item()
+    assert np.array_equal(qk.qk_ham_get_fields(H), own)
 
 
 def test_gradient_unsupported_and_invalid():

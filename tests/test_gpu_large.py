@@ -91,7 +91,7 @@ def test_l24_free_fermions_all_times(pbc):
         assert abs(torch.linalg.vector_norm(psi).item() - 1.0) < 1e-11
 
 
-@pytest.mark.parametrize("L,m,dt,t_end,h", [(28, 30, 0.1, 2.0, 1.5), (30, 20, 0.05, 0.5, 0.0), (30, 20, 0.05, 0.5, 2.0)])
+@pytest.mark.parametrize("L,m,dt,t_end,h", [(28, 30, 0.1, 2.0, 1.5), (30, 20, 0.05, 0.5, 0.0)])
 def test_large_free_fermions(L, m, dt, t_end, h):
     b = qk.qk_basis_build(L, L // 2)
     hf = OM.fields(L, h, BETA_GOLDEN, PHI)
@@ -143,25 +143,76 @@ def test_l28_benchmark_workload_invariants():
     assert err < 1e-5
 
 
+def _evolve_adaptive(b, H, L, times, m, tol, dtype=torch.complex128):
+    """P at each output time, reached by error-controlled Krylov steps
+    (qk_krylov_evolve, tolerance per unit time) between output times."""
+    k = qk.qk_krylov_create(H, m, dtype)
+    D = qk.qk_basis_dim(b)
+    r0 = _neel_row(b, L)
+    psi = torch.zeros(D, dtype=dtype, device="cuda")
+    psi[r0] = 1.0
+    P = torch.empty(len(times), dtype=torch.float64, device="cuda")
+    t_prev, steps = 0.0, 0
+    for i, t in enumerate(times):
+        info = qk.qk_krylov_evolve(k, psi, float(t) - t_prev, tol, dt_init=0.5)
+        steps += info["steps"]
+        qk.qk_return_prob(b, psi, r0=r0, out=P[i:i + 1])
+        t_prev = float(t)
+        if i % 40 == 39:
+            say("  reached t =", t, "after", steps, "steps")
+    del k
+    return to_host(P), psi, steps
+
+
 @pytest.mark.parametrize("h", [0.0, 2.0])
-def test_l30_fp64_vs_fp32(h):
-    # the large chain with zz coupling: m = 20, dt = 0.05, Krylov basis resident
-    # in HBM (about 50 GB in complex128)
-    L = 30
+def test_l30_to_t100_fp64_vs_fp32(h):
+    # the large chain with zz coupling (L = 30 ring, D = 155,117,520, m = 20,
+    # Krylov basis resident in HBM: about 50 GB in complex128), output cadence
+    # 0.5 to t = 100 with error-controlled steps (tolerance 1e-9 per unit time,
+    # the paper's adaptive stepping): no exact reference exists at this size,
+    # so the norm and the energy <psi|H|psi> (the Neel diagonal element) are
+    # held, and complex64 storage agrees with complex128 at all 200 outputs
+    L, m, tol = 30, 20, 1e-9
     b = qk.qk_basis_build(L, L // 2)
     hf = OM.fields(L, h, BETA_GOLDEN, PHI)
     H = qk.qk_ham_create(b, 1.0, 1.0, True, hf)
-    times = 0.05 * np.arange(1, 11)
-    say("L30 fp64", h)
-    P64, psi, _ = _evolve(b, H, L, times, 20, 0.05)
-    assert abs(torch.linalg.vector_norm(psi).item() - 1.0) < 1e-12
+    times = 0.5 * np.arange(1, 201)
+    say("L30 to t=100 fp64", h)
+    P64, psi, n64 = _evolve_adaptive(b, H, L, times, m, tol)
+    say("  steps", n64)
+    assert np.all(P64 >= 0.0) and np.all(P64 <= 1.0 + 1e-12)
+    assert abs(torch.linalg.vector_norm(psi).item() - 1.0) < 1e-11
+    E0 = float(OH.diagonal(np.array([OM.neel_state(L)]), L, True, 1.0, hf)[0])
+    E = torch.vdot(psi, qk.qk_ham_apply(H, psi)).real.item()
+    say("  E =", E, "E0 =", E0)
+    assert abs(E - E0) < 1e-9 * max(1.0, abs(E0))
     del psi
     torch.cuda.empty_cache()
-    say("L30 fp32", h)
-    P32, _, _ = _evolve(b, H, L, times, 20, 0.05, torch.complex64)
+    say("L30 to t=100 fp32", h)
+    P32, psi32, n32 = _evolve_adaptive(b, H, L, times, m, tol, torch.complex64)
     err = np.max(np.abs(P32 - P64))
-    say("  complex64 vs complex128 max |dP| =", err)
+    say("  steps", n32, "complex64 vs complex128 max |dP| =", err)
     assert err < 1e-5
+    del psi32
+    torch.cuda.empty_cache()
+
+
+def test_l30_free_fermions_to_t100():
+    # zz coupling 0 on the same kernels: the determinant closed form at all
+    # 200 outputs of cadence 0.5 to t = 100 (error-controlled steps with
+    # tolerance 5e-13 per unit time: at most 1e-10 in P over the run)
+    L, m = 30, 20
+    b = qk.qk_basis_build(L, L // 2)
+    hf = OM.fields(L, 2.0, BETA_GOLDEN, PHI)
+    H = qk.qk_ham_create(b, 1.0, 0.0, True, hf)
+    times = 0.5 * np.arange(1, 201)
+    say("L30 free fermions to t=100")
+    P, psi, n = _evolve_adaptive(b, H, L, times, m, 5e-13)
+    ref = OF.survival_probability(L, L // 2, True, 1.0, hf, OM.neel_state(L), times)
+    err = np.max(np.abs(P - ref))
+    say("  steps", n, "max |dP| =", err)
+    assert err < 1e-10
+    assert abs(torch.linalg.vector_norm(psi).item() - 1.0) < 1e-11
 
 
 def test_l28_batched_form_at_full_size():
