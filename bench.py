@@ -14,7 +14,11 @@ Forms: plain complex128 (the headline `value`), complex64 storage, and a
 batch of 8 phases in complex64 ([D][8] layout); `adaptive` runs the same
 complex128 chain from the Neel state to t = 100 with error-controlled steps
 (tolerance 1e-7 per unit time), the evolution the paper times in Sec. 5, and
-reports its step count and wall time.  Also reported: standalone
+reports its step count and wall time; `mixed` times the batched workload of
+64 phases of the L = 20 ring plus single rings of L = 16, 18, 20, 22 (h = 2,
+complex64, one hipGraph replay per step); `large` times Krylov steps of the
+L = 30 ring (m = 20, dt = 0.05, complex128 and complex64).  Every rate is the
+median of --repeats timed runs of exactly --steps steps.  Also reported: standalone
 y = H x throughput (algorithmic bytes 2 s D per call), a device-copy ceiling,
 the roofline of the dominant kernel from HIP events recorded on the step's
 stream, and the CPU oracle timed on a bounded sample of the same workload.
@@ -26,6 +30,8 @@ import hashlib
 import json
 import math
 import os
+import platform
+import statistics
 import sys
 import time
 
@@ -37,7 +43,8 @@ PEAK_HBM_GBS = 8000.0          # MI355X HBM3E, published
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_lanczos_h_L28.json")
 # sources of the blocked H-pass kernel; stored counter bytes are used only
 # while these files are unchanged
-KERNEL_SRCS = [os.path.join(ROOT, "paper_1704_02770_amd", "csrc", f) for f in ("qk_blocked.hip", "qk_device.h")]
+KERNEL_SRCS = [os.path.join(ROOT, "paper_1704_02770_amd", "csrc", f)
+               for f in ("qk_blocked.hip", "qk_blocked.h", "qk_device.h")]
 
 
 def log(*a):
@@ -54,7 +61,10 @@ def parse():
     ap.add_argument("--dt", type=float, default=0.1)
     ap.add_argument("--h", type=float, default=1.5)
     ap.add_argument("--batch", type=int, default=8)
-    ap.add_argument("--forms", default="fp64,fp32,batched,adaptive")
+    ap.add_argument("--forms", default="fp64,fp32,batched,adaptive,mixed,large")
+    ap.add_argument("--repeats", type=int, default=5, help="timed runs of --steps steps per form (median reported)")
+    ap.add_argument("--mixed-steps", type=int, default=50, help="steps of the mixed batched workload per timed run")
+    ap.add_argument("--large-steps", type=int, default=5, help="steps of the L = 30 form per timed run")
     ap.add_argument("--adaptive-t", type=float, default=100.0)
     ap.add_argument("--adaptive-tol", type=float, default=1e-7)
     ap.add_argument("--hv-reps", type=int, default=100)
@@ -66,8 +76,8 @@ def parse():
                     help="time the CPU oracle at several sizes on this host (no GPU) and print one JSON line")
     args = ap.parse_args()
     problems = []
-    if args.steps < 1 or args.warmup < 0 or args.hv_reps < 1:
-        problems.append("--steps and --hv-reps must be >= 1 and --warmup >= 0")
+    if args.steps < 1 or args.warmup < 0 or args.hv_reps < 1 or args.repeats < 1:
+        problems.append("--steps, --repeats and --hv-reps must be >= 1 and --warmup >= 0")
     if args.L < 4 or args.L > 32 or args.L % 2:
         problems.append("--L must be even, 4 <= L <= 32 (the Sz = 0 sector)")
     if args.m < 1 or args.m > 64 or not math.isfinite(args.dt) or args.dt <= 0:
@@ -87,11 +97,14 @@ def source_sha():
     return h.hexdigest()
 
 
-def run_form(qk, torch, b, fields, m, dt, dtype, steps, warmup, r0):
-    """Times `steps` Krylov steps (+ survival probability) after `warmup`."""
+def run_form(qk, torch, b, fields, m, dt, dtype, steps, warmup, r0, repeats, pbc=True):
+    """Times `steps` Krylov steps (+ survival probability) after `warmup`:
+    one run with HIP events around every kernel (per-kernel times), then
+    `repeats` runs without events, each bracketed by device synchronisation;
+    the rate is the median of the latter."""
     D = qk.qk_basis_dim(b)
     B = fields.shape[0]
-    H = qk.qk_ham_create(b, 1.0, 1.0, True, fields)
+    H = qk.qk_ham_create(b, 1.0, 1.0, pbc, fields)
     k = qk.qk_krylov_create(H, m, dtype)
     psi = torch.zeros((D, B) if B > 1 else D, dtype=dtype, device="cuda")
     psi[r0] = 1.0
@@ -100,33 +113,139 @@ def run_form(qk, torch, b, fields, m, dt, dtype, steps, warmup, r0):
         qk.qk_krylov_expm_step(k, psi, dt)
         qk.qk_return_prob(b, psi, r0=r0, batch=B, out=P[s])
     torch.cuda.synchronize()
-    # timed region; HIP events bracket every kernel launch on the same stream
+    # HIP events bracket every kernel launch on the same stream
     qk.qk_krylov_profile(k, True)
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
     for s in range(steps):
         qk.qk_krylov_expm_step(k, psi, dt)
         qk.qk_return_prob(b, psi, r0=r0, batch=B, out=P[warmup + s])
     torch.cuda.synchronize()
-    t1 = time.perf_counter()
     prof = qk.qk_krylov_profile_read(k)
     qk.qk_krylov_profile(k, False)
-    # same number of steps without events, to show their cost
-    torch.cuda.synchronize()
-    t2 = time.perf_counter()
-    for s in range(steps):
-        qk.qk_krylov_expm_step(k, psi, dt)
-    torch.cuda.synchronize()
-    t3 = time.perf_counter()
+    secs = []
+    for _ in range(repeats):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for s in range(steps):
+            qk.qk_krylov_expm_step(k, psi, dt)
+            qk.qk_return_prob(b, psi, r0=r0, batch=B, out=P[warmup + s])
+        torch.cuda.synchronize()
+        secs.append(time.perf_counter() - t0)
     info = qk.qk_krylov_expm_step(k, psi, dt, info=True)
     norm = torch.linalg.vector_norm(psi.reshape(D, B).to(torch.complex128), dim=0).cpu().tolist()
-    out = dict(sec=t1 - t0, sec_no_events=t3 - t2, prof=prof, m_used=[i["m_used"] for i in info],
+    out = dict(sec=statistics.median(secs), sec_all=secs, prof=prof, m_used=[i["m_used"] for i in info],
                err_est=max(i["err_est"] for i in info), P_last=P[warmup + steps - 1].cpu().tolist(),
                norm_drift=max(abs(x - 1.0) for x in norm))
     del k, H, psi
     torch.cuda.synchronize()
     torch.cuda.empty_cache()
     return out
+
+
+def run_mixed(qk, torch, steps, warmup, repeats, m=30, dt=0.1, h=2.0):
+    """The batched workload: 64 phases of the L = 20 ring and single rings of
+    L = 16, 18, 20, 22 (h = 2, Neel state, complex64 vectors, FP64 Lanczos
+    coefficients), one hipGraph replay per step for all of them; also the
+    64-phase workspace's kernels timed alone with HIP events (eager steps)."""
+    from workloads import BETA_GOLDEN, phases
+    spec = [(20, 64, 0), (16, 1, 1), (18, 1, 2), (20, 1, 3), (22, 1, 4)]
+    hold, ks, psis, r0s = [], [], [], []
+    for L, Bn, seed in spec:
+        b = qk.qk_basis_build(L, L // 2)
+        f = qk.qk_fields_quasiperiodic(L, h, BETA_GOLDEN, phases(Bn, seed))
+        H = qk.qk_ham_create(b, 1.0, 1.0, True, f)
+        k = qk.qk_krylov_create(H, m, torch.complex64)
+        D = qk.qk_basis_dim(b)
+        r0 = int(qk.qk_basis_rank(b, [sum(1 << i for i in range(0, L, 2))])[0])
+        psi = torch.zeros((D, Bn) if Bn > 1 else D, dtype=torch.complex64, device="cuda")
+        psi[r0] = 1.0
+        hold.append((b, H))
+        ks.append(k)
+        psis.append(psi)
+        r0s.append(r0)
+    bt = qk.qk_batch_create(ks, psis, r0s)
+    items = qk.qk_batch_items(bt)
+    out = torch.empty((steps, items), dtype=torch.float64, device="cuda")
+    if warmup:
+        qk.qk_batch_run(bt, dt, warmup, use_graph=True)
+    secs = []
+    for _ in range(repeats):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        qk.qk_batch_run(bt, dt, steps, use_graph=True, out=out)
+        torch.cuda.synchronize()
+        secs.append(time.perf_counter() - t0)
+    sec = statistics.median(secs)
+    # kernels of the 64-phase L = 20 workspace alone (eager steps with events)
+    k64, psi64 = ks[0], psis[0]
+    qk.qk_krylov_profile(k64, True)
+    for _ in range(steps):
+        qk.qk_krylov_expm_step(k64, psi64, dt)
+    torch.cuda.synchronize()
+    prof = qk.qk_krylov_profile_read(k64)
+    qk.qk_krylov_profile(k64, False)
+    D20 = qk.qk_basis_dim(hold[0][0])
+    res = dict(items=items, steps=steps, sec=sec, sec_all=secs, phase_steps_per_s=items * steps / sec,
+               steps_per_s=steps / sec, prof64=prof, D20=D20)
+    bt.close()
+    del ks, psis, hold
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    return res
+
+
+def run_large(qk, torch, args, L=30, m=20, dt=0.5, h=2.0):
+    """Krylov steps of the L = 30 ring (D = 155,117,520; h = 2, Neel state,
+    m = 20, dt = 0.5) in complex128 and in complex64 storage, the Krylov basis
+    resident in HBM."""
+    from workloads import BETA_GOLDEN, phases
+    b = qk.qk_basis_build(L, L // 2)
+    D = qk.qk_basis_dim(b)
+    f = qk.qk_fields_quasiperiodic(L, h, BETA_GOLDEN, phases(1, 0))
+    r0 = int(qk.qk_basis_rank(b, [sum(1 << i for i in range(0, L, 2))])[0])
+    out = dict(workload=f"XXZ ring L={L} Sz=0 (D={D}), J=Delta=1, h={h} quasiperiodic, Neel state, m={m}, dt={dt}")
+    for name, dtype, s in (("fp64", torch.complex128, 16), ("fp32", torch.complex64, 8)):
+        log("large", name)
+        r = run_form(qk, torch, b, f, m, dt, dtype, args.large_steps, 1, r0, args.repeats)
+        out[name] = dict(steps_per_s=round(args.large_steps / r["sec"], 3),
+                         ms_per_step=round(1e3 * r["sec"] / args.large_steps, 2),
+                         ms_per_step_runs=[round(1e3 * x / args.large_steps, 2) for x in r["sec_all"]],
+                         roofline=hpass_roofline(r["prof"], m, D, 1, s, None),
+                         m_used=r["m_used"], err_est=r["err_est"], norm_drift=r["norm_drift"], P_last=r["P_last"])
+    b.close()
+    torch.cuda.empty_cache()
+    return out
+
+
+def hpass_roofline(prof, m, D, B, s, traffic):
+    """Roofline entry of the H-pass (the dominant kernel): algorithmic bytes
+    per step are (3m - 1) s D B (iteration 0 reads u_0 and writes w; later
+    iterations also read u_{j-1}), divided by the HIP-event time of its m
+    launches."""
+    ms_h, n_h = prof["lanczos_h"]
+    bytes_launch = (3 * m - 1) * s * D * B / m
+    achieved = bytes_launch * n_h / (ms_h / 1e3) / 1e9
+    return dict(bound="hbm", achieved=round(achieved, 1), peak=PEAK_HBM_GBS, unit="GB/s",
+                frac=round(achieved / PEAK_HBM_GBS, 4), traffic=traffic,
+                bytes_per_launch_avg=bytes_launch, ms_per_launch_avg=ms_h / max(n_h, 1))
+
+
+def host_cpu():
+    """Model name and usable thread count of the host."""
+    model = platform.processor() or "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count() or 1
+    return model, cores
 
 
 def run_adaptive(qk, torch, b, fields, m, r0, t_end, tol):
@@ -419,7 +538,7 @@ def main():
 
     res = {}
     hv = {}
-    adaptive = None
+    adaptive = mixed = large = None
     log("H*x throughput")
     hv["fp64"] = hv_throughput(qk, torch, b, fields1, torch.complex128, args.hv_reps)
     hv["fp32"] = hv_throughput(qk, torch, b, fields1, torch.complex64, args.hv_reps)
@@ -430,14 +549,18 @@ def main():
     for f in forms:
         log("form", f)
         if f == "fp64":
-            res[f] = run_form(qk, torch, b, fields1, m, dt, torch.complex128, args.steps, args.warmup, r0)
+            res[f] = run_form(qk, torch, b, fields1, m, dt, torch.complex128, args.steps, args.warmup, r0, args.repeats)
         elif f == "fp32":
-            res[f] = run_form(qk, torch, b, fields1, m, dt, torch.complex64, args.steps, args.warmup, r0)
+            res[f] = run_form(qk, torch, b, fields1, m, dt, torch.complex64, args.steps, args.warmup, r0, args.repeats)
         elif f == "batched":
             fb = qk.qk_fields_quasiperiodic(L, args.h, BETA_GOLDEN, phases(args.batch, 0))
-            res[f] = run_form(qk, torch, b, fb, m, dt, torch.complex64, args.steps, args.warmup, r0)
+            res[f] = run_form(qk, torch, b, fb, m, dt, torch.complex64, args.steps, args.warmup, r0, args.repeats)
         elif f == "adaptive":
             adaptive = run_adaptive(qk, torch, b, fields1, m, r0, args.adaptive_t, args.adaptive_tol)
+        elif f == "mixed":
+            mixed = run_mixed(qk, torch, args.mixed_steps, 2, args.repeats)
+        elif f == "large":
+            large = run_large(qk, torch, args)
         else:
             raise SystemExit(f"unknown form {f}")
 
@@ -447,36 +570,28 @@ def main():
     head = res[head_form]
     steps = args.steps
     value = steps / head["sec"]
-    # element bytes and phases of the head form (the roofline's kernel)
-    s_bytes = 16 if head_form == "fp64" else 8
     B_head = args.batch if head_form == "batched" else 1
-    # dominant kernel: the H-pass of each Lanczos iteration.  Algorithmic
-    # bytes per step: iteration 0 reads u_0 and writes w (2 vectors), later
-    # iterations also read u_{j-1} (3 vectors).
-    ms_h, n_h = head["prof"]["lanczos_h"]
-    bytes_h_step = (3 * m - 1) * s_bytes * D * B_head
-    achieved = bytes_h_step * steps / (ms_h / 1e3) / 1e9
     traffic = None
     if head_form == "fp64" and os.path.exists(TRAFFIC_FILE):
         tr = json.load(open(TRAFFIC_FILE))
         if tr.get("kernel_source_sha256") == source_sha() and tr.get("m") == m and tr.get("L") == L:
             traffic = tr.get("bytes_per_launch")
-    roof = dict(bound="hbm", achieved=round(achieved, 1), peak=PEAK_HBM_GBS, unit="GB/s",
-                frac=round(achieved / PEAK_HBM_GBS, 4), traffic=traffic,
-                kernel=("H-pass of the Lanczos iteration, w = a H u_j - b u_{j-1} with its dot products "
-                        + {"fp64": "(k_blk<double,11,true>, the blocked matrix-free kernel used for L >= 18)",
-                           "fp32": "(k_blk<float,11,true>, complex64 storage)",
-                           "batched": f"(k_blkb<float,true>, {args.batch} phases in complex64)"}[head_form]),
-                form=head_form,
-                bytes_per_launch_avg=bytes_h_step / m, ms_per_launch_avg=ms_h / max(n_h, 1))
+    roof = hpass_roofline(head["prof"], m, D, B_head, 16 if head_form == "fp64" else 8, traffic)
+    roof["kernel"] = ("H-pass of the Lanczos iteration, w = a H u_j - b u_{j-1} with its dot products "
+                      + {"fp64": "(k_blk<double,11,true>, the blocked matrix-free kernel used for L >= 18)",
+                         "fp32": "(k_blk<float,11,true>, complex64 storage)",
+                         "batched": f"(k_blkb<float,true>, {args.batch} phases in complex64)"}[head_form])
+    roof["form"] = head_form
 
-    def form_summary(r, B, s):
+    def form_summary(r, B, s, m_, D_, steps_):
         sec = r["sec"]
         kernels = {kname: dict(ms_per_launch=ms / max(n, 1), launches=n) for kname, (ms, n) in r["prof"].items()}
-        step_bytes = (7 * m - 1) * s * D * B
-        return dict(steps_per_s=round(steps / sec, 3), phase_steps_per_s=round(B * steps / sec, 3),
-                    ms_per_step=round(1e3 * sec / steps, 3), ms_per_step_no_events=round(1e3 * r["sec_no_events"] / steps, 3),
-                    step_algorithmic_GBps=round(step_bytes * steps / sec / 1e9, 1), kernels=kernels,
+        step_bytes = (7 * m_ - 1) * s * D_ * B
+        return dict(steps_per_s=round(steps_ / sec, 3), phase_steps_per_s=round(B * steps_ / sec, 3),
+                    ms_per_step=round(1e3 * sec / steps_, 3),
+                    ms_per_step_runs=[round(1e3 * x / steps_, 3) for x in r["sec_all"]],
+                    step_algorithmic_GBps=round(step_bytes * steps_ / sec / 1e9, 1), kernels=kernels,
+                    roofline=hpass_roofline(r["prof"], m_, D_, B, s, None),
                     m_used=r["m_used"], err_est=r["err_est"], norm_drift=r["norm_drift"], P_last=r["P_last"])
 
     out = {
@@ -505,9 +620,22 @@ def main():
     for f, r in res.items():
         B = args.batch if f == "batched" else 1
         s = 16 if f == "fp64" else 8
-        out["forms"][f] = form_summary(r, B, s)
+        out["forms"][f] = form_summary(r, B, s, m, D, steps)
     if adaptive is not None:
         out["adaptive"] = adaptive
+    if mixed is not None:
+        out["mixed"] = dict(
+            workload="64 phases of the L=20 ring (D=184756) + rings L=16,18,20,22 (one phase each), h=2, "
+                     "J=Delta=1, Neel state, m=30, dt=0.1, complex64 vectors, FP64 Lanczos coefficients; "
+                     "all members advanced by one hipGraph replay per step",
+            items=mixed["items"], steps=mixed["steps"], phase_steps_per_s=round(mixed["phase_steps_per_s"], 1),
+            steps_per_s=round(mixed["steps_per_s"], 2), ms_per_step=round(1e3 * mixed["sec"] / mixed["steps"], 3),
+            ms_per_step_runs=[round(1e3 * x / mixed["steps"], 3) for x in mixed["sec_all"]],
+            roofline_L20x64=hpass_roofline(mixed["prof64"], 30, mixed["D20"], 64, 8, None),
+            kernels_L20x64={kname: dict(ms_per_launch=ms_ / max(n_, 1), launches=n_)
+                            for kname, (ms_, n_) in mixed["prof64"].items()})
+    if large is not None:
+        out["large"] = large
     if aux is not None:
         out["aux"] = aux
     if not args.no_cpu_baseline:
@@ -515,6 +643,9 @@ def main():
         cb = cpu_baseline(L, m, fields1[0], True, args.cpu_seconds)
         out["cpu_baseline"] = {k: (round(v, 6) if isinstance(v, float) else v) for k, v in cb.items()
                                if k in ("value", "unit", "cores", "kind", "sample")}
+        model, avail = host_cpu()
+        out["cpu_baseline"]["host_cpu"] = model
+        out["cpu_baseline"]["host_threads_available"] = avail
     print(json.dumps(out), flush=True)
 
 
