@@ -368,10 +368,17 @@ void qk_batch_destroy(qk_batch* b);
  * costate lambda(s) = exp(+iH(T-s)) e_r0 propagated backward by Krylov steps
  * of -dt; inside each step the time integral of <lambda|Z_i|psi> is taken
  * between the two Krylov bases by Gauss-Legendre quadrature of the projected
- * propagators.  The forward states are kept every ckpt_every (>= 1) steps;
- * the backward sweep recomputes the states of one segment from its
- * checkpoint (one extra forward pass in total, identical results), so the
- * call holds n_steps / ckpt_every + ckpt_every + 2 state vectors plus one more
+ * propagators.  When n_steps Krylov bases of the workspace (n_steps * m
+ * vectors) and n_steps + 1 states fit in 80 % of the free device memory, the
+ * forward pass keeps every basis with its coefficients in a bank owned by the
+ * workspace (kept for later calls of at most that many steps, freed by
+ * qk_krylov_destroy) and every state, and the backward pass uses them
+ * directly; ckpt_every is then not used.  Otherwise (or with the environment
+ * variable QK_GRAD_KEEP=0) the forward states are kept every ckpt_every
+ * (>= 1) steps, the backward sweep recomputes the states of one segment from
+ * its checkpoint (one extra forward pass in total) and rebuilds each basis
+ * from its state; both ways give identical results.  The call also holds
+ * up to n_steps / ckpt_every + ckpt_every + 2 state vectors plus one more
  * workspace, allocated for its duration.  Uses the workspace's Hamiltonian,
  * Krylov dimension and launch shape.  Requires dtype QK_C128, batch 1 and
  * m <= 32 (else QK_EUNSUPPORTED).  Synchronous; F_host and dFdh_host are host

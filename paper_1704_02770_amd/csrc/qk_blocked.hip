@@ -661,7 +661,7 @@ qk_status launch_blocked_build(qk_ham* H, hipStream_t s) {
     e = hipGetLastError();
   }
   if (e == hipSuccess) e = hipStreamSynchronize(s);
-  else hipStreamSynchronize(s);   // nothing queued may still use the temporaries
+  else (void)hipStreamSynchronize(s);   // nothing queued may still use the temporaries
   dev_free(H->al, tmp);
   dev_free(H->al, flag);
   dev_free(H->al, idx);

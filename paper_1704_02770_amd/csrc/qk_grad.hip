@@ -21,6 +21,7 @@
 //     converges to rounding error), and the row sum is one pass over the two
 //     Krylov bases.
 #include <cmath>
+#include <cstdlib>
 #include <new>
 #include <vector>
 
@@ -118,14 +119,23 @@ k_grad_coeffs(KState fw, KState bw, double dt, GaussRule gr, double* __restrict_
 }
 
 // Per row r: s_r = sum_c conj(u'_c[r]) sum_d C~_cd u_d[r] (u_0 = psi_k,
-// u'_0 = lambda_{k+1}, further vectors from the workspace slots).  Every tile
-// of 256 rows puts its s_r and states in LDS, and thread q < 2(L_max+1) adds
+// u'_0 = lambda_{k+1}, further vectors from the workspace slots).  Four
+// lanes share two rows: lane g accumulates t_c = sum_d C~_cd u_d of both
+// rows for the columns c = g, g+4, ... (at most eight), so each C~ value read
+// from LDS serves two rows and every lane holds sixteen accumulators; the
+// four partial sums of s_r are combined by lane shuffles.  Every tile of 128
+// rows puts its s_r and states in LDS, and thread q < 2(L_max+1) adds
 // component q&1 of s_r over the tile's rows whose state has bit q>>1 set
 // (q>>1 == L_max: all rows), so each block writes 2(L_max+1) partial sums.
 constexpr int kGradQ = 2 * (QK_MAX_L + 1);
+constexpr int kGradLanesPerRow = 4;
+constexpr int kGradRowsPerLane = 2;
+constexpr int kGradCPer = kGradMaxM / kGradLanesPerRow;
+constexpr int kGradGroups = 256 / kGradLanesPerRow;            // lane groups of a 256-thread block
+constexpr int kGradRows = kGradGroups * kGradRowsPerLane;       // rows per tile
 
 template <typename S>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(256, 4)
 k_grad_contract(const S* __restrict__ states, uint64_t niter, int L, const double2* __restrict__ psi_k,
                 const double2* __restrict__ Uf, const double2* __restrict__ lam, const double2* __restrict__ Ub,
                 size_t stride, const uint32_t* __restrict__ line_r0, const uint8_t* __restrict__ line_n, int pe,
@@ -134,51 +144,78 @@ k_grad_contract(const S* __restrict__ states, uint64_t niter, int L, const doubl
   // the sorted basis, or, with line tables, elements of the padded layout
   // whose row comes from their line's entry (unused padding is skipped)
   __shared__ double2 C[kGradMaxM * kGradMaxM];
-  __shared__ double2 sbuf[256];
-  __shared__ S sst[256];
+  __shared__ double2 sbuf[kGradRows];
+  __shared__ S sst[kGradRows];
   const int tid = threadIdx.x;
   for (int i = tid; i < kGradMaxM * kGradMaxM; i += blockDim.x) C[i] = make_double2(Ct[2 * i], Ct[2 * i + 1]);
   __syncthreads();
   const int muf = fw.mused[0] < kGradMaxM ? fw.mused[0] : kGradMaxM;
   const int mub = bw.mused[0] < kGradMaxM ? bw.mused[0] : kGradMaxM;
   const int site = tid >> 1, comp = tid & 1;
+  const int grp = tid / kGradLanesPerRow, lg = tid % kGradLanesPerRow;
   double acc = 0.0;
-  for (uint64_t base = (uint64_t)blockIdx.x * 256u; base < niter; base += (uint64_t)gridDim.x * 256u) {
-    const uint64_t p = base + tid;
-    bool valid = p < niter;
-    size_t r = (size_t)p;
-    if (valid && line_r0) {
-      const uint64_t ln = p / (uint64_t)pe;
-      const uint32_t e = (uint32_t)(p - ln * (uint64_t)pe);
-      valid = e < line_n[ln];
-      r = (size_t)line_r0[ln] + e;
-    }
-    double sr = 0.0, si = 0.0;
-    S stt = 0;
-    if (valid) {
-      double2 u[kGradMaxM];
+  for (uint64_t base = (uint64_t)blockIdx.x * kGradRows; base < niter; base += (uint64_t)gridDim.x * kGradRows) {
+    uint64_t p[kGradRowsPerLane];
+    size_t r[kGradRowsPerLane];
+    bool valid[kGradRowsPerLane];
 #pragma unroll
-      for (int d = 0; d < kGradMaxM; ++d)
-        u[d] = (d < muf) ? (d == 0 ? psi_k[r] : Uf[(size_t)(d - 1) * stride + p]) : make_double2(0.0, 0.0);
-      for (int c = 0; c < mub; ++c) {
-        const double2 w = (c == 0) ? lam[r] : Ub[(size_t)(c - 1) * stride + p];
-        double tr = 0.0, ti = 0.0;
-#pragma unroll
-        for (int d = 0; d < kGradMaxM; ++d) {
-          const double2 cc = C[c * kGradMaxM + d];
-          tr += cc.x * u[d].x - cc.y * u[d].y;
-          ti += cc.x * u[d].y + cc.y * u[d].x;
-        }
-        sr += w.x * tr + w.y * ti;   // conj(w) t
-        si += w.x * ti - w.y * tr;
+    for (int i = 0; i < kGradRowsPerLane; ++i) {
+      p[i] = base + (uint64_t)i * kGradGroups + grp;   // consecutive lane groups take consecutive rows
+      valid[i] = p[i] < niter;
+      r[i] = (size_t)p[i];
+      if (valid[i] && line_r0) {
+        const uint64_t ln = p[i] / (uint64_t)pe;
+        const uint32_t e = (uint32_t)(p[i] - ln * (uint64_t)pe);
+        valid[i] = e < line_n[ln];
+        r[i] = (size_t)line_r0[ln] + e;
       }
-      stt = states[r];
     }
-    sbuf[tid] = make_double2(sr, si);
-    sst[tid] = stt;
+    double tr[kGradRowsPerLane][kGradCPer], ti[kGradRowsPerLane][kGradCPer];
+#pragma unroll
+    for (int i = 0; i < kGradRowsPerLane; ++i)
+#pragma unroll
+      for (int k = 0; k < kGradCPer; ++k) tr[i][k] = ti[i][k] = 0.0;
+    for (int d = 0; d < muf; ++d) {
+      double2 u[kGradRowsPerLane];
+#pragma unroll
+      for (int i = 0; i < kGradRowsPerLane; ++i)
+        u[i] = !valid[i] ? make_double2(0.0, 0.0) : (d == 0 ? psi_k[r[i]] : Uf[(size_t)(d - 1) * stride + p[i]]);
+#pragma unroll
+      for (int k = 0; k < kGradCPer; ++k) {
+        const double2 cc = C[(lg + kGradLanesPerRow * k) * kGradMaxM + d];
+#pragma unroll
+        for (int i = 0; i < kGradRowsPerLane; ++i) {
+          tr[i][k] += cc.x * u[i].x - cc.y * u[i].y;
+          ti[i][k] += cc.x * u[i].y + cc.y * u[i].x;
+        }
+      }
+    }
+    double sr[kGradRowsPerLane], si[kGradRowsPerLane];
+#pragma unroll
+    for (int i = 0; i < kGradRowsPerLane; ++i) {
+      sr[i] = si[i] = 0.0;
+#pragma unroll
+      for (int k = 0; k < kGradCPer; ++k) {
+        const int c = lg + kGradLanesPerRow * k;
+        if (valid[i] && c < mub) {
+          const double2 w = c == 0 ? lam[r[i]] : Ub[(size_t)(c - 1) * stride + p[i]];
+          sr[i] += w.x * tr[i][k] + w.y * ti[i][k];   // conj(w) t
+          si[i] += w.x * ti[i][k] - w.y * tr[i][k];
+        }
+      }
+      // the four lanes of a group are adjacent in the wave
+      sr[i] += __shfl_xor(sr[i], 1);
+      si[i] += __shfl_xor(si[i], 1);
+      sr[i] += __shfl_xor(sr[i], 2);
+      si[i] += __shfl_xor(si[i], 2);
+      if (lg == 0) {
+        sbuf[i * kGradGroups + grp] = make_double2(sr[i], si[i]);
+        sst[i * kGradGroups + grp] = valid[i] ? states[r[i]] : (S)0;
+      }
+    }
     __syncthreads();
     if (tid < kGradQ && (site < L || site == QK_MAX_L)) {
-      for (int q = 0; q < 256; ++q) {
+      for (int q = 0; q < kGradRows; ++q) {
         const bool on = site == QK_MAX_L || ((sst[q] >> site) & (S)1);
         const double v = comp ? sbuf[q].y : sbuf[q].x;
         acc += on ? v : 0.0;
@@ -220,7 +257,54 @@ qk_status grad_return_prob(qk_krylov* k, int64_t r0, double T, int n_steps, int 
   const double dt = T / n_steps;
   const size_t vbytes = sizeof(double2) * (size_t)D;
   const int G = 1024;
-  const int c = ckpt_every < 1 ? 1 : (ckpt_every > n_steps ? n_steps : ckpt_every);
+  // Every forward Krylov basis (and its coefficients) is kept when all of
+  // them fit in 80 % of the free device memory, so the backward pass needs
+  // no rebuilding; the bank stays with the workspace for later calls.
+  // QK_GRAD_KEEP=0 turns this off.  Otherwise each basis is rebuilt from its
+  // checkpoint.
+  const size_t ubytes = sizeof(double2) * (size_t)k->ustride * (size_t)k->m;   // one basis
+  const size_t cdoubles = kstate_doubles(k->m, 1);
+  const char* keep_env = getenv("QK_GRAD_KEEP");
+  const bool want = !(keep_env && keep_env[0] == '0');
+  {
+    if (want && k->g_steps < n_steps) {
+      // replace a smaller bank (its memory counts as free)
+      const size_t held = ubytes * (size_t)k->g_steps;
+      size_t fr = 0, tot = 0;
+      if (hipMemGetInfo(&fr, &tot) == hipSuccess &&
+          ubytes * (size_t)n_steps + vbytes * (size_t)(n_steps + 1) <= (fr + held) / 10 * 8) {
+        dev_free(k->al, k->g_ubank);
+        dev_free(k->al, k->g_cbank);
+        dev_free(k->al, k->g_ibank);
+        k->g_ubank = nullptr;
+        k->g_cbank = nullptr;
+        k->g_ibank = nullptr;
+        k->g_steps = 0;
+        void* ub = nullptr;
+        double* cb = nullptr;
+        int32_t* ib = nullptr;
+        if (dev_alloc(k->al, &ub, ubytes * (size_t)n_steps) == hipSuccess &&
+            dev_alloc(k->al, (void**)&cb, sizeof(double) * cdoubles * n_steps) == hipSuccess &&
+            dev_alloc(k->al, (void**)&ib, sizeof(int32_t) * 2 * (size_t)n_steps) == hipSuccess) {
+          k->g_ubank = ub;
+          k->g_cbank = cb;
+          k->g_ibank = ib;
+          k->g_steps = n_steps;
+        } else {
+          dev_free(k->al, ub);
+          dev_free(k->al, cb);
+          dev_free(k->al, ib);
+          (void)hipGetLastError();
+        }
+      }
+    }
+  }
+  void* const ubank = want && k->g_steps >= n_steps ? k->g_ubank : nullptr;
+  double* const cbank = k->g_cbank;
+  int32_t* const ibank = k->g_ibank;
+  const bool keep = ubank != nullptr;
+  // kept bases need every state psi_t as a checkpoint
+  const int c = keep ? 1 : (ckpt_every < 1 ? 1 : (ckpt_every > n_steps ? n_steps : ckpt_every));
   const int nck = n_steps / c + 1;   // checkpoints psi_0, psi_c, psi_2c, ...
   qk_krylov* kb = nullptr;   // workspace of the backward steps
   double2* ck = nullptr;     // checkpoints
@@ -271,8 +355,19 @@ qk_status grad_return_prob(qk_krylov* k, int64_t r0, double T, int n_steps, int 
     e = hipMemcpyAsync(ck, cur, vbytes, hipMemcpyDeviceToDevice, s);
     chk("checkpoint copy");
   }
+  void* const u_home = k->d_U;
   for (int t = 0; t < n_steps && st == QK_OK; ++t) {
+    // with kept bases the step builds its basis directly in the bank
+    if (keep) k->d_U = (char*)ubank + (size_t)t * ubytes;
     st = launch_krylov_step(k, cur, dt, s, true);
+    k->d_U = u_home;
+    if (st == QK_OK && keep) {
+      e = hipMemcpyAsync(cbank + (size_t)t * cdoubles, k->d_coef, sizeof(double) * cdoubles, hipMemcpyDeviceToDevice,
+                         s);
+      if (e == hipSuccess)
+        e = hipMemcpyAsync(ibank + 2 * (size_t)t, k->d_int, sizeof(int32_t) * 2, hipMemcpyDeviceToDevice, s);
+      chk("basis bank copy");
+    }
     if (st == QK_OK && (t + 1) % c == 0 && (t + 1) / c < nck) {
       e = hipMemcpyAsync(ck + (size_t)((t + 1) / c) * D, cur, vbytes, hipMemcpyDeviceToDevice, s);
       chk("checkpoint copy");
@@ -304,25 +399,28 @@ qk_status grad_return_prob(qk_krylov* k, int64_t r0, double T, int n_steps, int 
       }
       if (st != QK_OK) break;
     }
-    // Krylov basis of psi_t (the stored state is left unchanged)
-    st = launch_krylov_step(k, state_at(t), dt, s, false);
+    // Krylov basis of psi_t: kept from the forward pass, or rebuilt from the
+    // stored state (which is left unchanged)
+    const double2* Uf = keep ? (const double2*)((char*)ubank + (size_t)t * ubytes) : (const double2*)k->d_U;
+    const KState fwt = keep ? kstate_at(k, cbank + (size_t)t * cdoubles, ibank + 2 * (size_t)t) : fw;
+    if (!keep) st = launch_krylov_step(k, state_at(t), dt, s, false);
     if (st != QK_OK) break;
     // lambda_t = exp(+iH dt) lambda_{t+1}; lamp keeps lambda_{t+1}
     e = hipMemcpyAsync(lamp, lam, vbytes, hipMemcpyDeviceToDevice, s);
     chk("costate copy");
     if (st == QK_OK) st = launch_krylov_step(kb, lam, -dt, s, true);
     if (st != QK_OK) break;
-    hipLaunchKernelGGL(k_grad_coeffs, dim3(1), dim3(64), 0, s, fw, bw, dt, gr, Ct);
+    hipLaunchKernelGGL(k_grad_coeffs, dim3(1), dim3(64), 0, s, fwt, bw, dt, gr, Ct);
     chk("k_grad_coeffs");
     if (st != QK_OK) break;
     if (H->basis->wide)
       hipLaunchKernelGGL(k_grad_contract<uint64_t>, dim3(G), dim3(256), 0, s, (const uint64_t*)H->basis->d_states,
-                         niter, L, (const double2*)state_at(t), (const double2*)k->d_U, (const double2*)lamp,
-                         (const double2*)kb->d_U, (size_t)k->ustride, lr0, lnn, pe, fw, bw, Ct, part);
+                         niter, L, (const double2*)state_at(t), Uf, (const double2*)lamp,
+                         (const double2*)kb->d_U, (size_t)k->ustride, lr0, lnn, pe, fwt, bw, Ct, part);
     else
       hipLaunchKernelGGL(k_grad_contract<uint32_t>, dim3(G), dim3(256), 0, s, (const uint32_t*)H->basis->d_states,
-                         niter, L, (const double2*)state_at(t), (const double2*)k->d_U, (const double2*)lamp,
-                         (const double2*)kb->d_U, (size_t)k->ustride, lr0, lnn, pe, fw, bw, Ct, part);
+                         niter, L, (const double2*)state_at(t), Uf, (const double2*)lamp,
+                         (const double2*)kb->d_U, (size_t)k->ustride, lr0, lnn, pe, fwt, bw, Ct, part);
     chk("k_grad_contract");
     if (st != QK_OK) break;
     hipLaunchKernelGGL(k_grad_accum, dim3(1), dim3(256), 0, s, part, G, L, dA);

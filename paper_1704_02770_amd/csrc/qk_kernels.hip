@@ -713,9 +713,10 @@ ModelArgs model_args(const qk_ham* H) {
   return a;
 }
 
-KState make_kstate(const qk_krylov* k) {
+KState make_kstate(const qk_krylov* k) { return kstate_at(k, k->d_coef, k->d_int); }
+
+KState kstate_at(const qk_krylov* k, double* p, int32_t* ints) {
   const int m = k->m, B = k->batch;
-  double* p = k->d_coef;
   KState s;
   s.alpha = p;
   s.beta = p + (size_t)m * B;
@@ -724,8 +725,8 @@ KState make_kstate(const qk_krylov* k) {
   s.gre = p + (size_t)(3 * m + 2) * B;
   s.gim = p + (size_t)(4 * m + 2) * B;
   s.err = p + (size_t)(5 * m + 2) * B;
-  s.mused = k->d_int;
-  s.status = k->d_int + B;
+  s.mused = ints;
+  s.status = ints + B;
   s.tau = p + (size_t)(5 * m + 3) * B;
   return s;
 }

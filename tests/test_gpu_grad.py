@@ -73,21 +73,40 @@ def test_gradient_workload_vs_oracle_richardson():
     assert F2 == F and np.array_equal(g2, g)   # deterministic
 
 
-def test_checkpoint_stride_gives_identical_results():
-    # states kept every c steps and recomputed per segment: the same kernels on
-    # the same inputs, so F and dF/dh agree bitwise for every stride
+def test_checkpoint_stride_gives_identical_results(monkeypatch):
+    # bases rebuilt in the backward pass (QK_GRAD_KEEP=0) from states kept
+    # every c steps and recomputed per segment: the same kernels on the same
+    # inputs, so F and dF/dh agree bitwise for every stride, and with the
+    # forward bases kept in device memory instead
     L, T, n = 12, 5.0, 50
     b, H, k, hf = _ws(L, True, 1.5, 0.9)
     r0 = neel_row(L)
     say("grad checkpoint strides")
+    monkeypatch.setenv("QK_GRAD_KEEP", "0")
     F1, g1 = qk.qk_grad_return_prob(k, r0, T, n, 1)
     for c in (3, 7, 50, 80):
         Fc, gc = qk.qk_grad_return_prob(k, r0, T, n, c)
         assert Fc == F1 and np.array_equal(gc, g1), c
+    monkeypatch.delenv("QK_GRAD_KEEP")
+    Fk, gk = qk.qk_grad_return_prob(k, r0, T, n, 7)
+    assert Fk == F1 and np.array_equal(gk, g1)
     F_ref, g_ref = OG.dF_dh(L, L // 2, True, 1.0, 1.0, hf, r0, T)
     assert np.max(np.abs(g1 - g_ref)) < 1e-9 * max(1.0, np.max(np.abs(g_ref)))
     with pytest.raises(qk.QkError):
         qk.qk_grad_return_prob(k, r0, T, n, 0)
+
+
+def test_kept_bases_equal_rebuilt_blocked_path(monkeypatch):
+    # the blocked H-pass (L = 20): forward bases kept in device memory and
+    # bases rebuilt from checkpoints give the same bits
+    L, T, n = 20, 1.0, 10
+    b, H, k, hf = _ws(L, True, 1.5, 0.4)
+    r0 = neel_row(L)
+    say("grad kept vs rebuilt bases, L=20")
+    Fk, gk = qk.qk_grad_return_prob(k, r0, T, n, 4)
+    monkeypatch.setenv("QK_GRAD_KEEP", "0")
+    Fr, gr = qk.qk_grad_return_prob(k, r0, T, n, 4)
+    assert Fk == Fr and np.array_equal(gk, gr)
 
 
 def test_autograd_wrapper():
