@@ -6,8 +6,8 @@ h in {0, 1, 3}, open and periodic bonds, at all 200 log-spaced output times
 
 Every value comes from the oracle alone: its sorted basis, its CSR Hamiltonian
 and scipy's expm_multiply (oracle.midsize), step by step between output times.
-The six cases run in parallel processes, one host thread each (about 20
-minutes of wall time on the 8-core build host).
+The six cases run in parallel processes, one host thread each (one to two
+hours of wall time on an 8-core host).
 Run from the repository root:  python tests/golden/make_golden_l24.py
 """
 import os
