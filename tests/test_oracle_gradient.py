@@ -41,3 +41,25 @@ def test_clean_ring_sublattice_pattern():
     assert np.allclose(g[0::2], g[0], atol=1e-12)
     assert np.allclose(g[1::2], -g[0], atol=1e-12)
     assert abs(g[0]) > 1e-4
+
+
+def test_finite_differences_through_expm_multiply_and_richardson():
+    # the route of the L = 20 golden values: F from the mid-size propagator
+    # (expm_multiply on the CSR H), central differences at eps and eps / 2
+    # combined by one Richardson step, against the Daleckii-Krein derivative
+    from oracle import hamiltonian as OH
+    from oracle import midsize as OMS
+    L, T = 10, 2.0
+    h = M.fields(L, 1.5, BETA_GOLDEN, 0.7)
+    r0 = _r0(L)
+
+    def F(hh):
+        return float(OMS.survival_probability(OH.build_csr(L, L // 2, True, 1.0, 1.0, hh), r0, [T])[0])
+
+    _, g = G.dF_dh(L, L // 2, True, 1.0, 1.0, h, r0, T)
+    idx = [0, 3, 7]
+    d1 = G.dF_dh_finite_difference(L, L // 2, True, 1.0, 1.0, h, r0, T, eps=1e-3, propagate=F, indices=idx)
+    d2 = G.dF_dh_finite_difference(L, L // 2, True, 1.0, 1.0, h, r0, T, eps=5e-4, propagate=F, indices=idx)
+    rich = (4.0 * d2 - d1) / 3.0
+    assert np.max(np.abs(d1 - g[idx])) < 1e-5          # O(eps^2) truncation visible
+    assert np.max(np.abs(rich - g[idx])) < 1e-9          # removed by the Richardson step
