@@ -171,7 +171,7 @@ def test_blocked_equals_row_form(pbc):
 
 
 BATCHED_BLOCKED = [(18, 9, True, 2), (18, 9, False, 4), (20, 10, True, 8), (20, 10, False, 64), (19, 9, True, 16),
-                   (22, 11, True, 32)]
+                   (22, 11, True, 32), (18, 9, True, 64), (21, 10, True, 64)]
 
 
 @pytest.mark.parametrize("dtype", [torch.complex128, torch.complex64])
