@@ -370,14 +370,18 @@ def aux_timings(qk, torch, L, fields1, b, csr_L, h):
     del psi0, psi, P
     torch.cuda.empty_cache()
     # adjoint gradient dF/dh_i: the gradient workload (L = 20, T = 5 in 50
-    # steps, m = 30) and five steps of the L chain
+    # steps, m = 30) and five steps of the L chain; the handles and the call's
+    # temporaries (checkpoints, the kept Krylov bases) come from torch's
+    # caching allocator, and a first identical call fills its cache, so the
+    # timed call measures the steady state of repeated gradient calls
+    qk.use_torch_allocator()
     for Lg, T, n in ((20, 5.0, 50), (L, 0.5, 5)):
         bg = qk.qk_basis_build(Lg, Lg // 2)
         fg = qk.qk_fields_quasiperiodic(Lg, 1.5, BETA_GOLDEN, phases(1, 0))
         Hg = qk.qk_ham_create(bg, 1.0, 1.0, True, fg)
         kg = qk.qk_krylov_create(Hg, 30, torch.complex128)
         rg = int(qk.qk_basis_rank(bg, [sum(1 << i for i in range(0, Lg, 2))])[0])
-        qk.qk_grad_return_prob(kg, rg, T / n, 1)
+        qk.qk_grad_return_prob(kg, rg, T, n)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         F, dF = qk.qk_grad_return_prob(kg, rg, T, n)
@@ -388,6 +392,7 @@ def aux_timings(qk, torch, L, fields1, b, csr_L, h):
         Hg.close()
         bg.close()
         torch.cuda.empty_cache()
+    qk.qk_set_allocator()
     return out
 
 

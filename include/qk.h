@@ -375,10 +375,9 @@ void qk_batch_destroy(qk_batch* b);
  * between the two Krylov bases by Gauss-Legendre quadrature of the projected
  * propagators.  When n_steps Krylov bases of the workspace (n_steps * m
  * vectors) and n_steps + 1 states fit in 80 % of the free device memory, the
- * forward pass keeps every basis with its coefficients in a bank owned by the
- * workspace (kept for later calls of at most that many steps, freed by
- * qk_krylov_destroy) and every state, and the backward pass uses them
- * directly; ckpt_every is then not used.  Otherwise (or with the environment
+ * forward pass keeps every basis with its coefficients and every state for
+ * the duration of the call, and the backward pass uses them directly;
+ * ckpt_every is then not used.  Otherwise (or with the environment
  * variable QK_GRAD_KEEP=0) the forward states are kept every ckpt_every
  * (>= 1) steps, the backward sweep recomputes the states of one segment from
  * its checkpoint (one extra forward pass in total) and rebuilds each basis

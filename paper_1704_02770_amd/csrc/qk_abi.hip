@@ -604,9 +604,6 @@ QK_API void qk_krylov_destroy(qk_krylov* k) {
   dev_free(k->al, k->d_ptot);
   dev_free(k->al, k->d_Z);
   dev_free(k->al, k->d_sp);
-  dev_free(k->al, k->g_ubank);
-  dev_free(k->al, k->g_cbank);
-  dev_free(k->al, k->g_ibank);
   delete k;
 }
 

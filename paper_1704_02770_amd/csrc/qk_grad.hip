@@ -257,51 +257,33 @@ qk_status grad_return_prob(qk_krylov* k, int64_t r0, double T, int n_steps, int 
   const double dt = T / n_steps;
   const size_t vbytes = sizeof(double2) * (size_t)D;
   const int G = 1024;
-  // Every forward Krylov basis (and its coefficients) is kept when all of
-  // them fit in 80 % of the free device memory, so the backward pass needs
-  // no rebuilding; the bank stays with the workspace for later calls.
-  // QK_GRAD_KEEP=0 turns this off.  Otherwise each basis is rebuilt from its
-  // checkpoint.
+  // Every forward Krylov basis (and its coefficients) is kept for the
+  // duration of the call when all of them fit in 80 % of the free device
+  // memory, so the backward pass needs no rebuilding; QK_GRAD_KEEP=0 turns
+  // this off.  Otherwise each basis is rebuilt from its checkpoint.
   const size_t ubytes = sizeof(double2) * (size_t)k->ustride * (size_t)k->m;   // one basis
   const size_t cdoubles = kstate_doubles(k->m, 1);
-  const char* keep_env = getenv("QK_GRAD_KEEP");
-  const bool want = !(keep_env && keep_env[0] == '0');
+  void* ubank = nullptr;
+  double* cbank = nullptr;
+  int32_t* ibank = nullptr;
   {
-    if (want && k->g_steps < n_steps) {
-      // replace a smaller bank (its memory counts as free)
-      const size_t held = ubytes * (size_t)k->g_steps;
-      size_t fr = 0, tot = 0;
-      if (hipMemGetInfo(&fr, &tot) == hipSuccess &&
-          ubytes * (size_t)n_steps + vbytes * (size_t)(n_steps + 1) <= (fr + held) / 10 * 8) {
-        dev_free(k->al, k->g_ubank);
-        dev_free(k->al, k->g_cbank);
-        dev_free(k->al, k->g_ibank);
-        k->g_ubank = nullptr;
-        k->g_cbank = nullptr;
-        k->g_ibank = nullptr;
-        k->g_steps = 0;
-        void* ub = nullptr;
-        double* cb = nullptr;
-        int32_t* ib = nullptr;
-        if (dev_alloc(k->al, &ub, ubytes * (size_t)n_steps) == hipSuccess &&
-            dev_alloc(k->al, (void**)&cb, sizeof(double) * cdoubles * n_steps) == hipSuccess &&
-            dev_alloc(k->al, (void**)&ib, sizeof(int32_t) * 2 * (size_t)n_steps) == hipSuccess) {
-          k->g_ubank = ub;
-          k->g_cbank = cb;
-          k->g_ibank = ib;
-          k->g_steps = n_steps;
-        } else {
-          dev_free(k->al, ub);
-          dev_free(k->al, cb);
-          dev_free(k->al, ib);
-          (void)hipGetLastError();
-        }
+    const char* ev = getenv("QK_GRAD_KEEP");
+    size_t fr = 0, tot = 0;
+    if (!(ev && ev[0] == '0') && hipMemGetInfo(&fr, &tot) == hipSuccess &&
+        ubytes * (size_t)n_steps + vbytes * (size_t)(n_steps + 1) <= fr / 10 * 8) {
+      if (dev_alloc(k->al, &ubank, ubytes * (size_t)n_steps) != hipSuccess ||
+          dev_alloc(k->al, (void**)&cbank, sizeof(double) * cdoubles * n_steps) != hipSuccess ||
+          dev_alloc(k->al, (void**)&ibank, sizeof(int32_t) * 2 * (size_t)n_steps) != hipSuccess) {
+        dev_free(k->al, ubank);
+        dev_free(k->al, cbank);
+        dev_free(k->al, ibank);
+        ubank = nullptr;
+        cbank = nullptr;
+        ibank = nullptr;
+        (void)hipGetLastError();
       }
     }
   }
-  void* const ubank = want && k->g_steps >= n_steps ? k->g_ubank : nullptr;
-  double* const cbank = k->g_cbank;
-  int32_t* const ibank = k->g_ibank;
   const bool keep = ubank != nullptr;
   // kept bases need every state psi_t as a checkpoint
   const int c = keep ? 1 : (ckpt_every < 1 ? 1 : (ckpt_every > n_steps ? n_steps : ckpt_every));
@@ -314,7 +296,12 @@ qk_status grad_return_prob(qk_krylov* k, int64_t r0, double T, int n_steps, int 
   double2* lamp = nullptr;   // lambda_{k+1}
   double *Ct = nullptr, *part = nullptr, *dA = nullptr;
   qk_status st = krylov_create(H, k->m, QK_C128, k->reorth, k->al, &kb);
-  if (st != QK_OK) return st;
+  if (st != QK_OK) {
+    dev_free(k->al, ubank);
+    dev_free(k->al, cbank);
+    dev_free(k->al, ibank);
+    return st;
+  }
   kb->threads = k->threads;
   kb->blocks_per_cu = k->blocks_per_cu;
   kb->blocked_wgs = k->blocked_wgs;
@@ -445,6 +432,9 @@ qk_status grad_return_prob(qk_krylov* k, int64_t r0, double T, int n_steps, int 
   dev_free(k->al, Ct);
   dev_free(k->al, part);
   dev_free(k->al, dA);
+  dev_free(k->al, ubank);
+  dev_free(k->al, cbank);
+  dev_free(k->al, ibank);
   qk_krylov_destroy(kb);
   return st;
 }

@@ -131,12 +131,6 @@ struct qk_krylov {
   // two-pass split iteration (one field set, no reorthogonalisation)
   void* d_Z = nullptr;            // [ustride] high-pass result z of the current iteration (padded layout)
   double* d_sp = nullptr;         // partial sums: high pass [kMaxPartialBlocks][2], low pass 2 x ([kMaxPartialBlocks] norms, [kMaxPartialBlocks] forms)
-  // gradient: forward Krylov bases kept for the backward pass (qk_grad_return_prob),
-  // reused by later calls of the same or a smaller size, freed with the workspace
-  void* g_ubank = nullptr;        // [g_steps][m slots of ustride elements]
-  double* g_cbank = nullptr;      // [g_steps] coefficient blocks
-  int32_t* g_ibank = nullptr;     // [g_steps][2] m_used, status
-  int g_steps = 0;
   // event timing (qk_krylov_profile)
   bool profiling = false;
   struct Pending { int kind; hipEvent_t start, end; };

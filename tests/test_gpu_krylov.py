@@ -28,6 +28,20 @@ def _problem(L, pbc, h=1.5, jz=1.0, phi=0.4, mode=qk.QK_MATFREE, Bn=1):
     return b, H, hf
 
 
+_L16_REF = {}
+
+
+def _l16_workload_reference(w, hf, r0, times):
+    """Dense propagation of the L = 16 workload (one eigendecomposition of
+    the 12,870-dimensional H, shared by the tests that use it)."""
+    key = hf.tobytes()
+    if key not in _L16_REF:
+        Hd = OH.build_dense(w.L, w.n_up, w.pbc, w.jxy, w.jz, hf)
+        _L16_REF[key] = (Hd, OX.eig(Hd))
+    Hd, eigsys = _L16_REF[key]
+    return OX.survival_probability(Hd, r0, times, eigsys=eigsys)
+
+
 def _neel_psi(b, L, dtype=torch.complex128, Bn=1):
     D = qk.qk_basis_dim(b)
     r0 = int(qk.qk_basis_rank(b, [OM.neel_state(L)])[0])
@@ -72,8 +86,7 @@ def test_workload_L16_to_t10():
     for s in range(n):
         qk.qk_krylov_expm_step(k, psi, w.dt)
         qk.qk_return_prob(b, psi, r0=r0, out=P[s:s + 1])
-    Hd = OH.build_dense(w.L, w.n_up, w.pbc, w.jxy, w.jz, hf)
-    F = OX.survival_probability(Hd, r0, w.dt * np.arange(1, n + 1))
+    F = _l16_workload_reference(w, hf, r0, w.dt * np.arange(1, n + 1))
     assert np.max(np.abs(to_host(P) - F)) < 1e-10
     assert abs(torch.linalg.vector_norm(psi).item() - 1.0) < 1e-12
 
@@ -182,18 +195,19 @@ def test_zero_and_nonfinite_vectors():
 
 
 def test_complex64_storage_path():
-    L = 16
-    b, H, hf = _problem(L, True)
-    psi, r0 = _neel_psi(b, L, torch.complex64)
-    k = qk.qk_krylov_create(H, 30, torch.complex64)
-    steps, dt = 50, 0.1
+    # the L = 16 workload in complex64 vectors (FP64 coefficients) against
+    # dense propagation
+    w = WORKLOADS["xxz_L16_pbc"]
+    b, H, hf = _problem(w.L, w.pbc, h=w.h, phi=w.phis()[0])
+    psi, r0 = _neel_psi(b, w.L, torch.complex64)
+    k = qk.qk_krylov_create(H, w.m, torch.complex64)
+    steps, dt = 50, w.dt
     P = torch.empty(steps, dtype=torch.float64, device="cuda")
     say("complex64 path")
     for s in range(steps):
         qk.qk_krylov_expm_step(k, psi, dt)
         qk.qk_return_prob(b, psi, r0=r0, out=P[s:s + 1])
-    Hd = OH.build_dense(L, L // 2, True, 1.0, 1.0, hf)
-    F = OX.survival_probability(Hd, r0, dt * np.arange(1, steps + 1))
+    F = _l16_workload_reference(w, hf, r0, dt * np.arange(1, steps + 1))
     err = np.max(np.abs(to_host(P) - F))
     say("complex64 max |dP| =", err)
     assert err < 1e-5
