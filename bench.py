@@ -69,6 +69,8 @@ def parse():
     ap.add_argument("--adaptive-tol", type=float, default=1e-7)
     ap.add_argument("--hv-reps", type=int, default=100)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="keep the default launch shapes instead of running the library's autotuner per form")
     ap.add_argument("--no-aux", action="store_true", help="skip the set-up, CSR and overlap timings")
     ap.add_argument("--csr-L", type=int, default=22, help="chain length of the CSR-versus-matrix-free H x timing")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU time of the oracle sample")
@@ -97,15 +99,18 @@ def source_sha():
     return h.hexdigest()
 
 
-def run_form(qk, torch, b, fields, m, dt, dtype, steps, warmup, r0, repeats, pbc=True):
+def run_form(qk, torch, b, fields, m, dt, dtype, steps, warmup, r0, repeats, pbc=True, tune=True):
     """Times `steps` Krylov steps (+ survival probability) after `warmup`:
     one run with HIP events around every kernel (per-kernel times), then
     `repeats` runs without events, each bracketed by device synchronisation;
-    the rate is the median of the latter."""
+    the rate is the median of the latter.  With `tune` the library's
+    autotuner picks the workspace's launch shape and block decomposition
+    first (outside the timed runs)."""
     D = qk.qk_basis_dim(b)
     B = fields.shape[0]
     H = qk.qk_ham_create(b, 1.0, 1.0, pbc, fields)
     k = qk.qk_krylov_create(H, m, dtype)
+    shape = qk.qk_krylov_autotune(k, dt) if tune else qk.qk_krylov_get_shape(k)
     psi = torch.zeros((D, B) if B > 1 else D, dtype=dtype, device="cuda")
     psi[r0] = 1.0
     P = torch.empty((steps + warmup, B), dtype=torch.float64, device="cuda")
@@ -133,7 +138,7 @@ def run_form(qk, torch, b, fields, m, dt, dtype, steps, warmup, r0, repeats, pbc
         secs.append(time.perf_counter() - t0)
     info = qk.qk_krylov_expm_step(k, psi, dt, info=True)
     norm = torch.linalg.vector_norm(psi.reshape(D, B).to(torch.complex128), dim=0).cpu().tolist()
-    out = dict(sec=statistics.median(secs), sec_all=secs, prof=prof, m_used=[i["m_used"] for i in info],
+    out = dict(sec=statistics.median(secs), sec_all=secs, prof=prof, shape=shape, m_used=[i["m_used"] for i in info],
                err_est=max(i["err_est"] for i in info), P_last=P[warmup + steps - 1].cpu().tolist(),
                norm_drift=max(abs(x - 1.0) for x in norm))
     del k, H, psi
@@ -142,7 +147,7 @@ def run_form(qk, torch, b, fields, m, dt, dtype, steps, warmup, r0, repeats, pbc
     return out
 
 
-def run_mixed(qk, torch, steps, warmup, repeats, m=30, dt=0.1, h=2.0):
+def run_mixed(qk, torch, steps, warmup, repeats, m=30, dt=0.1, h=2.0, tune=True):
     """The batched workload: 64 phases of the L = 20 ring and single rings of
     L = 16, 18, 20, 22 (h = 2, Neel state, complex64 vectors, FP64 Lanczos
     coefficients), one hipGraph replay per step for all of them; also the
@@ -155,6 +160,8 @@ def run_mixed(qk, torch, steps, warmup, repeats, m=30, dt=0.1, h=2.0):
         f = qk.qk_fields_quasiperiodic(L, h, BETA_GOLDEN, phases(Bn, seed))
         H = qk.qk_ham_create(b, 1.0, 1.0, True, f)
         k = qk.qk_krylov_create(H, m, torch.complex64)
+        if tune:
+            qk.qk_krylov_autotune(k, dt)
         D = qk.qk_basis_dim(b)
         r0 = int(qk.qk_basis_rank(b, [sum(1 << i for i in range(0, L, 2))])[0])
         psi = torch.zeros((D, Bn) if Bn > 1 else D, dtype=torch.complex64, device="cuda")
@@ -206,7 +213,7 @@ def run_large(qk, torch, args, L=30, m=20, dt=0.5, h=2.0):
     out = dict(workload=f"XXZ ring L={L} Sz=0 (D={D}), J=Delta=1, h={h} quasiperiodic, Neel state, m={m}, dt={dt}")
     for name, dtype, s in (("fp64", torch.complex128, 16), ("fp32", torch.complex64, 8)):
         log("large", name)
-        r = run_form(qk, torch, b, f, m, dt, dtype, args.large_steps, 1, r0, args.repeats)
+        r = run_form(qk, torch, b, f, m, dt, dtype, args.large_steps, 1, r0, args.repeats, tune=not args.no_tune)
         out[name] = dict(steps_per_s=round(args.large_steps / r["sec"], 3),
                          ms_per_step=round(1e3 * r["sec"] / args.large_steps, 2),
                          ms_per_step_runs=[round(1e3 * x / args.large_steps, 2) for x in r["sec_all"]],
@@ -554,16 +561,19 @@ def main():
     for f in forms:
         log("form", f)
         if f == "fp64":
-            res[f] = run_form(qk, torch, b, fields1, m, dt, torch.complex128, args.steps, args.warmup, r0, args.repeats)
+            res[f] = run_form(qk, torch, b, fields1, m, dt, torch.complex128, args.steps, args.warmup, r0, args.repeats,
+                              tune=not args.no_tune)
         elif f == "fp32":
-            res[f] = run_form(qk, torch, b, fields1, m, dt, torch.complex64, args.steps, args.warmup, r0, args.repeats)
+            res[f] = run_form(qk, torch, b, fields1, m, dt, torch.complex64, args.steps, args.warmup, r0, args.repeats,
+                              tune=not args.no_tune)
         elif f == "batched":
             fb = qk.qk_fields_quasiperiodic(L, args.h, BETA_GOLDEN, phases(args.batch, 0))
-            res[f] = run_form(qk, torch, b, fb, m, dt, torch.complex64, args.steps, args.warmup, r0, args.repeats)
+            res[f] = run_form(qk, torch, b, fb, m, dt, torch.complex64, args.steps, args.warmup, r0, args.repeats,
+                              tune=not args.no_tune)
         elif f == "adaptive":
             adaptive = run_adaptive(qk, torch, b, fields1, m, r0, args.adaptive_t, args.adaptive_tol)
         elif f == "mixed":
-            mixed = run_mixed(qk, torch, args.mixed_steps, 2, args.repeats)
+            mixed = run_mixed(qk, torch, args.mixed_steps, 2, args.repeats, tune=not args.no_tune)
         elif f == "large":
             large = run_large(qk, torch, args)
         else:
@@ -596,7 +606,7 @@ def main():
                     ms_per_step=round(1e3 * sec / steps_, 3),
                     ms_per_step_runs=[round(1e3 * x / steps_, 3) for x in r["sec_all"]],
                     step_algorithmic_GBps=round(step_bytes * steps_ / sec / 1e9, 1), kernels=kernels,
-                    roofline=hpass_roofline(r["prof"], m_, D_, B, s, None),
+                    roofline=hpass_roofline(r["prof"], m_, D_, B, s, None), launch_shape=r["shape"],
                     m_used=r["m_used"], err_est=r["err_est"], norm_drift=r["norm_drift"], P_last=r["P_last"])
 
     out = {

@@ -47,7 +47,7 @@
 extern "C" {
 #endif
 
-#define QK_ABI_VERSION 1
+#define QK_ABI_VERSION 2
 #define QK_MAX_L 64          /* states are 32-bit integers for L <= 32, 64-bit above */
 #define QK_MAX_M 64          /* Krylov dimension limit (one wavefront per projected problem) */
 #define QK_MAX_BATCH 64      /* problems per batched handle */
@@ -305,17 +305,32 @@ typedef struct {
   int32_t blocks_per_cu;       /* blocks per compute unit of the row-streaming kernels; 0 = 4 */
   int32_t blocked_wgs_per_cu;  /* work-groups per compute unit of the blocked H-pass;
                                   0 = as many as fit */
+  int32_t blocked_llo;         /* low bits of the block decomposition of the blocked
+                                  kernels (matrix-free, 18 <= L <= 32): 9..11 for one
+                                  phase; for batches 5..11 with the staged block of B
+                                  complex128 phases within 64 KB, the work-group's LDS
+                                  within the device limit and at most 2^20 blocks;
+                                  0 = keep */
 } qk_launch_shape;
 
 /* Sets / reads the launch shape of a workspace's kernels.  Results do not
- * depend on the shape beyond the order of floating-point reductions. */
+ * depend on the shape beyond the order of floating-point reductions.  A
+ * blocked_llo that differs from the Hamiltonian's rebuilds the Hamiltonian's
+ * block tables (synchronous, after all device work): every workspace and
+ * batch on that Hamiltonian then uses the new decomposition (batches capture
+ * their graph again); no work on the Hamiltonian may be in flight on other
+ * threads meanwhile.  QK_EINVAL for an unsupported low-bit count,
+ * QK_EUNSUPPORTED for a nonzero one on a Hamiltonian without block tables. */
 qk_status qk_krylov_set_shape(qk_krylov* k, const qk_launch_shape* shape);
 qk_status qk_krylov_get_shape(const qk_krylov* k, qk_launch_shape* shape);
 
 /*
  * Autotuner: times one step of the workspace (time step dt) for a small set
  * of launch shapes with HIP events on `stream`, on a scratch vector the call
- * allocates and frees, and applies the fastest.  With a non-NULL cache_path
+ * allocates and frees, and applies the fastest.  With block tables the search
+ * covers the low-bit count of the decomposition (three or four candidates
+ * around the default) and the blocked H-pass's work-groups per CU, then the
+ * row-streaming shape.  With a non-NULL cache_path
  * the result is looked up first and stored afterwards in that JSON file,
  * keyed by (L, n_up, boundary, batch, mode, dtype, m, reorth, compute units).
  * Synchronous.  *chosen (may be NULL) receives the shape.

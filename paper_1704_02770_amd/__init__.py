@@ -321,11 +321,14 @@ def qk_krylov_profile_read(k: Krylov) -> dict:
 
 
 def _shape_dict(sh: LaunchShape) -> dict:
-    return dict(threads=sh.threads, blocks_per_cu=sh.blocks_per_cu, blocked_wgs_per_cu=sh.blocked_wgs_per_cu)
+    return dict(threads=sh.threads, blocks_per_cu=sh.blocks_per_cu, blocked_wgs_per_cu=sh.blocked_wgs_per_cu,
+                blocked_llo=sh.blocked_llo)
 
 
-def qk_krylov_set_shape(k: Krylov, threads: int = 0, blocks_per_cu: int = 0, blocked_wgs_per_cu: int = 0) -> None:
-    sh = LaunchShape(threads, blocks_per_cu, blocked_wgs_per_cu)
+def qk_krylov_set_shape(k: Krylov, threads: int = 0, blocks_per_cu: int = 0, blocked_wgs_per_cu: int = 0,
+                        blocked_llo: int = 0) -> None:
+    """blocked_llo != 0 rebuilds the block tables of the workspace's Hamiltonian."""
+    sh = LaunchShape(threads, blocks_per_cu, blocked_wgs_per_cu, blocked_llo)
     _check(lib.qk_krylov_set_shape(k.ptr, C.byref(sh)), "qk_krylov_set_shape")
 
 

@@ -33,7 +33,7 @@ class KernelTime(C.Structure):
 
 
 class LaunchShape(C.Structure):
-    _fields_ = [("threads", i32), ("blocks_per_cu", i32), ("blocked_wgs_per_cu", i32)]
+    _fields_ = [("threads", i32), ("blocks_per_cu", i32), ("blocked_wgs_per_cu", i32), ("blocked_llo", i32)]
 
 
 class AdaptParams(C.Structure):

@@ -620,6 +620,7 @@ QK_API qk_status qk_krylov_get_shape(const qk_krylov* k, qk_launch_shape* shape)
   shape->threads = k->threads;
   shape->blocks_per_cu = k->blocks_per_cu;
   shape->blocked_wgs_per_cu = k->blocked_wgs;
+  shape->blocked_llo = k->H->llo;
   return QK_OK;
 }
 

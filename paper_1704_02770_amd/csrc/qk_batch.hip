@@ -131,6 +131,8 @@ static bool parse_shape(const std::string& obj, qk_launch_shape* sh) {
     *out = atoi(obj.c_str() + c + 1);
     return true;
   };
+  sh->blocked_llo = 0;
+  if (!field("\"blocked_llo\"", &sh->blocked_llo)) sh->blocked_llo = 0;   // absent in older caches: keep
   return field("\"threads\"", &sh->threads) && field("\"blocks_per_cu\"", &sh->blocks_per_cu) &&
          field("\"blocked_wgs_per_cu\"", &sh->blocked_wgs_per_cu);
 }
@@ -162,6 +164,19 @@ qk_status apply_shape(qk_krylov* k, const qk_launch_shape* sh) {
   if (sh->blocks_per_cu > 64 || sh->blocked_wgs_per_cu > 64) {
     set_error("per-CU counts must be <= 64");
     return QK_EINVAL;
+  }
+  if (sh->blocked_llo < 0) {
+    set_error("blocked_llo must be >= 0");
+    return QK_EINVAL;
+  }
+  if (sh->blocked_llo > 0 && sh->blocked_llo != k->H->llo) {
+    if (k->H->llo <= 0) {
+      set_error("this Hamiltonian has no block decomposition");
+      return QK_EUNSUPPORTED;
+    }
+    // the decomposition belongs to the Hamiltonian, which the workspace shares
+    const qk_status st = blocked_rebuild(const_cast<qk_ham*>(k->H), sh->blocked_llo);
+    if (st != QK_OK) return st;
   }
   k->threads = sh->threads;
   k->blocks_per_cu = sh->blocks_per_cu;
@@ -230,21 +245,26 @@ qk_status krylov_autotune(qk_krylov* k, double dt, const char* cache_path, hipSt
     }
   };
   const bool blocked = blocked_usable(k->H, k->dtype);
-  // coordinate search: work-groups of the blocked H-pass first, then the
-  // shape of the row-streaming kernels
+  const int llo0 = k->H->llo;
+  // coordinate search: the low-bit count of the block decomposition with the
+  // work-groups of the blocked H-pass first, then the shape of the
+  // row-streaming kernels
   if (blocked) {
-    for (int w : {2, 4, 6, 8}) {
-      cur = qk_launch_shape{0, 0, w};
-      trial(cur);
+    for (int llo = llo0 - 2; llo <= llo0 + 1; ++llo) {
+      if (!blocked_llo_valid(k->H, llo)) continue;
+      for (int w : {2, 4, 6, 8}) {
+        cur = qk_launch_shape{0, 0, w, llo};
+        trial(cur);
+      }
     }
   } else {
-    trial(qk_launch_shape{0, 0, 0});
+    trial(qk_launch_shape{0, 0, 0, 0});
   }
-  const int wbest = best.blocked_wgs_per_cu;
+  const int wbest = best.blocked_wgs_per_cu, lbest = best.blocked_llo;
   for (int t : {64, 128, 256})
     for (int c : {4, 8, 16}) {
       if (t < k->batch) continue;
-      cur = qk_launch_shape{t, c, wbest};
+      cur = qk_launch_shape{t, c, wbest, lbest};
       trial(cur);
     }
   k->profiling = prof;
@@ -258,8 +278,10 @@ qk_status krylov_autotune(qk_krylov* k, double dt, const char* cache_path, hipSt
   if (cache_path && *cache_path) {
     auto m = read_cache(cache_path);
     char obj[256];
-    snprintf(obj, sizeof obj, "{\"threads\": %d, \"blocks_per_cu\": %d, \"blocked_wgs_per_cu\": %d, \"ms_per_step\": %.4f}",
-             best.threads, best.blocks_per_cu, best.blocked_wgs_per_cu, best_ms);
+    snprintf(obj, sizeof obj,
+             "{\"threads\": %d, \"blocks_per_cu\": %d, \"blocked_wgs_per_cu\": %d, \"blocked_llo\": %d, "
+             "\"ms_per_step\": %.4f}",
+             best.threads, best.blocks_per_cu, best.blocked_wgs_per_cu, best.blocked_llo, best_ms);
     m[key] = obj;
     if (!write_cache(cache_path, m)) {
       set_error(std::string("could not write the tuning cache ") + cache_path);
@@ -294,6 +316,7 @@ struct qk_batch {
   double graph_dt = NAN;
   double* graph_P = nullptr;
   double* graph_C = nullptr;
+  std::vector<uint64_t> graph_sig;  // launch configuration the graph was captured with
 };
 
 namespace qk {
@@ -419,6 +442,22 @@ static qk_status batch_step(qk_batch* b, double dt, double* P, double* C, hipStr
   return QK_OK;
 }
 
+// What a captured step depends on besides dt and the output arrays: each
+// workspace's launch shape and its Hamiltonian's table generation (a rebuilt
+// block decomposition frees the tables the old graph points to).
+static std::vector<uint64_t> batch_signature(const qk_batch* b) {
+  std::vector<uint64_t> sig;
+  for (const qk_krylov* k : b->ks) {
+    sig.push_back(k->H->tables_gen);
+    sig.push_back((uint64_t)k->H->llo);
+    sig.push_back((uint64_t)k->threads);
+    sig.push_back((uint64_t)k->blocks_per_cu);
+    sig.push_back((uint64_t)k->blocked_wgs);
+    sig.push_back((uint64_t)k->grid);
+  }
+  return sig;
+}
+
 qk_status batch_run(qk_batch* b, double dt, int n_steps, int use_graph, double* P, double* C, hipStream_t s) {
   std::vector<bool> prof(b->ks.size());
   for (size_t i = 0; i < b->ks.size(); ++i) {
@@ -440,7 +479,8 @@ qk_status batch_run(qk_batch* b, double dt, int n_steps, int use_graph, double* 
     restore();
     return st;
   }
-  if (!b->exec || b->graph_dt != dt || b->graph_P != P || b->graph_C != C) {
+  const std::vector<uint64_t> sig = batch_signature(b);
+  if (!b->exec || b->graph_dt != dt || b->graph_P != P || b->graph_C != C || b->graph_sig != sig) {
     batch_release(b);
     hipError_t e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) {
@@ -465,6 +505,7 @@ qk_status batch_run(qk_batch* b, double dt, int n_steps, int use_graph, double* 
     b->graph_dt = dt;
     b->graph_P = P;
     b->graph_C = C;
+    b->graph_sig = sig;
   }
   for (int k = 0; k < n_steps; ++k) {
     hipError_t e = hipGraphLaunch(b->exec, s);

@@ -677,6 +677,53 @@ qk_status launch_blocked_fields(qk_ham* H, hipStream_t s) {
   return QK_OK;
 }
 
+bool blocked_llo_valid(const qk_ham* H, int llo) {
+  const int L = H->basis->L, B = H->batch;
+  if (H->llo <= 0 || H->p.mode != QK_MATFREE || L < 18 || L > 32 || llo > L / 2) return false;
+  if (B == 1) return llo >= 9 && llo <= 11;
+  if (llo < 5 || llo > 11 || L - llo > 20 || binom_host(llo, llo / 2) * (uint64_t)B * 16u > 65536u) return false;
+  // the batched kernel's dynamic LDS (staged block of B complex128 phases,
+  // low tables, fields) must fit one work-group
+  const size_t dyn = blkb_xbytes((uint32_t)binom_host(llo, llo / 2), B, 16) + ((((size_t)4 << llo) + 15) & ~(size_t)15) +
+                     sizeof(double) * ((size_t)B * L + 2 * (size_t)B);
+  int lim = 0;
+  if (hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, H->device) != hipSuccess) return false;
+  return dyn <= (size_t)lim;
+}
+
+qk_status blocked_rebuild(qk_ham* H, int llo) {
+  if (!blocked_llo_valid(H, llo)) {
+    set_error("unsupported low-bit count for this Hamiltonian's block decomposition");
+    return QK_EINVAL;
+  }
+  if (llo == H->llo) return QK_OK;
+  QK_HIP(hipDeviceSynchronize());   // no queued kernel may still read the old tables
+  const int old = H->llo;
+  auto drop = [&]() {
+    dev_free(H->al, H->d_lo_state);
+    dev_free(H->al, H->d_lo_rank);
+    dev_free(H->al, H->d_blk);
+    H->d_lo_state = nullptr;
+    H->d_lo_rank = nullptr;
+    H->d_blk = nullptr;
+    H->nblk = 0;
+  };
+  drop();
+  H->llo = llo;
+  ++H->tables_gen;
+  qk_status st = launch_blocked_build(H, nullptr);
+  if (st != QK_OK) {
+    // back to the previous decomposition, or to the row-form kernels
+    drop();
+    H->llo = old;
+    if (launch_blocked_build(H, nullptr) != QK_OK) {
+      drop();
+      H->llo = 0;
+    }
+  }
+  return st;
+}
+
 bool blocked_usable(const qk_ham* H, int dtype) {
   // the single-phase kernel addresses vectors with 32-bit byte offsets
   const uint64_t bytes = (uint64_t)H->basis->D * (dtype == QK_C128 ? 16u : 8u);

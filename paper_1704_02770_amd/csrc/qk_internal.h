@@ -104,6 +104,7 @@ struct qk_ham {
   uint16_t* d_lo_rank = nullptr;  // [2^llo]
   void* d_blk = nullptr;          // [nblk] block entries (high bits, first row, ring-partner first row)
   int nblk = 0;
+  uint64_t tables_gen = 0;        // incremented whenever the block tables are rebuilt
   // two-pass high/low split (one field set, 18 <= L <= 32): tables of qk_split.hip
   void* split = nullptr;
 };
@@ -180,6 +181,10 @@ qk_status launch_blocked_build(qk_ham* H, hipStream_t s);
 qk_status launch_blocked_apply(const qk_ham* H, const void* x, void* y, int dtype, hipStream_t s);
 qk_status launch_blocked_fields(qk_ham* H, hipStream_t s);
 bool blocked_usable(const qk_ham* H, int dtype);
+// Valid low-bit counts of the block decomposition for this Hamiltonian
+// (empty without block tables), and a rebuild of the tables at another one.
+bool blocked_llo_valid(const qk_ham* H, int llo);
+qk_status blocked_rebuild(qk_ham* H, int llo);
 // two-pass high/low split (qk_split.hip)
 qk_status split_build(qk_ham* H, hipStream_t s);   // no-op unless one field set, matrix-free, 18 <= L <= 32
 qk_status split_fields(qk_ham* H, hipStream_t s);

@@ -49,7 +49,7 @@ def test_binding_covers_every_symbol():
 def test_version_and_validation_without_device():
     import paper_1704_02770_amd as qk
     from paper_1704_02770_amd._native import lib
-    assert qk.qk_abi_version() == 1
+    assert qk.qk_abi_version() == 2
     out = C.c_void_p()
     assert lib.qk_basis_build(65, 2, None, C.byref(out)) == qk.QK_EINVAL
     assert b"L must be" in lib.qk_last_error()

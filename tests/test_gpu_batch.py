@@ -179,6 +179,75 @@ def test_autotune_keeps_results_and_caches(tmp_path, L, Bn, dtype):
         qk.qk_krylov_set_shape(w2["k"], blocks_per_cu=-1)
 
 
+def test_block_decomposition_is_tunable(monkeypatch):
+    # the low-bit count of the block decomposition (set by hand or by the
+    # autotuner) changes only the order of the sums: H x and Krylov steps
+    # agree to rounding for every valid count; a batch captured before the
+    # change captures its graph again; invalid counts are rejected
+    L = 20
+    b = qk.qk_basis_build(L, L // 2)
+    hf = OM.fields(L, 1.5, BETA_GOLDEN, 0.3)
+    H = qk.qk_ham_create(b, 1.0, 1.0, True, hf)
+    D = qk.qk_basis_dim(b)
+    k = qk.qk_krylov_create(H, 30)
+    assert qk.qk_krylov_get_shape(k)["blocked_llo"] == 10   # at most L / 2
+    x = torch.from_numpy(random_complex(D, 3)).to("cuda")
+    r0 = neel_row(L)
+    psi0 = torch.zeros(D, dtype=torch.complex128, device="cuda")
+    psi0[r0] = 1.0
+    ref_y = ref_psi = None
+    for llo in (10, 9):
+        say("block decomposition", llo)
+        qk.qk_krylov_set_shape(k, blocked_llo=llo)
+        assert qk.qk_krylov_get_shape(k)["blocked_llo"] == llo
+        y = to_host(qk.qk_ham_apply(H, x))
+        psi = psi0.clone()
+        for _ in range(5):
+            qk.qk_krylov_expm_step(k, psi, 0.1)
+        if ref_y is None:
+            ref_y, ref_psi = y, to_host(psi)
+        assert max_rel(y, ref_y) < 1e-14 and max_rel(to_host(psi), ref_psi) < 1e-12
+    # a batch graph captured at llo = 9, the decomposition changed, replayed
+    psi = psi0.clone()
+    bt = qk.qk_batch_create([k], [psi], [r0])
+    P1 = to_host(qk.qk_batch_run(bt, 0.1, 3, use_graph=True))
+    qk.qk_krylov_set_shape(k, blocked_llo=10)
+    P2 = to_host(qk.qk_batch_run(bt, 0.1, 3, use_graph=True))
+    psi_chk = psi0.clone()
+    P_ref = []
+    for _ in range(6):
+        qk.qk_krylov_expm_step(k, psi_chk, 0.1)
+        P_ref.append(abs(psi_chk[r0].item()) ** 2)
+    assert max_rel(to_host(psi), to_host(psi_chk)) < 1e-12
+    assert np.max(np.abs(np.concatenate([P1[:, 0], P2[:, 0]]) - np.array(P_ref))) < 1e-12
+    for bad in (8, 11, -1):
+        with pytest.raises(qk.QkError):
+            qk.qk_krylov_set_shape(k, blocked_llo=bad)
+    assert qk.qk_krylov_get_shape(k)["blocked_llo"] == 10
+    # batches: the staged block of B complex128 phases must fit 64 KB
+    hb = np.stack([OM.fields(L, 2.0, BETA_GOLDEN, p) for p in phases(8, 1)])
+    Hb = qk.qk_ham_create(b, 1.0, 1.0, True, hb)
+    kb = qk.qk_krylov_create(Hb, 30, torch.complex64)
+    llo_b = qk.qk_krylov_get_shape(kb)["blocked_llo"]
+    xb = torch.from_numpy(random_complex(D * 8, 4).reshape(D, 8)).to(device="cuda", dtype=torch.complex64)
+    yb = to_host(qk.qk_ham_apply(Hb, xb))
+    qk.qk_krylov_set_shape(kb, blocked_llo=llo_b - 1)
+    assert max_rel(to_host(qk.qk_ham_apply(Hb, xb)), yb) < 2e-6
+    with pytest.raises(qk.QkError):
+        qk.qk_krylov_set_shape(kb, blocked_llo=11)   # above L / 2
+    h64 = np.stack([OM.fields(L, 2.0, BETA_GOLDEN, p) for p in phases(64, 1)])
+    k64 = qk.qk_krylov_create(qk.qk_ham_create(b, 1.0, 1.0, True, h64), 30, torch.complex64)
+    assert qk.qk_krylov_get_shape(k64)["blocked_llo"] == 6
+    with pytest.raises(qk.QkError):
+        qk.qk_krylov_set_shape(k64, blocked_llo=8)   # 70 rows x 64 phases x 16 B > 64 KB
+    # no block tables (row-form Hamiltonian): only 0 is accepted
+    Hr = qk.qk_ham_create(b, 1.0, 1.0, True, hf, qk.QK_MATFREE_ROWS)
+    kr = qk.qk_krylov_create(Hr, 30)
+    assert qk.qk_krylov_get_shape(kr)["blocked_llo"] == 0
+    with pytest.raises(qk.QkError):
+        qk.qk_krylov_set_shape(kr, blocked_llo=10)
+
+
 def _random_states(D, Bn, seed, dtype):
     z = random_complex(D * Bn, seed).reshape(D, Bn) if Bn > 1 else random_complex(D, seed)
     z = z / np.linalg.norm(z, axis=0)
