@@ -152,9 +152,15 @@ typedef struct qk_ham qk_ham;
  * Hamiltonian of Eq. (1) on basis `b` (Sec. 3, "Hamiltonian matrix
  * construction") for `batch` field sets h_host[batch][L] (host doubles,
  * copied).  QK_MATFREE generates every row on the fly in the apply kernels;
- * for L >= 18 and a single field set it processes blocks of states sharing
- * their high bits (low-bit tables and a block list are built here), otherwise
- * one row per thread from the stored basis.  QK_MATFREE_ROWS always uses the
+ * for 18 <= L <= 32 it processes blocks of states sharing their high bits
+ * (low-bit tables and a block list are built here; one field set or a
+ * batch), otherwise one row per thread from the stored basis.  With the
+ * environment variable QK_SPLIT=1 set at this call, a single-field-set
+ * Hamiltonian also builds the tables of the two-pass split (high bonds over
+ * column slabs, then low bonds with the Lanczos update; vectors in a padded
+ * workspace layout), which its reorthogonalisation-free complex workspaces
+ * then use: exact, and slower than the one-pass form on MI355X at L = 28, so
+ * off by default.  QK_MATFREE_ROWS always uses the
  * one-row-per-thread form (an independent second formulation).  QK_CSR
  * stores the column indices of the off-diagonal entries after an exact
  * counting pass (the exact preallocation of Sec. 3); allowed for D <= 2^24.
