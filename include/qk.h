@@ -191,11 +191,11 @@ qk_status qk_ham_shape(const qk_ham* H, int64_t* D, int32_t* batch, int32_t* mod
  * matrix-free modes).  For every batch item (problem k uses field set k):
  * x, y are [D][B] device arrays of `dtype`; x and y must not overlap
  * (QK_EINVAL).  QK_C128 accumulates in double, QK_C64 in float.  Matrix-free
- * Hamiltonians with 18 <= L <= 32 use the blocked kernels, which address a
- * single-phase vector with 32-bit byte offsets: they run while D times the
- * element size is below 2^32 bytes (every half-filled chain up to L = 30 in
- * both dtypes); larger vectors take the row-form kernels (same results,
- * slower).  The same choice applies to the Lanczos H-pass of every workspace.
+ * Hamiltonians with 18 <= L <= 32 use the blocked kernels; a single-phase
+ * vector below 4 GB is addressed with 32-bit byte offsets, a larger one
+ * (the half-filled L = 32 chain) with 64-bit element offsets, which needs the
+ * 11-bit block decomposition (the default there; QK_EUNSUPPORTED for another
+ * one).  The same choice applies to the Lanczos H-pass of every workspace.
  */
 qk_status qk_ham_apply(const qk_ham* H, const void* x, void* y, int32_t dtype, void* stream);
 

@@ -139,30 +139,37 @@ constexpr size_t blk_xbytes() {
   return b > kQA * kBlkThreads * sizeof(double) ? b : kQA * kBlkThreads * sizeof(double);
 }
 
-// Element idx of a vector through a 32-bit byte offset from a uniform base
-// (the launcher guarantees D * sizeof(V) < 2^32).
-template <typename V>
+// Element idx of a vector from a uniform base: through a 32-bit byte offset
+// (the common case, D * sizeof(V) < 2^32: one VGPR per address), or through
+// a 64-bit element offset for larger vectors (W64).
+template <bool W64, typename V>
+__device__ __forceinline__ const V* elem(const V* base, uint32_t idx) {
+  if (W64) return base + (size_t)idx;
+  return reinterpret_cast<const V*>(reinterpret_cast<const char*>(base) + idx * (uint32_t)sizeof(V));
+}
+template <bool W64, typename V>
+__device__ __forceinline__ V* elem(V* base, uint32_t idx) {
+  if (W64) return base + (size_t)idx;
+  return reinterpret_cast<V*>(reinterpret_cast<char*>(base) + idx * (uint32_t)sizeof(V));
+}
+template <typename V, bool W64 = false>
 __device__ __forceinline__ V ld32(const V* __restrict__ base, uint32_t idx) {
-  return *reinterpret_cast<const V*>(reinterpret_cast<const char*>(base) + idx * (uint32_t)sizeof(V));
+  return *elem<W64>(base, idx);
 }
-template <typename V>
-__device__ __forceinline__ void st32(V* __restrict__ base, uint32_t idx, V v) {
-  *reinterpret_cast<V*>(reinterpret_cast<char*>(base) + idx * (uint32_t)sizeof(V)) = v;
-}
-// Non-temporal forms of the two above, for data read or written once per pass.
-template <typename V>
+// Non-temporal forms, for data read or written once per pass.
+template <typename V, bool W64 = false>
 __device__ __forceinline__ V ld32_stream(const V* __restrict__ base, uint32_t idx) {
   using S = decltype(V{}.x);
   typedef S E __attribute__((ext_vector_type(2)));
-  const E* p = reinterpret_cast<const E*>(reinterpret_cast<const char*>(base) + idx * (uint32_t)sizeof(V));
+  const E* p = reinterpret_cast<const E*>(elem<W64>(base, idx));
   const E e = __builtin_nontemporal_load(p);
   return V{e.x, e.y};
 }
-template <typename V>
+template <typename V, bool W64 = false>
 __device__ __forceinline__ void st32_stream(V* __restrict__ base, uint32_t idx, V v) {
   using S = decltype(V{}.x);
   typedef S E __attribute__((ext_vector_type(2)));
-  E* p = reinterpret_cast<E*>(reinterpret_cast<char*>(base) + idx * (uint32_t)sizeof(V));
+  E* p = reinterpret_cast<E*>(elem<W64>(base, idx));
   const E e = {v.x, v.y};
   __builtin_nontemporal_store(e, p);
 }
@@ -181,7 +188,7 @@ constexpr int blk_min_blocks() {
   return std::is_same<T, float>::value ? 6 : 1;
 }
 
-template <typename T, int LLO, bool LANCZOS>
+template <typename T, int LLO, bool LANCZOS, bool W64 = false>
 __global__ void __launch_bounds__(kBlkThreads, blk_min_blocks<T>())
 k_blk(BlkArgs ba, const typename Cx<T>::V* __restrict__ x, typename Cx<T>::V* __restrict__ y,
       const typename Cx<T>::V* __restrict__ ujm1, KState st, LanczosArgs la, const double* __restrict__ partB, int Gp,
@@ -252,7 +259,7 @@ k_blk(BlkArgs ba, const typename Cx<T>::V* __restrict__ x, typename Cx<T>::V* __
     const BlkEntry* ep = ba.blk + bi;
     const uint32_t len = sbin[LLO * kBinomStride + (ba.N - __popc(ep->a))];
     const uint32_t off = ep->off;
-    for (uint32_t i = tid; i < len; i += kBlkThreads) xsb[i] = ld32(x, off + i);
+    for (uint32_t i = tid; i < len; i += kBlkThreads) xsb[i] = ld32<V, W64>(x, off + i);
     if (tid < kMaxHi) hds[0][tid] = ep->delta[tid];
   }
   __syncthreads();
@@ -283,24 +290,24 @@ k_blk(BlkArgs ba, const typename Cx<T>::V* __restrict__ x, typename Cx<T>::V* __
       // add no cache lines to the wave's request.
       const V z = {0, 0};
       V um = z;
-      if (prev) um = ld32_stream(ujm1, r);
+      if (prev) um = ld32_stream<V, W64>(ujm1, r);
       const uint32_t bl = (b >> (LLO - 1)) & 1u;
       const bool cx = (bl ^ (a & 1u)) != 0u;
       const uint32_t pcl = (uint32_t)__popc(b & ((1u << (LLO - 1)) - 1u));
       const uint32_t cc = sbin[(LLO - 1) * kBinomStride + pcl];
       V vc = z;
-      if (cx) vc = ld32(x, bl ? r + cc : r - cc);
+      if (cx) vc = ld32<V, W64>(x, bl ? r + cc : r - cc);
       const bool wx = ba.pbc && ((b & 1u) != top);
       V vw = z;
-      if (wx) vw = ld32(x, offw + lo_rank[b ^ 1u]);
+      if (wx) vw = ld32<V, W64>(x, offw + lo_rank[b ^ 1u]);
       // high bonds: uniform row shifts, contiguous runs of the partner blocks,
       // four loads at a time; slots beyond the block's active bonds are skipped
       // by a uniform test and contribute zero.  The first group is issued
       // before the in-block LDS work and consumed after it.
-      const V q0 = (0 < nact) ? ld32(x, r + (uint32_t)hd[0]) : z;
-      const V q1 = (1 < nact) ? ld32(x, r + (uint32_t)hd[1]) : z;
-      const V q2 = (2 < nact) ? ld32(x, r + (uint32_t)hd[2]) : z;
-      const V q3 = (3 < nact) ? ld32(x, r + (uint32_t)hd[3]) : z;
+      const V q0 = (0 < nact) ? ld32<V, W64>(x, r + (uint32_t)hd[0]) : z;
+      const V q1 = (1 < nact) ? ld32<V, W64>(x, r + (uint32_t)hd[1]) : z;
+      const V q2 = (2 < nact) ? ld32<V, W64>(x, r + (uint32_t)hd[2]) : z;
+      const V q3 = (3 < nact) ? ld32<V, W64>(x, r + (uint32_t)hd[3]) : z;
       // in-block work from LDS
       const V xr = xs[j];
       const int anti = __popc((b ^ (b >> 1)) & ((1u << (LLO - 1)) - 1u)) + (cx ? 1 : 0) + (wx ? 1 : 0);
@@ -325,10 +332,10 @@ k_blk(BlkArgs ba, const typename Cx<T>::V* __restrict__ x, typename Cx<T>::V* __
         hs.y += w0 * q0.y + w1 * q1.y + w2 * q2.y + w3 * q3.y;
       }
       for (int g0 = 4; g0 < nact; g0 += 4) {
-        const V v0 = ld32(x, r + (uint32_t)hd[g0]);
-        const V v1 = (g0 + 1 < nact) ? ld32(x, r + (uint32_t)hd[g0 + 1]) : z;
-        const V v2 = (g0 + 2 < nact) ? ld32(x, r + (uint32_t)hd[g0 + 2]) : z;
-        const V v3 = (g0 + 3 < nact) ? ld32(x, r + (uint32_t)hd[g0 + 3]) : z;
+        const V v0 = ld32<V, W64>(x, r + (uint32_t)hd[g0]);
+        const V v1 = (g0 + 1 < nact) ? ld32<V, W64>(x, r + (uint32_t)hd[g0 + 1]) : z;
+        const V v2 = (g0 + 2 < nact) ? ld32<V, W64>(x, r + (uint32_t)hd[g0 + 2]) : z;
+        const V v3 = (g0 + 3 < nact) ? ld32<V, W64>(x, r + (uint32_t)hd[g0 + 3]) : z;
         const T w1 = (g0 + 1 < nact) ? (T)1 : (T)0;
         const T w2 = (g0 + 2 < nact) ? (T)1 : (T)0;
         const T w3 = (g0 + 3 < nact) ? (T)1 : (T)0;
@@ -344,21 +351,21 @@ k_blk(BlkArgs ba, const typename Cx<T>::V* __restrict__ x, typename Cx<T>::V* __
         V wv;
         wv.x = ca * h.x - cb * um.x;
         wv.y = ca * h.y - cb * um.y;
-        st32_stream(y, r, wv);
+        st32_stream<V, W64>(y, r, wv);
         s1 += (double)xr.x * (double)wv.x + (double)xr.y * (double)wv.y;
         s2 += (double)xr.x * (double)xr.x + (double)xr.y * (double)xr.y;
         s3r += (double)um.x * (double)wv.x + (double)um.y * (double)wv.y;
         s3i += (double)um.x * (double)wv.y - (double)um.y * (double)wv.x;
       } else {
-        st32_stream(y, r, h);
+        st32_stream<V, W64>(y, r, h);
       }
     }
     if (has_next) {
       const BlkEntry* en = ba.blk + nbi;
       nlen = sbin[LLO * kBinomStride + (ba.N - __popc(en->a))];
       const uint32_t noff = en->off;
-      if ((uint32_t)tid < nlen) p0 = ld32(x, noff + tid);
-      if ((uint32_t)tid + kBlkThreads < nlen) p1 = ld32(x, noff + tid + kBlkThreads);
+      if ((uint32_t)tid < nlen) p0 = ld32<V, W64>(x, noff + tid);
+      if ((uint32_t)tid + kBlkThreads < nlen) p1 = ld32<V, W64>(x, noff + tid + kBlkThreads);
       if (tid < kMaxHi) nd = en->delta[tid];
     }
     if (has_next) {
@@ -725,9 +732,10 @@ qk_status blocked_rebuild(qk_ham* H, int llo) {
 }
 
 bool blocked_usable(const qk_ham* H, int dtype) {
-  // the single-phase kernel addresses vectors with 32-bit byte offsets
+  // the single-phase kernel addresses vectors below 4 GB with 32-bit byte
+  // offsets and larger ones (11 low bits) with 64-bit element offsets
   const uint64_t bytes = (uint64_t)H->basis->D * (dtype == QK_C128 ? 16u : 8u);
-  return H->llo > 0 && (H->batch > 1 || bytes < (1ull << 32));
+  return H->llo > 0 && (H->batch > 1 || bytes < (1ull << 32) || H->llo == 11);
 }
 
 template <typename T, bool LANCZOS>
@@ -764,14 +772,14 @@ static qk_status launch_blkb_t(const qk_ham* H, const void* x, void* y, const vo
   return QK_OK;
 }
 
-template <typename T, int LLO, bool LANCZOS>
-static qk_status launch_blk_t(const qk_ham* H, const void* x, void* y, const void* ujm1, const KState* st,
+template <typename T, int LLO, bool LANCZOS, bool W64>
+static qk_status launch_blk_k(const qk_ham* H, const void* x, void* y, const void* ujm1, const KState* st,
                               const LanczosArgs* la, const double* partB, int Gp, double* partA, int* grid_out,
                               int wgs_req, hipStream_t s) {
   using V = typename Cx<T>::V;
   BlkArgs ba = blk_args(H);
   const size_t dyn = blk_xbytes<T, LLO>() + 2 * sizeof(uint16_t) * ((size_t)1 << LLO);
-  auto kern = k_blk<T, LLO, LANCZOS>;
+  auto kern = k_blk<T, LLO, LANCZOS, W64>;
   // work-groups per CU the kernel can hold (queried once per instantiation; thread-safe static init)
   static const int occ = [&]() {
     int n = 0;
@@ -798,6 +806,24 @@ static qk_status launch_blk_t(const qk_ham* H, const void* x, void* y, const voi
   QK_HIP(hipGetLastError());
   if (grid_out) *grid_out = G;
   return QK_OK;
+}
+
+// Vectors of 4 GB or more (the half-filled L = 32 chain) take 64-bit element
+// offsets; they always have 11 low bits (L >= 22).  QK_BLOCKED_W64=1 selects
+// the 64-bit form for smaller vectors too (same arithmetic, so the same bits).
+template <typename T, int LLO, bool LANCZOS>
+static qk_status launch_blk_t(const qk_ham* H, const void* x, void* y, const void* ujm1, const KState* st,
+                              const LanczosArgs* la, const double* partB, int Gp, double* partA, int* grid_out,
+                              int wgs_req, hipStream_t s) {
+  using V = typename Cx<T>::V;
+  const char* fw = getenv("QK_BLOCKED_W64");
+  const bool force = fw && fw[0] == '1' && LLO == 11;
+  if ((uint64_t)H->basis->D * sizeof(V) < (1ull << 32) && !force)
+    return launch_blk_k<T, LLO, LANCZOS, false>(H, x, y, ujm1, st, la, partB, Gp, partA, grid_out, wgs_req, s);
+  if constexpr (LLO == 11)
+    return launch_blk_k<T, LLO, LANCZOS, true>(H, x, y, ujm1, st, la, partB, Gp, partA, grid_out, wgs_req, s);
+  set_error("vectors of 4 GB or more need the 11-bit block decomposition");
+  return QK_EUNSUPPORTED;
 }
 
 template <typename T, bool LANCZOS>

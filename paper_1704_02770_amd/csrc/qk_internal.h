@@ -186,7 +186,7 @@ bool blocked_usable(const qk_ham* H, int dtype);
 bool blocked_llo_valid(const qk_ham* H, int llo);
 qk_status blocked_rebuild(qk_ham* H, int llo);
 // two-pass high/low split (qk_split.hip)
-qk_status split_build(qk_ham* H, hipStream_t s);   // no-op unless one field set, matrix-free, 18 <= L <= 32
+qk_status split_build(qk_ham* H, hipStream_t s);   // no-op unless QK_SPLIT=1, one field set, matrix-free, 18 <= L <= 30
 qk_status split_fields(qk_ham* H, hipStream_t s);
 void split_free(qk_ham* H);
 bool split_usable(const qk_ham* H);

@@ -705,7 +705,9 @@ qk_status split_build(qk_ham* H, hipStream_t s) {
   const qk_basis* bs = H->basis;
   const int L = bs->L, N = bs->N;
   if (!split_enabled()) return QK_OK;
-  if (H->batch != 1 || H->p.mode != QK_MATFREE || L < 18 || L > 32 || bs->wide) return QK_OK;
+  // its kernels address the padded vectors with 32-bit byte offsets:
+  // complex128 vectors of the half-filled L = 30 chain (2.5 GB) are the largest
+  if (H->batch != 1 || H->p.mode != QK_MATFREE || L < 18 || L > 30 || bs->wide) return QK_OK;
   static const HostBinom hb;
   SplitTables* t = new (std::nothrow) SplitTables();
   if (!t) {

@@ -330,3 +330,55 @@ def test_zz_chain_short_time_amplitudes_vs_moments(L, m, t):
             assert abs(g - w) < tol, (L, dtype, s, g, w)
         del k, psi
         torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("dtype", [torch.complex128, torch.complex64])
+def test_blocked_64bit_offsets_same_bits(monkeypatch, dtype):
+    # vectors of 4 GB or more take 64-bit element offsets in the blocked
+    # kernel; forced at L = 24 the same arithmetic gives the same bits
+    L = 24
+    b = qk.qk_basis_build(L, L // 2)
+    H = qk.qk_ham_create(b, 1.0, 1.0, True, OM.fields(L, 1.5, BETA_GOLDEN, PHI))
+    D = qk.qk_basis_dim(b)
+    x = torch.from_numpy(np.random.default_rng(2).standard_normal(D) + 0j).to(device="cuda", dtype=dtype)
+    r0 = _neel_row(b, L)
+    out = {}
+    for w64 in ("0", "1"):
+        monkeypatch.setenv("QK_BLOCKED_W64", w64)
+        say("blocked 64-bit offsets", w64, dtype)
+        y = to_host(qk.qk_ham_apply(H, x))
+        k = qk.qk_krylov_create(H, 30, dtype)
+        psi = torch.zeros(D, dtype=dtype, device="cuda")
+        psi[r0] = 1.0
+        for _ in range(3):
+            qk.qk_krylov_expm_step(k, psi, 0.1)
+        out[w64] = (y, to_host(psi))
+    assert np.array_equal(out["0"][0], out["1"][0]) and np.array_equal(out["0"][1], out["1"][1])
+
+
+def test_l32_complex64_free_fermions():
+    # the half-filled L = 32 ring (D = 601,080,390) in complex64 storage: its
+    # vectors (4.8 GB) take the blocked kernel's 64-bit offsets; zz coupling 0,
+    # four Krylov steps against the free-fermion determinant
+    L, m, dt = 32, 20, 0.05
+    b = qk.qk_basis_build(L, L // 2)
+    D = qk.qk_basis_dim(b)
+    assert D == math.comb(32, 16)
+    hf = OM.fields(L, 2.0, BETA_GOLDEN, PHI)
+    H = qk.qk_ham_create(b, 1.0, 0.0, True, hf)
+    r0 = _neel_row(b, L)
+    k = qk.qk_krylov_create(H, m, torch.complex64)
+    psi = torch.zeros(D, dtype=torch.complex64, device="cuda")
+    psi[r0] = 1.0
+    P = []
+    say("L32 complex64 free fermions")
+    for _ in range(4):
+        qk.qk_krylov_expm_step(k, psi, dt)
+        P.append(abs(psi[r0].item()) ** 2)
+    ref = OF.survival_probability(L, L // 2, True, 1.0, hf, OM.neel_state(L), dt * np.arange(1, 5))
+    err = np.max(np.abs(np.array(P) - ref))
+    say("  max |dP| =", err, "P =", P)
+    assert err < 2e-6
+    assert abs(torch.linalg.vector_norm(psi.to(torch.complex128)).item() - 1.0) < 1e-5
+    del k, psi
+    torch.cuda.empty_cache()
