@@ -57,7 +57,7 @@ typedef enum {
   QK_EINVAL = 1,        /* bad argument; nothing was enqueued */
   QK_ENOMEM = 2,        /* device allocation failed */
   QK_EHIP = 3,          /* a HIP runtime call failed (text in qk_last_error) */
-  QK_EUNSUPPORTED = 4,  /* valid request outside what this build implements */
+  QK_EUNSUPPORTED = 4,  /* valid request outside what the library implements */
   QK_ENUMERIC = 5       /* non-finite Lanczos coefficient, or an adaptive evolution that could not reach t */
 } qk_status;
 

@@ -63,59 +63,55 @@ static GaussRule gauss_legendre() {
   return g;
 }
 
-// C~_cd = sigma'_c sigma_d C_cd for the stored (unnormalised) basis vectors,
-// C = integral_0^dt conj(q(tau)) p(tau)^T dtau.  One wavefront; lane i owns
-// component i of p and q; C is accumulated in LDS.
+// C = integral_0^dt conj(q(tau)) p(tau)^T dtau by the Gauss rule: block n
+// (one wavefront; lane i owns component i of p and q) evaluates node n and
+// writes its weighted term w_n conj(q_c) p_d to Cn[n][c][d] (complex).
 __global__ void __launch_bounds__(64)
-k_grad_coeffs(KState fw, KState bw, double dt, GaussRule gr, double* __restrict__ Ct) {
-  __shared__ double Cr[kGradMaxM][kGradMaxM], Ci[kGradMaxM][kGradMaxM];
+k_grad_nodes(KState fw, KState bw, double dt, GaussRule gr, double* __restrict__ Cn) {
   __shared__ double Pr[64], Pi[64];
-  const int i = threadIdx.x;
+  const int i = threadIdx.x, n = blockIdx.x;
   const int muf = fw.mused[0], mub = bw.mused[0];
-  for (int c = 0; c < kGradMaxM; ++c)
-    if (i < kGradMaxM) {
-      Cr[c][i] = 0.0;
-      Ci[c][i] = 0.0;
-    }
-  __syncthreads();
-  if (fw.status[0] != QK_OK || bw.status[0] != QK_OK || muf <= 0 || mub <= 0) {
-    for (int c = 0; c < kGradMaxM; ++c)
-      if (i < kGradMaxM) {
-        Ct[2 * (c * kGradMaxM + i)] = 0.0;
-        Ct[2 * (c * kGradMaxM + i) + 1] = 0.0;
-      }
-    return;
-  }
+  if (fw.status[0] != QK_OK || bw.status[0] != QK_OK || muf <= 0 || mub <= 0) return;   // k_grad_coeffs writes zeros
   const bool onf = i < muf, onb = i < mub;
   const double alf = onf ? fw.alpha[i] : 0.0, bef = (i + 1 < muf) ? fw.beta[i] : 0.0;
   const double blf = (onf && i > 0) ? fw.beta[i - 1] : 0.0;
   const double alb = onb ? bw.alpha[i] : 0.0, beb = (i + 1 < mub) ? bw.beta[i] : 0.0;
   const double blb = (onb && i > 0) ? bw.beta[i - 1] : 0.0;
-  const double n0f = fw.n0[0], n0b = bw.n0[0];
-  for (int q = 0; q < kGaussNodes; ++q) {
-    const double tau = dt * gr.x[q], wq = dt * gr.w[q];
-    double pr, pi, qr, qi;
-    tri_expm_e1(alf, bef, blf, onf, i, tau, pr, pi);           // exp(-i tau T) e_1
-    tri_expm_e1(alb, beb, blb, onb, i, -(dt - tau), qr, qi);   // exp(+i (dt - tau) T') e_1
-    Pr[i] = n0f * pr;
-    Pi[i] = n0f * pi;
-    qr *= n0b;
-    qi *= n0b;
-    __syncthreads();
-    if (i < mub && i < kGradMaxM)
-      for (int d = 0; d < muf && d < kGradMaxM; ++d) {
-        // conj(q_i) p_d
-        Cr[i][d] += wq * (qr * Pr[d] + qi * Pi[d]);
-        Ci[i][d] += wq * (qr * Pi[d] - qi * Pr[d]);
-      }
-    __syncthreads();
-  }
-  if (i < kGradMaxM)
-    for (int c = 0; c < kGradMaxM; ++c) {
-      const double sc = (c < mub && i < muf) ? bw.sigma[c] * fw.sigma[i] : 0.0;
-      Ct[2 * (c * kGradMaxM + i)] = sc * Cr[c][i];
-      Ct[2 * (c * kGradMaxM + i) + 1] = sc * Ci[c][i];
+  const double tau = dt * gr.x[n], wq = dt * gr.w[n];
+  double pr, pi, qr, qi;
+  tri_expm_e1(alf, bef, blf, onf, i, tau, pr, pi);           // exp(-i tau T) e_1
+  tri_expm_e1(alb, beb, blb, onb, i, -(dt - tau), qr, qi);   // exp(+i (dt - tau) T') e_1
+  Pr[i] = fw.n0[0] * pr;
+  Pi[i] = fw.n0[0] * pi;
+  qr *= bw.n0[0];
+  qi *= bw.n0[0];
+  __syncthreads();
+  if (i < mub && i < kGradMaxM) {
+    double* out = Cn + (size_t)n * 2 * kGradMaxM * kGradMaxM + 2 * (size_t)i * kGradMaxM;
+    for (int d = 0; d < muf && d < kGradMaxM; ++d) {
+      // conj(q_i) p_d
+      out[2 * d] = wq * (qr * Pr[d] + qi * Pi[d]);
+      out[2 * d + 1] = wq * (qr * Pi[d] - qi * Pr[d]);
     }
+  }
+}
+
+// C~_cd = sigma'_c sigma_d C_cd for the stored (unnormalised) basis vectors:
+// the node terms summed in node order (one thread per entry).
+__global__ void __launch_bounds__(kGradMaxM * kGradMaxM)
+k_grad_coeffs(KState fw, KState bw, const double* __restrict__ Cn, double* __restrict__ Ct) {
+  const int e = threadIdx.x, c = e / kGradMaxM, d = e % kGradMaxM;
+  const int muf = fw.mused[0], mub = bw.mused[0];
+  const bool ok = fw.status[0] == QK_OK && bw.status[0] == QK_OK && c < mub && d < muf;
+  double cr = 0.0, ci = 0.0;
+  if (ok)
+    for (int n = 0; n < kGaussNodes; ++n) {
+      cr += Cn[(size_t)n * 2 * kGradMaxM * kGradMaxM + 2 * e];
+      ci += Cn[(size_t)n * 2 * kGradMaxM * kGradMaxM + 2 * e + 1];
+    }
+  const double sc = ok ? bw.sigma[c] * fw.sigma[d] : 0.0;
+  Ct[2 * e] = sc * cr;
+  Ct[2 * e + 1] = sc * ci;
 }
 
 // Per row r: s_r = sum_c conj(u'_c[r]) sum_d C~_cd u_d[r] (u_0 = psi_k,
@@ -226,21 +222,34 @@ k_grad_contract(const S* __restrict__ states, uint64_t niter, int L, const doubl
   if (tid < kGradQ) part[(size_t)blockIdx.x * kGradQ + tid] = acc;
 }
 
-// dA[i] += -i (S_i - S_total / 2) summed over the blocks in a fixed order.
-__global__ void k_grad_accum(const double* __restrict__ part, int G, int L, double* __restrict__ dA) {
-  const int q = threadIdx.x;   // kGradQ (<= 256) threads or more
+// dA[i] += -i (S_i - S_total / 2), the partial sums of the G contraction
+// blocks totalled in a fixed order: kAccLanes lanes per column each add every
+// kAccLanes-th block, then one thread adds the lanes in order.
+constexpr int kAccLanes = 7;
+constexpr int kAccThreads = 1024;
+static_assert(kGradQ * kAccLanes <= kAccThreads, "one lane group per column");
+__global__ void __launch_bounds__(kAccThreads) k_grad_accum(const double* __restrict__ part, int G, int L,
+                                                           double* __restrict__ dA) {
+  __shared__ double red[kGradQ * kAccLanes];
   __shared__ double tot[kGradQ];
-  if (q < kGradQ) {
-    double t = 0.0;
-    for (int g = 0; g < G; ++g) t += part[(size_t)g * kGradQ + q];
-    tot[q] = t;
+  const int t = threadIdx.x, c = t / kAccLanes, l = t % kAccLanes;
+  if (c < kGradQ) {
+    double acc = 0.0;
+    for (int g = l; g < G; g += kAccLanes) acc += part[(size_t)g * kGradQ + c];
+    red[c * kAccLanes + l] = acc;
   }
   __syncthreads();
-  if (q < L) {
-    const double gr = tot[2 * q] - 0.5 * tot[2 * QK_MAX_L];
-    const double gi = tot[2 * q + 1] - 0.5 * tot[2 * QK_MAX_L + 1];
-    dA[2 * q] += gi;       // -i (gr + i gi) = gi - i gr
-    dA[2 * q + 1] -= gr;
+  if (t < kGradQ) {
+    double s = 0.0;
+    for (int k = 0; k < kAccLanes; ++k) s += red[t * kAccLanes + k];
+    tot[t] = s;
+  }
+  __syncthreads();
+  if (t < L) {
+    const double gr = tot[2 * t] - 0.5 * tot[2 * QK_MAX_L];
+    const double gi = tot[2 * t + 1] - 0.5 * tot[2 * QK_MAX_L + 1];
+    dA[2 * t] += gi;       // -i (gr + i gi) = gi - i gr
+    dA[2 * t + 1] -= gr;
   }
 }
 
@@ -294,7 +303,7 @@ qk_status grad_return_prob(qk_krylov* k, int64_t r0, double T, int n_steps, int 
   double2* cur = nullptr;    // running forward state
   double2* lam = nullptr;    // lambda_k
   double2* lamp = nullptr;   // lambda_{k+1}
-  double *Ct = nullptr, *part = nullptr, *dA = nullptr;
+  double *Ct = nullptr, *Cn = nullptr, *part = nullptr, *dA = nullptr;
   qk_status st = krylov_create(H, k->m, QK_C128, k->reorth, k->al, &kb);
   if (st != QK_OK) {
     dev_free(k->al, ubank);
@@ -312,6 +321,7 @@ qk_status grad_return_prob(qk_krylov* k, int64_t r0, double T, int n_steps, int 
   if (e == hipSuccess) e = dev_alloc(k->al, (void**)&lam, vbytes);
   if (e == hipSuccess) e = dev_alloc(k->al, (void**)&lamp, vbytes);
   if (e == hipSuccess) e = dev_alloc(k->al, (void**)&Ct, sizeof(double) * 2 * kGradMaxM * kGradMaxM);
+  if (e == hipSuccess) e = dev_alloc(k->al, (void**)&Cn, sizeof(double) * 2 * kGradMaxM * kGradMaxM * kGaussNodes);
   if (e == hipSuccess) e = dev_alloc(k->al, (void**)&part, sizeof(double) * (size_t)G * kGradQ);
   if (e == hipSuccess) e = dev_alloc(k->al, (void**)&dA, sizeof(double) * 2 * L);
   if (e == hipSuccess) e = hipMemsetAsync(dA, 0, sizeof(double) * 2 * L, s);
@@ -397,7 +407,10 @@ qk_status grad_return_prob(qk_krylov* k, int64_t r0, double T, int n_steps, int 
     chk("costate copy");
     if (st == QK_OK) st = launch_krylov_step(kb, lam, -dt, s, true);
     if (st != QK_OK) break;
-    hipLaunchKernelGGL(k_grad_coeffs, dim3(1), dim3(64), 0, s, fwt, bw, dt, gr, Ct);
+    hipLaunchKernelGGL(k_grad_nodes, dim3(kGaussNodes), dim3(64), 0, s, fwt, bw, dt, gr, Cn);
+    chk("k_grad_nodes");
+    if (st != QK_OK) break;
+    hipLaunchKernelGGL(k_grad_coeffs, dim3(1), dim3(kGradMaxM * kGradMaxM), 0, s, fwt, bw, (const double*)Cn, Ct);
     chk("k_grad_coeffs");
     if (st != QK_OK) break;
     if (H->basis->wide)
@@ -410,7 +423,7 @@ qk_status grad_return_prob(qk_krylov* k, int64_t r0, double T, int n_steps, int 
                          (const double2*)kb->d_U, (size_t)k->ustride, lr0, lnn, pe, fwt, bw, Ct, part);
     chk("k_grad_contract");
     if (st != QK_OK) break;
-    hipLaunchKernelGGL(k_grad_accum, dim3(1), dim3(256), 0, s, part, G, L, dA);
+    hipLaunchKernelGGL(k_grad_accum, dim3(1), dim3(kAccThreads), 0, s, part, G, L, dA);
     chk("k_grad_accum");
   }
   std::vector<double> dAh(2 * L);
@@ -430,6 +443,7 @@ qk_status grad_return_prob(qk_krylov* k, int64_t r0, double T, int n_steps, int 
   dev_free(k->al, lam);
   dev_free(k->al, lamp);
   dev_free(k->al, Ct);
+  dev_free(k->al, Cn);
   dev_free(k->al, part);
   dev_free(k->al, dA);
   dev_free(k->al, ubank);
