@@ -362,13 +362,27 @@ qk_status qk_batch_create(qk_krylov* const* ks, void* const* psi, const int64_t*
 qk_status qk_batch_items(const qk_batch* b, int32_t* items);
 
 /*
- * n_steps Krylov steps of length dt of every workspace.  After step k the
- * survival probability |psi_i[r0_i]|^2 of every item is written to
- * P_device[k * items + offset_i + item] (offsets in workspace order).  With
- * use_graph = 1 one step of all workspaces (one graph branch each) is
- * captured into a hipGraph on first use (and again when dt or P_device
- * change) and replayed n_steps times; with 0 the same work is enqueued
- * directly.  Asynchronous.
+ * n_steps Krylov steps of length dt of every workspace (Sec. 2 "Krylov
+ * subspace methods"; the ensembles of Sec. 4 "Quasidisordered systems").
+ * After step k the survival probability |psi_i[r0_i]|^2 of every item is
+ * written to P_device[k * items + offset_i + item] (offsets in workspace
+ * order).  use_graph selects how a step is launched:
+ *   0  every kernel of every workspace enqueued directly;
+ *   1  one step of all workspaces (one graph branch each) captured into a
+ *      hipGraph on first use (again when dt, P_device or a launch shape
+ *      change) and replayed n_steps times;
+ *   2  one persistent kernel per step that advances all workspaces, records
+ *      P and advances C(t) (a work queue of every workspace's passes, each
+ *      pass waiting on the previous pass of its workspace), captured into a
+ *      hipGraph the same way and replayed n_steps times.  It runs the same
+ *      kernel bodies on the same grids as 0 and 1, so all three give the same
+ *      bits.  Requires one dtype for all workspaces, L <= 32, no split layout,
+ *      reorthogonalisation 0 or 1 and 256-thread row-streaming blocks (the
+ *      default shape; a batch of B items needs B a power of two), else
+ *      QK_EUNSUPPORTED before anything is enqueued.  Its work queue is built
+ *      on first use (device memory from the batch's allocator, kept until
+ *      the batch is destroyed or a launch shape changes).
+ * Asynchronous.
  */
 qk_status qk_batch_run(qk_batch* b, double dt, int32_t n_steps, int32_t use_graph, double* P_device, void* stream);
 

@@ -372,20 +372,34 @@ def qk_batch_items(b: Batch) -> int:
     return n.value
 
 
-def qk_batch_run(b: Batch, dt: float, n_steps: int, use_graph: bool = True, out: torch.Tensor | None = None,
+def _graph_mode(use_graph) -> int:
+    """0 (direct launches), 1 (graph of one branch per workspace) or 2 (graph of
+    the persistent step kernel); a bool means 0 or 1."""
+    if isinstance(use_graph, bool):
+        return int(use_graph)
+    m = int(use_graph)
+    if m not in (0, 1, 2):
+        raise ValueError("use_graph must be 0, 1 or 2")
+    return m
+
+
+def qk_batch_run(b: Batch, dt: float, n_steps: int, use_graph: bool | int = True, out: torch.Tensor | None = None,
                  stream=None) -> torch.Tensor:
-    """n_steps steps of every workspace; returns the device tensor P[n_steps, items]."""
+    """n_steps steps of every workspace; returns the device tensor P[n_steps, items].
+    use_graph: 0/False direct launches, 1/True one graph branch per workspace,
+    2 the persistent step kernel (one launch per step, captured in a graph)."""
     items = qk_batch_items(b)
     if out is None:
         out = torch.empty((n_steps, items), dtype=torch.float64, device="cuda")
     if out.numel() < n_steps * items or out.dtype != torch.float64:
         raise ValueError("out must be a float64 tensor of n_steps * items entries")
-    _check(lib.qk_batch_run(b.ptr, float(dt), int(n_steps), int(bool(use_graph)), _dptr(out), _stream(stream)),
+    _check(lib.qk_batch_run(b.ptr, float(dt), int(n_steps), _graph_mode(use_graph), _dptr(out), _stream(stream)),
            "qk_batch_run")
     return out
 
 
-def qk_batch_run_autocorr(b: Batch, dt: float, n_steps: int, use_graph: bool = True, out: torch.Tensor | None = None,
+def qk_batch_run_autocorr(b: Batch, dt: float, n_steps: int, use_graph: bool | int = True,
+                          out: torch.Tensor | None = None,
                           out_c: torch.Tensor | None = None, stream=None):
     """As qk_batch_run, plus the temporal autocorrelation C(t) of every item
     after every step; returns the device tensors (P, C), each [n_steps, items]."""
@@ -397,7 +411,7 @@ def qk_batch_run_autocorr(b: Batch, dt: float, n_steps: int, use_graph: bool = T
     for t in (out, out_c):
         if t.numel() < n_steps * items or t.dtype != torch.float64:
             raise ValueError("out and out_c must be float64 tensors of n_steps * items entries")
-    _check(lib.qk_batch_run_autocorr(b.ptr, float(dt), int(n_steps), int(bool(use_graph)), _dptr(out), _dptr(out_c),
+    _check(lib.qk_batch_run_autocorr(b.ptr, float(dt), int(n_steps), _graph_mode(use_graph), _dptr(out), _dptr(out_c),
                                      _stream(stream)), "qk_batch_run_autocorr")
     return out, out_c
 

@@ -14,13 +14,18 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libqkrylov.so")
-SOURCES = ["qk_kernels.hip", "qk_blocked.hip", "qk_split.hip", "qk_batch.hip", "qk_grad.hip", "qk_abi.hip"]
+SOURCES = ["qk_kernels.hip", "qk_blocked.hip", "qk_split.hip", "qk_batch.hip", "qk_persist.hip", "qk_grad.hip",
+           "qk_abi.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared", "-fvisibility=hidden",
     # packed FP32 instructions stay off in every HIP translation unit
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # multiply-adds are fused only where one source expression holds both, so
+    # a kernel body gives the same bits in every kernel it is inlined into
+    # (the plain launches and the persistent step) and in every variant of it
+    "-ffp-contract=on",
     "-Wno-unused-command-line-argument",
 ]
 

@@ -673,7 +673,7 @@ QK_API qk_status qk_batch_run_autocorr(qk_batch* b, double dt, int32_t n_steps, 
   if (!b || !P_device) return inval("NULL pointer");
   if (!std::isfinite(dt)) return inval("dt not finite");
   if (n_steps < 0) return inval("n_steps < 0");
-  if (use_graph != 0 && use_graph != 1) return inval("use_graph must be 0 or 1");
+  if (use_graph < 0 || use_graph > 2) return inval("use_graph must be 0, 1 or 2");
   qk_status st = check_device(batch_device(b));
   if (st != QK_OK) return st;
   if (n_steps == 0) return QK_OK;

@@ -28,7 +28,8 @@
 #include <string>
 #include <vector>
 
-#include "qk_device.h"
+#include "qk_persist.h"
+#include "qk_step_bodies.h"
 
 namespace qk {
 
@@ -36,36 +37,18 @@ namespace qk {
 template <typename T>
 __global__ void k_record(const typename Cx<T>::V* __restrict__ psi, uint32_t r0, int B, double* __restrict__ P,
                          const int* __restrict__ counter, int off, int items) {
-  const int b = threadIdx.x;
-  if (b >= B) return;
-  const typename Cx<T>::V v = psi[(size_t)r0 * B + b];
-  P[(size_t)(*counter) * items + off + b] = (double)v.x * (double)v.x + (double)v.y * (double)v.y;
+  record_body<T>(psi, r0, B, P, counter, off, items);
 }
 
 __global__ void k_counter(int* counter, int reset) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *counter = reset ? 0 : *counter + 1;
 }
 
-// Trapezoid step of the autocorrelation integral for every item: S += dt/2
-// (P_prev + P_now), P_prev = P_now, t += dt, C = S / t (written when C is
-// not NULL).  One block; `state` = [S(items), P_prev(items), t].
+// Trapezoid step of the autocorrelation integral (autocorr_body), one block.
 __global__ void __launch_bounds__(256)
 k_autocorr(const double* __restrict__ P, const int* __restrict__ counter, int items, double dt, double* state,
            double* C) {
-  const int c = *counter;
-  double* S = state;
-  double* prev = state + items;
-  double* tp = state + 2 * (size_t)items;
-  const double t = *tp + dt;
-  for (int j = threadIdx.x; j < items; j += blockDim.x) {
-    const double pn = P[(size_t)c * items + j];
-    const double sj = S[j] + 0.5 * dt * (prev[j] + pn);
-    S[j] = sj;
-    prev[j] = pn;
-    if (C) C[(size_t)c * items + j] = (t > 0.0) ? sj / t : pn;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) *tp = t;
+  autocorr_body(P, counter, items, dt, state, C);
 }
 
 // Deterministic pseudo-random complex entries (an integer hash of the index),
@@ -317,6 +300,9 @@ struct qk_batch {
   double* graph_P = nullptr;
   double* graph_C = nullptr;
   std::vector<uint64_t> graph_sig;  // launch configuration the graph was captured with
+  int graph_mode = 0;               // 1: one branch per workspace, 2: the persistent step kernel
+  qk::PersistPlan* plan = nullptr;  // work queue of the persistent step (mode 2)
+  std::vector<uint64_t> plan_sig;
 };
 
 namespace qk {
@@ -339,6 +325,15 @@ void batch_release(qk_batch* b) {
   if (b->graph) (void)hipGraphDestroy(b->graph);
   b->exec = nullptr;
   b->graph = nullptr;
+}
+
+static void batch_release_plan(qk_batch* b) {
+  if (b->plan) {
+    (void)hipDeviceSynchronize();   // no queued launch may still read the plan
+    persist_free(b->plan);
+  }
+  b->plan = nullptr;
+  b->plan_sig.clear();
 }
 
 qk_status batch_create(qk_krylov* const* ks, void* const* psi, const int64_t* r0, int n, qk_batch** out) {
@@ -410,6 +405,7 @@ void batch_destroy(qk_batch* b) {
   if (!b) return;
   (void)hipDeviceSynchronize();
   batch_release(b);
+  batch_release_plan(b);
   for (auto s : b->streams) (void)hipStreamDestroy(s);
   for (auto e : b->joins) (void)hipEventDestroy(e);
   if (b->fork) (void)hipEventDestroy(b->fork);
@@ -458,6 +454,30 @@ static std::vector<uint64_t> batch_signature(const qk_batch* b) {
   return sig;
 }
 
+// The persistent step's work queue for the current launch shapes (rebuilt
+// when a workspace's shape or block decomposition has changed).
+static qk_status batch_plan(qk_batch* b, const std::vector<uint64_t>& sig) {
+  if (b->plan && b->plan_sig == sig) return QK_OK;
+  batch_release(b);   // a captured graph may point at the old plan
+  batch_release_plan(b);
+  PersistInput in;
+  in.al = b->al;
+  in.ks = b->ks;
+  in.psi = b->psi;
+  in.r0 = b->r0;
+  for (void* p : b->psi0) in.psi0.push_back(p);
+  in.part = b->part;
+  in.ogrid = b->ogrid;
+  in.item_off = b->item_off;
+  qk_status st = persist_plan(in, &b->plan);
+  if (st != QK_OK) {
+    b->plan = nullptr;
+    return st;
+  }
+  b->plan_sig = sig;
+  return QK_OK;
+}
+
 qk_status batch_run(qk_batch* b, double dt, int n_steps, int use_graph, double* P, double* C, hipStream_t s) {
   std::vector<bool> prof(b->ks.size());
   for (size_t i = 0; i < b->ks.size(); ++i) {
@@ -480,14 +500,25 @@ qk_status batch_run(qk_batch* b, double dt, int n_steps, int use_graph, double* 
     return st;
   }
   const std::vector<uint64_t> sig = batch_signature(b);
-  if (!b->exec || b->graph_dt != dt || b->graph_P != P || b->graph_C != C || b->graph_sig != sig) {
+  if (use_graph == 2) {
+    st = batch_plan(b, sig);
+    if (st != QK_OK) {
+      restore();
+      return st;
+    }
+  }
+  if (!b->exec || b->graph_mode != use_graph || b->graph_dt != dt || b->graph_P != P || b->graph_C != C ||
+      b->graph_sig != sig) {
     batch_release(b);
     hipError_t e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) {
       restore();
       return hip_fail(e, "hipStreamBeginCapture");
     }
-    st = batch_step(b, dt, P, C, b->cap);
+    if (use_graph == 2)
+      st = persist_launch(b->plan, dt, P, C, b->d_counter, b->d_state, b->items, b->cap);
+    else
+      st = batch_step(b, dt, P, C, b->cap);
     hipGraph_t g = nullptr;
     e = hipStreamEndCapture(b->cap, &g);
     if (st != QK_OK || e != hipSuccess) {
@@ -502,6 +533,7 @@ qk_status batch_run(qk_batch* b, double dt, int n_steps, int use_graph, double* 
       restore();
       return hip_fail(e, "hipGraphInstantiate");
     }
+    b->graph_mode = use_graph;
     b->graph_dt = dt;
     b->graph_P = P;
     b->graph_C = C;

@@ -177,20 +177,38 @@ __device__ __forceinline__ typename Cx<T>::V h_row(uint32_t r, int b, const Mode
   return acc;
 }
 
+// The block index and block count a kernel body works with.  A plain launch
+// passes (blockIdx.x, gridDim.x); the persistent step kernel (qk_persist.hip)
+// passes the tile it has claimed and the tile count of that pass, so a body
+// produces the same values, partial sums included, either way.
+struct VGrid {
+  uint32_t id, n;
+};
+__device__ __forceinline__ VGrid hw_grid() { return VGrid{blockIdx.x, gridDim.x}; }
+
+// A run of consecutive virtual blocks v0 .. v1-1 of a grid of n, taken by one
+// work-group one after another: what a block's results depend on (tables,
+// the scalars reduced from the previous pass) is set up once for the run,
+// then each virtual block does its own rows and writes its own partial sums.
+struct VRange {
+  uint32_t v0, v1, n;
+};
+__device__ __forceinline__ VRange hw_range() { return VRange{blockIdx.x, blockIdx.x + 1, gridDim.x}; }
+
 // XCD-aware tile walk: work-groups are dealt round-robin to the 8 XCDs, so
 // block i runs on XCD i % 8.  Each XCD gets one contiguous eighth of the row
 // tiles, and its blocks stride through that eighth together, which keeps the
 // rows being read on one XCD close together in that XCD's L2.
 struct TileWalk {
   uint32_t t, t_end, step;
-  __device__ TileWalk(uint32_t ntiles) {
-    if (gridDim.x % kNumXcd) {   // a grid that does not split evenly over the XCDs: plain grid stride
-      t = blockIdx.x;
+  __device__ TileWalk(uint32_t ntiles, VGrid g) {
+    if (g.n % kNumXcd) {   // a grid that does not split evenly over the XCDs: plain grid stride
+      t = g.id;
       t_end = ntiles;
-      step = gridDim.x;
+      step = g.n;
       return;
     }
-    const uint32_t x = blockIdx.x % kNumXcd, k = blockIdx.x / kNumXcd, per = gridDim.x / kNumXcd;
+    const uint32_t x = g.id % kNumXcd, k = g.id / kNumXcd, per = g.n / kNumXcd;
     const uint32_t t0 = (uint32_t)(((uint64_t)ntiles * x) / kNumXcd);
     t_end = (uint32_t)(((uint64_t)ntiles * (x + 1)) / kNumXcd);
     t = t0 + k;
@@ -317,19 +335,20 @@ __device__ __forceinline__ void tri_expm_e1(double al, double be, double bl, boo
 // Scalars of the H-pass of Lanczos iteration j for every batch column b,
 // from the update pass of iteration j-1 (its partial sums |u_j|^2):
 //   sa[b] = sigma_j, sb[b] = beta_{j-1} sigma_{j-1}, act[b] = column still running.
-// Block 0 records beta_{j-1}, sigma_j, and m_used / status on breakdown or a
+// Block 0 (of the virtual grid g) records beta_{j-1}, sigma_j, and m_used / status on breakdown or a
 // non-finite norm.  Every block reduces the same partials in the same order,
 // so all blocks reach the same decisions.
 __device__ __forceinline__ void lanczos_h_scalars(int B, const KState& st, const LanczosArgs& la,
                                                   const double* __restrict__ partB, int Gp, double* red, double* tot,
-                                                  double* sa, double* sb, int* act) {
+                                                  double* sa, double* sb, int* act, VGrid g) {
   const int j = la.j;
+  const bool first = g.id == 0;   // the block that records the shared results
   if (j == 0) {
     for (int b = threadIdx.x; b < B; b += blockDim.x) {
       sa[b] = 1.0;
       sb[b] = 0.0;
       act[b] = 1;
-      if (blockIdx.x == 0) {
+      if (first) {
         st.mused[b] = la.m;
         st.status[b] = QK_OK;
       }
@@ -346,20 +365,20 @@ __device__ __forceinline__ void lanczos_h_scalars(int B, const KState& st, const
         for (int i = 0; i + 1 < j; ++i) scale = fmax(scale, st.beta[i * B + b]);
         if (!isfinite(beta)) {
           active = 0;
-          if (blockIdx.x == 0) {
+          if (first) {
             st.status[b] = QK_ENUMERIC;
             st.mused[b] = j;
           }
         } else if (beta <= la.breakdown_rtol * scale) {
           active = 0;  // invariant subspace: the Krylov space stops at dimension j
-          if (blockIdx.x == 0) st.mused[b] = j;
+          if (first) st.mused[b] = j;
         }
-        if (blockIdx.x == 0) st.beta[(j - 1) * B + b] = beta;
+        if (first) st.beta[(j - 1) * B + b] = beta;
       }
       if (active) {
         sa[b] = 1.0 / beta;
         sb[b] = beta * st.sigma[(j - 1) * B + b];
-        if (blockIdx.x == 0) st.sigma[j * B + b] = 1.0 / beta;
+        if (first) st.sigma[j * B + b] = 1.0 / beta;
       }
       act[b] = active;
     }

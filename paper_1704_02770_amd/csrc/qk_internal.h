@@ -32,6 +32,10 @@ constexpr int kMaxBlock = 256;
 constexpr int kReorthChunk = 8;         // Krylov vectors per dot-product pass of the full reorthogonalisation
 constexpr int kReorthGrid = 512;        // blocks of that pass
 constexpr int kMaxPartialBlocks = 4096; // partial-sum slots per reduction (>= any grid used)
+// Fewest (row, column) elements a work-group of a Krylov-step pass is given:
+// small sectors get fewer, fuller work-groups instead of a chip-filling grid
+// of nearly empty ones (and fewer partial sums for the next pass to reduce)
+constexpr uint64_t kMinBlockWork = 2048;
 
 void set_error(const std::string& msg);
 qk_status hip_fail(hipError_t e, const char* what);

@@ -16,7 +16,7 @@
 #include <mutex>
 #include <type_traits>
 
-#include "qk_device.h"
+#include "qk_step_bodies.h"
 
 namespace qk {
 
@@ -88,7 +88,7 @@ k_apply(const typename Cx<T>::V* __restrict__ x, typename Cx<T>::V* __restrict__
   const int B = a.B, b = threadIdx.x % B;
   const uint32_t R = blockDim.x / B, rl = threadIdx.x / B;
   const uint32_t ntiles = (hv.D + R - 1) / R;
-  for (TileWalk w(ntiles); w.t < w.t_end; w.t += w.step) {
+  for (TileWalk w(ntiles, hw_grid()); w.t < w.t_end; w.t += w.step) {
     const uint32_t r = w.t * R + rl;
     if (r >= hv.D) continue;
     typename Cx<T>::V xr;
@@ -102,82 +102,14 @@ k_lanczos_A(const typename Cx<T>::V* __restrict__ uj, const typename Cx<T>::V* _
             typename Cx<T>::V* __restrict__ w, ModelArgs a, HamView<S> hv, const uint32_t* __restrict__ gtab,
             const double* __restrict__ gfields, KState st, LanczosArgs la, const double* __restrict__ partB, int Gp,
             double* __restrict__ partA) {
-  using V = typename Cx<T>::V;
-  __shared__ RowShared<S> sh;
-  __shared__ double red[kQA * kMaxBlock];
-  __shared__ double tot[QK_MAX_BATCH];
-  __shared__ double sa[QK_MAX_BATCH], sb[QK_MAX_BATCH];
-  __shared__ int act[QK_MAX_BATCH];
-  load_row_shared(sh, a, gtab, gfields);
-  const int B = a.B;
-  lanczos_h_scalars(B, st, la, partB, Gp, red, tot, sa, sb, act);
-
-  const int b = threadIdx.x % B;
-  const uint32_t R = blockDim.x / B, rl = threadIdx.x / B;
-  const uint32_t ntiles = (hv.D + R - 1) / R;
-  double s1 = 0.0, s2 = 0.0, s3r = 0.0, s3i = 0.0;
-  if (act[b]) {
-    const T ca = (T)sa[b], cb = (T)sb[b];
-    for (TileWalk tw(ntiles); tw.t < tw.t_end; tw.t += tw.step) {
-      const uint32_t r = tw.t * R + rl;
-      if (r >= hv.D) continue;
-      V xr;
-      const V hx = h_row<T, CSR, S>(r, b, a, sh, hv, uj, xr);
-      V wv;
-      wv.x = ca * hx.x;
-      wv.y = ca * hx.y;
-      if (la.j > 0) {
-        const V um = ujm1[(size_t)r * B + b];
-        wv.x -= cb * um.x;
-        wv.y -= cb * um.y;
-        s3r += (double)um.x * (double)wv.x + (double)um.y * (double)wv.y;
-        s3i += (double)um.x * (double)wv.y - (double)um.y * (double)wv.x;
-      }
-      w[(size_t)r * B + b] = wv;
-      s1 += (double)xr.x * (double)wv.x + (double)xr.y * (double)wv.y;
-      s2 += (double)xr.x * (double)xr.x + (double)xr.y * (double)xr.y;
-    }
-  }
-  double v[kQA] = {s1, s2, s3r, s3i};
-  block_partials<kQA>(v, B, red, partA + (size_t)blockIdx.x * kQA * B);
+  __shared__ LanczosAShared<S> ls;
+  lanczos_a_body<T, CSR, S>(hw_range(), ls, uj, ujm1, w, a, hv, gtab, gfields, st, la, partB, Gp, partA);
 }
 
-// Non-temporal load of one complex element, for vectors a pass reads once.
-// Used only for vectors larger than the last-level cache (kNtBytes): there it
-// makes the update pass 9 % and the combination 8 % faster (complex128,
-// L = 28); for vectors that the 256 MB cache can hold (L = 24, 26) it is slower.
-constexpr size_t kNtBytes = (size_t)256 << 20;
-template <typename V>
-__device__ __forceinline__ V ld_nt(const V* p) {
-  using S = decltype(V{}.x);
-  typedef S E __attribute__((ext_vector_type(2)));
-  const E e = __builtin_nontemporal_load(reinterpret_cast<const E*>(p));
-  return V{e.x, e.y};
-}
-
-// Totals of per-block partial sums part[g][c] (g < G, c < cols) into tot[c],
-// each column summed in a fixed order (32 lanes over g, then a fixed tree
-// over the lanes), so every consumer reads one row instead of reducing G rows
-// itself.  Used for batches of kPreReduceBatch items or more, where the
-// G x cols partials make that per-block reduction the longest part of a pass.
-constexpr int kPreReduceBatch = 8;
-constexpr int kTotLanes = 32;                  // lanes per column
-constexpr int kTotCols = 256 / kTotLanes;      // columns per block
 __global__ void __launch_bounds__(256) k_partials_total(const double* __restrict__ part, int G, int cols,
                                                         double* __restrict__ tot) {
   __shared__ double red[256];
-  const int tid = threadIdx.x;
-  const int c = blockIdx.x * kTotCols + tid / kTotLanes, l = tid % kTotLanes;
-  double acc = 0.0;
-  if (c < cols)
-    for (int g = l; g < G; g += kTotLanes) acc += part[(size_t)g * cols + c];
-  red[tid] = acc;
-  __syncthreads();
-  for (int h = kTotLanes / 2; h > 0; h >>= 1) {
-    if (l < h) red[tid] += red[tid + h];
-    __syncthreads();
-  }
-  if (l == 0 && c < cols) tot[c] = red[tid];
+  partials_total_body(hw_range(), red, part, G, cols, tot);
 }
 
 template <typename T, bool NT>
@@ -185,95 +117,10 @@ __global__ void __launch_bounds__(kMaxBlock)
 k_lanczos_B(const typename Cx<T>::V* __restrict__ uj, const typename Cx<T>::V* __restrict__ ujm1,
             typename Cx<T>::V* __restrict__ w, uint32_t D, int B, KState st, LanczosArgs la,
             const double* __restrict__ partA, int Gp, double* __restrict__ partB, int store) {
-  using V = typename Cx<T>::V;
-  __shared__ double red[kMaxBlock];
-  __shared__ double tot[kQA * QK_MAX_BATCH];
-  __shared__ double sc[QK_MAX_BATCH], sd[QK_MAX_BATCH], ser[QK_MAX_BATCH], sei[QK_MAX_BATCH];
-  __shared__ int act[QK_MAX_BATCH];
-  const int j = la.j;
-  const bool ro = la.reorth && j > 0;
-  reduce_partials(partA, Gp, kQA, B, red, tot);
-  for (int b = threadIdx.x; b < B; b += blockDim.x) {
-    int active = st.mused[b] > j;
-    if (active) {
-      const double S1 = tot[b], S2 = tot[B + b];
-      double alpha, c, d;
-      if (j == 0) {
-        const double n0 = sqrt(S2);
-        alpha = S1 / S2;
-        c = 1.0 / n0;
-        d = alpha;
-        if (blockIdx.x == 0) {
-          st.n0[b] = n0;
-          st.sigma[b] = 1.0 / n0;
-        }
-        if (!(n0 > 0.0)) {
-          active = 0;   // zero vector: nothing to propagate
-          if (blockIdx.x == 0) {
-            st.mused[b] = 0;
-            if (!isfinite(S2)) st.status[b] = QK_ENUMERIC;
-          }
-        }
-      } else {
-        const double sj = st.sigma[j * B + b];
-        alpha = sj * S1;
-        c = 1.0;
-        d = alpha * sj;
-      }
-      if (active && !isfinite(alpha)) {
-        active = 0;
-        if (blockIdx.x == 0) {
-          st.status[b] = QK_ENUMERIC;
-          st.mused[b] = j;
-        }
-      }
-      if (active && blockIdx.x == 0) st.alpha[j * B + b] = alpha;
-      sc[b] = c;
-      sd[b] = d;
-      // component of w along v_{j-1}: <v_{j-1}, w> v_{j-1} = sigma_{j-1}^2 <u_{j-1}, w> u_{j-1}
-      const double sm = ro ? st.sigma[(j - 1) * B + b] : 0.0;
-      ser[b] = sm * sm * tot[2 * B + b];
-      sei[b] = sm * sm * tot[3 * B + b];
-    }
-    act[b] = active;
-  }
-  __syncthreads();
-
-  const int b = threadIdx.x % B;
-  const uint32_t R = blockDim.x / B, rl = threadIdx.x / B;
-  const uint32_t ntiles = (D + R - 1) / R;
-  double s = 0.0;
-  if (act[b]) {
-    const double c = sc[b], d = sd[b], er = ser[b], ei = sei[b];
-    for (TileWalk tw(ntiles); tw.t < tw.t_end; tw.t += tw.step) {
-      const uint32_t r = tw.t * R + rl;
-      if (r >= D) continue;
-      const size_t i = (size_t)r * B + b;
-      V wv, u;
-      if (NT) {
-        wv = ld_nt(w + i);
-        u = ld_nt(uj + i);
-      } else {
-        wv = w[i];
-        u = uj[i];
-      }
-      double nx = c * ((double)wv.x - d * (double)u.x);
-      double ny = c * ((double)wv.y - d * (double)u.y);
-      if (ro) {
-        const V um = ujm1[i];
-        nx -= er * (double)um.x - ei * (double)um.y;
-        ny -= er * (double)um.y + ei * (double)um.x;
-      }
-      V o;
-      o.x = (T)nx;
-      o.y = (T)ny;
-      if (store) w[i] = o;
-      s += (double)o.x * (double)o.x + (double)o.y * (double)o.y;
-    }
-  }
-  double v[1] = {s};
-  block_partials<1>(v, B, red, partB + (size_t)blockIdx.x * B);
+  __shared__ LanczosBShared ls;
+  lanczos_b_body<T, NT>(hw_range(), ls, uj, ujm1, w, D, B, st, la, partA, Gp, partB, store);
 }
+
 
 // ------------------------------------- full reorthogonalisation (reorth = 2)
 // Classical Gram-Schmidt applied twice to the new vector w = u_{j+1} against
@@ -294,7 +141,7 @@ k_reorth_dots(const typename Cx<T>::V* __restrict__ psi, const typename Cx<T>::V
   double acc[2 * kReorthChunk];
 #pragma unroll
   for (int q = 0; q < 2 * kReorthChunk; ++q) acc[q] = 0.0;
-  for (TileWalk tw(ntiles); tw.t < tw.t_end; tw.t += tw.step) {
+  for (TileWalk tw(ntiles, hw_grid()); tw.t < tw.t_end; tw.t += tw.step) {
     const uint32_t r = tw.t * R + rl;
     if (r >= D) continue;
     const size_t i = (size_t)r * B + b;
@@ -339,7 +186,7 @@ k_reorth_axpy(const typename Cx<T>::V* __restrict__ psi, const typename Cx<T>::V
   const uint32_t ntiles = (D + R - 1) / R;
   const size_t stride = (size_t)D * B;
   double s = 0.0;
-  for (TileWalk tw(ntiles); tw.t < tw.t_end; tw.t += tw.step) {
+  for (TileWalk tw(ntiles, hw_grid()); tw.t < tw.t_end; tw.t += tw.step) {
     const uint32_t r = tw.t * R + rl;
     if (r >= D) continue;
     const size_t i = (size_t)r * B + b;
@@ -361,76 +208,12 @@ k_reorth_axpy(const typename Cx<T>::V* __restrict__ psi, const typename Cx<T>::V
   block_partials<1>(v, B, red, partB + (size_t)blockIdx.x * B);
 }
 
-// ------------------------------------------ projected exponential (1 wave)
-// ||u_m|| of the last update pass (the norm of the residual after m steps;
-// only meaningful when the recurrence ran all m steps), reduced by one wave.
-__device__ __forceinline__ double last_residual_norm(const double* __restrict__ partB, int Gp, int B, int b,
-                                                     double* red) {
-  const int i = threadIdx.x;
-  double acc = 0.0;
-  for (int g = i; g < Gp; g += 64) acc += partB[(size_t)g * B + b];
-  red[i] = acc;
-  __syncthreads();
-  for (int s = 32; s > 0; s >>= 1) {
-    if (i < s) red[i] += red[i + s];
-    __syncthreads();
-  }
-  return sqrt(red[0]);
-}
-
-// Tridiagonal entries of column b seen by lane i (zero outside m_used).
-struct TriLane {
-  double al, be, bl;
-  bool on;
-};
-__device__ __forceinline__ TriLane tri_lane(const KState& st, int B, int b, int mu) {
-  const int i = threadIdx.x;
-  TriLane t;
-  t.on = i < mu;
-  t.al = t.on ? st.alpha[i * B + b] : 0.0;
-  t.be = (i + 1 < mu) ? st.beta[i * B + b] : 0.0;     // couples i and i+1
-  t.bl = (t.on && i > 0) ? st.beta[(i - 1) * B + b] : 0.0;
-  return t;
-}
-
-// c = exp(-i tau T) e_1 for the tridiagonal T of the Lanczos recurrence
-// (tri_expm_e1), times ||psi|| and the stored-vector scales, plus the
-// a-posteriori error estimate ||psi|| beta_m |c_m|.  With tau_dev != NULL the
-// step is the smallest of tau_dev[0..B) (the accepted steps of an adaptive
-// step, so that all columns stay at the same time).
 __global__ void __launch_bounds__(64)
 k_small_expm(KState st, int m, int B, double tau, const double* __restrict__ tau_dev, const double* __restrict__ partB,
              int Gp) {
-  const int b = blockIdx.x;
-  const int i = threadIdx.x;
-  __shared__ double red[64];
-  const double beta_last = last_residual_norm(partB, Gp, B, b, red);
-  if (tau_dev) {
-    tau = tau_dev[0];
-    for (int c = 1; c < B; ++c) tau = fmin(tau, tau_dev[c]);
-  }
-  const int mu = st.mused[b];
-  if (st.status[b] != QK_OK || mu <= 0) {
-    if (i < m) {
-      st.gre[i * B + b] = 0.0;
-      st.gim[i * B + b] = 0.0;
-    }
-    if (i == 0) st.err[b] = 0.0;
-    return;
-  }
-  if (mu == m && i == 0) st.beta[(m - 1) * B + b] = beta_last;
-  const TriLane t = tri_lane(st, B, b, mu);
-  double er, ei;
-  tri_expm_e1(t.al, t.be, t.bl, t.on, i, tau, er, ei);
-  const double n0 = st.n0[b];
-  if (i < m) {
-    const double g = t.on ? n0 * st.sigma[i * B + b] : 0.0;
-    st.gre[i * B + b] = g * er;
-    st.gim[i * B + b] = g * ei;
-  }
-  const double last = __shfl(sqrt(er * er + ei * ei), mu - 1);
-  if (i == 0) st.err[b] = (mu == m) ? n0 * beta_last * last : 0.0;
+  small_expm_wave((int)blockIdx.x, (int)threadIdx.x, st, m, B, tau, tau_dev, partB, Gp);
 }
+
 
 // Step-size control of one adaptive step (the rule of Expokit, which the
 // paper's runs use through SLEPc): starting from tau_max, the step tau of
@@ -445,12 +228,11 @@ __global__ void __launch_bounds__(64)
 k_step_size(KState st, int m, int B, double tau_max, double tol, const double* __restrict__ partB, int Gp) {
   const int b = blockIdx.x;
   const int i = threadIdx.x;
-  __shared__ double red[64];
-  const double beta_last = last_residual_norm(partB, Gp, B, b, red);
+  const double beta_last = last_residual_norm(partB, Gp, B, b, i);
   const int mu = st.mused[b];
   double tau = tau_max, next = tau_max;
   if (st.status[b] == QK_OK && mu == m && m > 1) {
-    const TriLane t = tri_lane(st, B, b, mu);
+    const TriLane t = tri_lane(st, B, b, mu, i);
     const double n0 = st.n0[b];
     const double xm = 1.0 / (double)(m - 1);
     double err = 0.0;
@@ -473,103 +255,14 @@ k_step_size(KState st, int m, int B, double tau_max, double tol, const double* _
   }
 }
 
-// ------------------------------------------------ Krylov combination
-// psi[r, b] = sum_{j < m_used} gamma_j u_j[r, b], u_0 = psi, accumulated in
-// double and rounded once.  The [D][B] arrays are walked as flat elements
-// i = r * B + b; a thread takes the E consecutive elements of one access
-// (E = 2 packs two complex64 values into 16 bytes) and issues the loads of
-// kCombineUnroll Krylov vectors before it accumulates them.  With one column
-// the coefficients are uniform (scalar loads); with several they are staged
-// in LDS.  Columns whose step failed or had nothing to propagate are left
-// unchanged.
-constexpr int kCombineUnroll = 8;
-
 template <typename T, int E, bool ONE, bool NT>
 __global__ void __launch_bounds__(kMaxBlock)
 k_combine(typename Cx<T>::V* __restrict__ psi, const typename Cx<T>::V* __restrict__ U, uint32_t D, int B, int m,
           KState st) {
-  using V = typename Cx<T>::V;
-  struct alignas(sizeof(V) * E) Pack {
-    V v[E];
-  };
   extern __shared__ double2 cf[];   // [m][B] coefficients when B > 1
-  if (!ONE) {
-    for (int i = threadIdx.x; i < m * B; i += blockDim.x) cf[i] = make_double2(st.gre[i], st.gim[i]);
-    __syncthreads();
-  }
-  auto coef = [&](int j, int b) -> double2 {
-    if (ONE) return make_double2(st.gre[j], st.gim[j]);
-    return cf[j * B + b];
-  };
-  const uint64_t np = (uint64_t)D * B / E;   // packs per vector (the launcher makes D * B a multiple of E)
-  const Pack* Up = reinterpret_cast<const Pack*>(U);
-  Pack* Pp = reinterpret_cast<Pack*>(psi);
-  for (uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; p < np; p += (uint64_t)gridDim.x * blockDim.x) {
-    int bc[E], mu[E];
-    bool ok[E];
-    int mumax = 0;
-#pragma unroll
-    for (int e = 0; e < E; ++e) {
-      bc[e] = ONE ? 0 : (int)((p * E + e) % (uint64_t)B);
-      mu[e] = st.mused[bc[e]];
-      ok[e] = st.status[bc[e]] == QK_OK && mu[e] > 0;
-      if (ok[e] && mu[e] > mumax) mumax = mu[e];
-    }
-    const Pack p0 = Pp[p];
-    double ar[E], ai[E];
-#pragma unroll
-    for (int e = 0; e < E; ++e) {
-      const double2 g = coef(0, bc[e]);
-      ar[e] = g.x * (double)p0.v[e].x - g.y * (double)p0.v[e].y;
-      ai[e] = g.x * (double)p0.v[e].y + g.y * (double)p0.v[e].x;
-    }
-    int jj = 1;
-    for (; jj + kCombineUnroll - 1 < mumax; jj += kCombineUnroll) {
-      Pack u[kCombineUnroll];
-#pragma unroll
-      for (int k = 0; k < kCombineUnroll; ++k) {
-        // the basis vectors are read once per step: non-temporal 16-byte loads
-        // when they exceed the last-level cache
-        const Pack* src = Up + (uint64_t)(jj - 1 + k) * np + p;
-        if constexpr (NT && sizeof(Pack) == 16) {
-          typedef double D2 __attribute__((ext_vector_type(2)));
-          const D2 v = __builtin_nontemporal_load(reinterpret_cast<const D2*>(src));
-          __builtin_memcpy(&u[k], &v, 16);
-        } else {
-          u[k] = *src;
-        }
-      }
-#pragma unroll
-      for (int k = 0; k < kCombineUnroll; ++k)
-#pragma unroll
-        for (int e = 0; e < E; ++e) {
-          if (ONE || jj + k < mu[e]) {
-            const double2 g = coef(jj + k, bc[e]);
-            ar[e] += g.x * (double)u[k].v[e].x - g.y * (double)u[k].v[e].y;
-            ai[e] += g.x * (double)u[k].v[e].y + g.y * (double)u[k].v[e].x;
-          }
-        }
-    }
-    for (; jj < mumax; ++jj) {
-      const Pack u = Up[(uint64_t)(jj - 1) * np + p];
-#pragma unroll
-      for (int e = 0; e < E; ++e) {
-        if (ONE || jj < mu[e]) {
-          const double2 g = coef(jj, bc[e]);
-          ar[e] += g.x * (double)u.v[e].x - g.y * (double)u.v[e].y;
-          ai[e] += g.x * (double)u.v[e].y + g.y * (double)u.v[e].x;
-        }
-      }
-    }
-    Pack o;
-#pragma unroll
-    for (int e = 0; e < E; ++e) {
-      o.v[e].x = ok[e] ? (T)ar[e] : p0.v[e].x;
-      o.v[e].y = ok[e] ? (T)ai[e] : p0.v[e].y;
-    }
-    Pp[p] = o;
-  }
+  combine_body<T, E, ONE, NT>(hw_range(), cf, psi, U, D, B, m, st);
 }
+
 
 // ------------------------------------------------ survival probability
 template <typename T>
@@ -585,20 +278,7 @@ __global__ void __launch_bounds__(kMaxBlock)
 k_overlap_partial(const typename Cx<T>::V* __restrict__ psi0, const typename Cx<T>::V* __restrict__ psi, uint32_t D,
                   int B, double* __restrict__ part) {
   __shared__ double red[2 * kMaxBlock];
-  const int b = threadIdx.x % B;
-  const uint32_t R = blockDim.x / B, rl = threadIdx.x / B;
-  const uint32_t ntiles = (D + R - 1) / R;
-  double sr = 0.0, si = 0.0;
-  for (TileWalk tw(ntiles); tw.t < tw.t_end; tw.t += tw.step) {
-    const uint32_t r = tw.t * R + rl;
-    if (r >= D) continue;
-    const size_t i = (size_t)r * B + b;
-    const typename Cx<T>::V a = psi0[i], c = psi[i];
-    sr += (double)a.x * (double)c.x + (double)a.y * (double)c.y;   // conj(a) c
-    si += (double)a.x * (double)c.y - (double)a.y * (double)c.x;
-  }
-  double v[2] = {sr, si};
-  block_partials<2>(v, B, red, part + (size_t)blockIdx.x * 2 * B);
+  overlap_partial_body<T>(hw_range(), red, psi0, psi, D, B, part);
 }
 
 // |<psi0, psi>|^2 per column into P[b], or, with a step counter, into
@@ -608,10 +288,9 @@ k_overlap_final(const double* __restrict__ part, int G, int B, double* P, const 
                 int items) {
   __shared__ double red[kMaxBlock];
   __shared__ double tot[2 * QK_MAX_BATCH];
-  reduce_partials(part, G, 2, B, red, tot);
-  double* out = counter ? P + (size_t)(*counter) * items + off : P;
-  for (int b = threadIdx.x; b < B; b += blockDim.x) out[b] = tot[b] * tot[b] + tot[B + b] * tot[B + b];
+  overlap_final_body(red, tot, part, G, B, P, counter, off, items);
 }
+
 
 // ------------------------------------------------------------- CSR form
 // Counting pass = the exact preallocation of Sec. 3.
@@ -685,6 +364,8 @@ int stream_grid(uint64_t rows, int B, int threads, int blocks_per_cu) {
   uint64_t g = (uint64_t)qk_num_cus() * blocks_per_cu;
   if (g > (uint64_t)kMaxPartialBlocks) g = kMaxPartialBlocks;
   if (g > tiles) g = tiles;
+  const uint64_t wcap = (rows * (uint64_t)B + kMinBlockWork - 1) / kMinBlockWork;
+  if (g > wcap) g = wcap;
   g = ((g + kNumXcd - 1) / kNumXcd) * kNumXcd;
   if (g < kNumXcd) g = kNumXcd;
   return (int)g;
@@ -700,6 +381,8 @@ static HamView<S> ham_view(const qk_ham* H) {
   v.D = (uint32_t)H->basis->D;
   return v;
 }
+
+HamView<uint32_t> ham_view32(const qk_ham* H) { return ham_view<uint32_t>(H); }
 
 ModelArgs model_args(const qk_ham* H) {
   ModelArgs a;

@@ -132,7 +132,7 @@ k_split_hi(HiArgs ha, const typename Cx<T>::V* __restrict__ x, const typename Cx
   __shared__ int act[1];
   for (int i = threadIdx.x; i < kBinomStride * kBinomStride; i += kHiThreads) sbin[i] = ha.binom[i];
   if (LANCZOS) {
-    lanczos_h_scalars(1, st, la, partB, Gp, red, tot, sa, sb, act);
+    lanczos_h_scalars(1, st, la, partB, Gp, red, tot, sa, sb, act, hw_grid());
   } else {
     if (threadIdx.x == 0) {
       sa[0] = 1.0;
