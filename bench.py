@@ -16,7 +16,8 @@ complex128 chain from the Neel state to t = 100 with error-controlled steps
 (tolerance 1e-7 per unit time), the evolution the paper times in Sec. 5, and
 reports its step count and wall time; `mixed` times the batched workload of
 64 phases of the L = 20 ring plus single rings of L = 16, 18, 20, 22 (h = 2,
-complex64, one hipGraph replay per step); `large` times Krylov steps of the
+complex64, one hipGraph replay per step, and in the default launch shape the
+graph of plain launches against the persistent step kernel); `large` times Krylov steps of the
 L = 30 ring (m = 20, dt = 0.05, complex128 and complex64).  Every rate is the
 median of --repeats timed runs of exactly --steps steps.  Also reported: standalone
 y = H x throughput (algorithmic bytes 2 s D per call), a device-copy ceiling,
@@ -44,7 +45,7 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_lanczos_h_L28.json")
 # sources of the blocked H-pass kernel; stored counter bytes are used only
 # while these files are unchanged
 KERNEL_SRCS = [os.path.join(ROOT, "paper_1704_02770_amd", "csrc", f)
-               for f in ("qk_blocked.hip", "qk_blocked.h", "qk_device.h")]
+               for f in ("qk_blocked.hip", "qk_blocked_bodies.h", "qk_blocked.h", "qk_device.h")]
 
 
 def log(*a):
@@ -183,6 +184,22 @@ def run_mixed(qk, torch, steps, warmup, repeats, m=30, dt=0.1, h=2.0, tune=True)
         torch.cuda.synchronize()
         secs.append(time.perf_counter() - t0)
     sec = statistics.median(secs)
+    # the same members in the default launch shape, one hipGraph of plain
+    # launches per step against one persistent kernel per step (the
+    # persistent step takes 256-thread row-streaming blocks)
+    for k in ks:
+        qk.qk_krylov_set_shape(k)
+    default = {}
+    for mode in (1, 2):
+        qk.qk_batch_run(bt, dt, max(warmup, 1), use_graph=mode)
+        ms = []
+        for _ in range(repeats):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            qk.qk_batch_run(bt, dt, steps, use_graph=mode, out=out)
+            torch.cuda.synchronize()
+            ms.append(time.perf_counter() - t0)
+        default[mode] = statistics.median(ms)
     # kernels of the 64-phase L = 20 workspace alone (eager steps with events)
     k64, psi64 = ks[0], psis[0]
     qk.qk_krylov_profile(k64, True)
@@ -193,7 +210,8 @@ def run_mixed(qk, torch, steps, warmup, repeats, m=30, dt=0.1, h=2.0, tune=True)
     qk.qk_krylov_profile(k64, False)
     D20 = qk.qk_basis_dim(hold[0][0])
     res = dict(items=items, steps=steps, sec=sec, sec_all=secs, phase_steps_per_s=items * steps / sec,
-               steps_per_s=steps / sec, prof64=prof, D20=D20)
+               steps_per_s=steps / sec, prof64=prof, D20=D20, sec_graph_default=default[1],
+               sec_persistent=default[2])
     bt.close()
     del ks, psis, hold
     torch.cuda.synchronize()
@@ -646,6 +664,12 @@ def main():
             items=mixed["items"], steps=mixed["steps"], phase_steps_per_s=round(mixed["phase_steps_per_s"], 1),
             steps_per_s=round(mixed["steps_per_s"], 2), ms_per_step=round(1e3 * mixed["sec"] / mixed["steps"], 3),
             ms_per_step_runs=[round(1e3 * x / mixed["steps"], 3) for x in mixed["sec_all"]],
+            default_shape=dict(
+                graph_ms_per_step=round(1e3 * mixed["sec_graph_default"] / mixed["steps"], 3),
+                persistent_ms_per_step=round(1e3 * mixed["sec_persistent"] / mixed["steps"], 3),
+                persistent_phase_steps_per_s=round(mixed["items"] * mixed["steps"] / mixed["sec_persistent"], 1),
+                note="the members in the default launch shape: one hipGraph of plain launches per step "
+                     "against one persistent kernel per step (qk_batch_run use_graph=2; same bits)"),
             roofline_L20x64=hpass_roofline(mixed["prof64"], 30, mixed["D20"], 64, 8, None),
             kernels_L20x64={kname: dict(ms_per_launch=ms_ / max(n_, 1), launches=n_)
                             for kname, (ms_, n_) in mixed["prof64"].items()})

@@ -16,7 +16,9 @@ struct PArgs {
   const PWork* ws;     // [workspaces]
   const PSeg* seg;     // [nseg] passes in queue order
   const int* deps;     // dependency list (pass indices)
-  int nseg, nitems;
+  const int* xfirst;   // [nseg][8]: first item of each pass in each XCD's queue
+  int nseg;
+  int xitems[8];       // items in each XCD's queue
   int* ctr;            // claim, exits, abort flag, done counter per pass
   double* P;           // records P[step][items]
   double* C;           // autocorrelation records, or NULL

@@ -15,15 +15,20 @@
 // passes of all workspaces are laid out in one queue, pass index by pass
 // index (workspace 0's first pass, workspace 1's first pass, ..., workspace
 // 0's second pass, ...), followed by the batch-wide autocorrelation step.
-// Work-groups claim queue items (tiles) in order with one atomic counter;
-// before running a tile, a work-group waits until the pass it depends on
-// (the previous pass of the same workspace; for the autocorrelation, the
-// record of every workspace) is complete.  Every pass depends only on passes
-// that come earlier in the queue, and an item is claimed only by a running
-// work-group, so the earliest unfinished item can always proceed: the launch
-// completes whether or not all work-groups are resident at once.  Different
-// workspaces' passes run side by side on the chip, without a launch gap
-// between the passes of one workspace.
+// The queue is dealt to eight sub-queues, one per XCD: tile t of a pass goes
+// to sub-queue t % 8, and work-group w takes its items from sub-queue w % 8
+// (the XCD it runs on), so that virtual block v runs on XCD v % 8 as in the
+// plain launch, whose block-to-XCD mapping keeps neighbouring blocks in one
+// XCD's L2.  Work-groups claim the items of their sub-queue in order with one
+// atomic counter per sub-queue; before running a tile, a work-group waits
+// until the pass it depends on (the previous pass of the same workspace; for
+// the autocorrelation, the record of every workspace) is complete.  Every
+// pass depends only on passes that come earlier in every sub-queue, and an
+// item is claimed only by a running work-group, so the tiles of the earliest
+// unfinished pass have all been claimed by work-groups that can proceed:
+// the launch completes whether or not all work-groups are resident at once.
+// Different workspaces' passes run side by side on the chip, without a
+// launch gap between the passes of one workspace.
 //
 // Each virtual block runs the same kernel body as the plain launch
 // (qk_blocked_bodies.h, qk_step_bodies.h) with the same block index and grid
@@ -86,7 +91,6 @@ struct PSeg {
   int vn;        // virtual grid of the pass (the plain launch's grid)
   int per;       // virtual blocks per tile
   int ntiles;    // tiles: ceil(vn / per)
-  int first;     // first queue item of the pass
   int dep0;      // first entry of the pass's dependencies in the dependency list
   int ndep;
 };
@@ -121,14 +125,15 @@ struct PWork {
   int item_off;
 };
 
-// Counters, one 128-byte line each: claim, exits, abort flag, then the done
-// counter of every pass, then the ready flag of every pass.
+// Counters, one 128-byte line each: the claim counter of each XCD's queue,
+// exits, abort flag, then the done counter of every pass, then the ready flag
+// of every pass.
 constexpr int kLine = 32;   // ints per line
-constexpr int kCtrClaim = 0, kCtrExit = kLine, kCtrAbort = 2 * kLine, kCtrDone = 3 * kLine;
+constexpr int kCtrClaim = 0, kCtrExit = kNumXcd * kLine, kCtrAbort = kCtrExit + kLine, kCtrDone = kCtrAbort + kLine;
 __host__ __device__ inline int ctr_done(int seg) { return kCtrDone + seg * kLine; }
 __host__ __device__ inline int ctr_ready(int seg, int nseg) { return kCtrDone + (nseg + seg) * kLine; }
 __host__ __device__ inline size_t ctr_ints(int nseg) { return (size_t)kCtrDone + 2 * (size_t)nseg * kLine; }
-constexpr int kSegLds = 4096;         // passes whose first items a work-group keeps in LDS
+constexpr int kSegLds = 4096;         // passes whose first items a work-group keeps in LDS (its queue's)
 constexpr double kTileWork = 8192;    // (row, column) elements a tile covers at least
 constexpr double kWaitSeconds = 5.0;  // bound on a work-group's waiting in one launch
 
@@ -259,11 +264,13 @@ __global__ void __launch_bounds__(kMaxBlock, 4) k_persist(PArgs pa) {
   extern __shared__ unsigned char smem[];
   __shared__ int s_seg, s_tile, s_stop;
   int* ctr = pa.ctr;
-  // first queue item of every pass, after the bodies' LDS (when it fits), for
-  // the search of the pass holding a claimed item
+  const int xq = (int)(blockIdx.x % kNumXcd);   // this work-group's sub-queue
+  const int* xfirst = pa.xfirst + xq;           // stride kNumXcd
+  // first item of every pass in this sub-queue, after the bodies' LDS (when
+  // it fits), for the search of the pass holding a claimed item
   int* sfirst = pa.nseg <= kSegLds ? reinterpret_cast<int*>(smem + pa.body_smem) : nullptr;
   if (sfirst)
-    for (int i = threadIdx.x; i < pa.nseg; i += blockDim.x) sfirst[i] = pa.seg[i].first;
+    for (int i = threadIdx.x; i < pa.nseg; i += blockDim.x) sfirst[i] = xfirst[(size_t)i * kNumXcd];
   __syncthreads();
   long long waited = 0;   // wall-clock ticks this work-group has spent waiting (thread 0)
   for (;;) {
@@ -272,20 +279,22 @@ __global__ void __launch_bounds__(kMaxBlock, 4) k_persist(PArgs pa) {
       if (ld_agent(ctr + kCtrAbort) != 0) {
         stop = 1;   // a wait gave up: claim nothing more
       } else {
-        const int item = atomicAdd(ctr + kCtrClaim, 1);
-        if (item >= pa.nitems) {
+        const int item = atomicAdd(ctr + kCtrClaim + xq * kLine, 1);
+        if (item >= pa.xitems[xq]) {
           stop = 1;
         } else {
-          // the pass holding this item: the last pass whose first item is <= item
+          // the pass holding this item: the last pass whose first item in
+          // this sub-queue is <= item (passes with no tile here share their
+          // first item with the next pass, so the last one is the holder)
           int lo = 0, hi = pa.nseg - 1;
           while (lo < hi) {
             const int mid = (lo + hi + 1) / 2;
-            if ((sfirst ? sfirst[mid] : pa.seg[mid].first) <= item) lo = mid;
+            if ((sfirst ? sfirst[mid] : xfirst[(size_t)mid * kNumXcd]) <= item) lo = mid;
             else hi = mid - 1;
           }
           seg = lo;
           const PSeg sg = pa.seg[lo];
-          tile = item - sg.first;
+          tile = xq + kNumXcd * (item - (sfirst ? sfirst[lo] : xfirst[(size_t)lo * kNumXcd]));
           // wait for the passes this one depends on: poll their ready flags,
           // sleeping 64 * ns cycles between polls, ns doubling up to 64
           for (int d = 0; d < sg.ndep && !stop; ++d) {
@@ -355,7 +364,7 @@ __global__ void __launch_bounds__(kMaxBlock, 4) k_persist(PArgs pa) {
         ctr[ctr_done(i)] = 0;
         ctr[ctr_ready(i, pa.nseg)] = 0;
       }
-      ctr[kCtrClaim] = 0;
+      for (int x = 0; x < kNumXcd; ++x) ctr[kCtrClaim + x * kLine] = 0;
       ctr[kCtrExit] = 0;
     }
   }
@@ -365,13 +374,15 @@ __global__ void __launch_bounds__(kMaxBlock, 4) k_persist(PArgs pa) {
 struct PersistPlan {
   qk_allocator al;
   int dtype = 0;
-  int nseg = 0, nitems = 0, grid = 0;
+  int nseg = 0, grid = 0;
+  int xitems[kNumXcd] = {0};
   size_t body_smem = 0;   // LDS of the largest kernel body
   size_t smem = 0;        // dynamic LDS of the launch: bodies, then the pass index
   long long wait_ticks = 0;   // wall-clock ticks of kWaitSeconds
   PWork* d_ws = nullptr;
   PSeg* d_seg = nullptr;
   int* d_deps = nullptr;
+  int* d_xfirst = nullptr;
   int* d_ctr = nullptr;
 };
 
@@ -380,6 +391,7 @@ void persist_free(PersistPlan* p) {
   dev_free(p->al, p->d_ws);
   dev_free(p->al, p->d_seg);
   dev_free(p->al, p->d_deps);
+  dev_free(p->al, p->d_xfirst);
   dev_free(p->al, p->d_ctr);
   delete p;
 }
@@ -484,7 +496,6 @@ qk_status persist_plan(const PersistInput& in, PersistPlan** out) {
   std::vector<int> last(n, -1);
   size_t longest = 0;
   for (int i = 0; i < n; ++i) longest = chain[i].size() > longest ? chain[i].size() : longest;
-  int items = 0;
   for (size_t p = 0; p < longest; ++p) {
     for (int i = 0; i < n; ++i) {
       if (p >= chain[i].size()) continue;
@@ -493,42 +504,51 @@ qk_status persist_plan(const PersistInput& in, PersistPlan** out) {
       int per = ps.work >= kTileWork ? 1 : (int)std::ceil(kTileWork / (ps.work > 1.0 ? ps.work : 1.0));
       if (per > ps.vn) per = ps.vn;
       const int ntiles = (ps.vn + per - 1) / per;
-      PSeg sg{i, ps.kind, ps.j, ps.vn, per, ntiles, items, (int)deps.size(), 0};
+      PSeg sg{i, ps.kind, ps.j, ps.vn, per, ntiles, (int)deps.size(), 0};
       if (last[i] >= 0) {
         deps.push_back(last[i]);
         sg.ndep = 1;
       }
       last[i] = (int)segs.size();
       segs.push_back(sg);
-      items += ntiles;
     }
   }
   {
-    PSeg sg{-1, PK_AUTO, 0, 1, 1, 1, items, (int)deps.size(), n};
+    PSeg sg{-1, PK_AUTO, 0, 1, 1, 1, (int)deps.size(), n};
     for (int i = 0; i < n; ++i) deps.push_back(last[i]);
     segs.push_back(sg);
-    items += 1;
   }
+  // the XCD sub-queues: tile t of a pass goes to sub-queue t % 8
+  std::vector<int> xfirst(segs.size() * kNumXcd);
+  int xitems[kNumXcd] = {0};
+  for (size_t g = 0; g < segs.size(); ++g)
+    for (int x = 0; x < kNumXcd; ++x) {
+      xfirst[g * kNumXcd + x] = xitems[x];
+      xitems[x] += segs[g].ntiles > x ? (segs[g].ntiles - x + kNumXcd - 1) / kNumXcd : 0;
+    }
   PersistPlan* pl = new (std::nothrow) PersistPlan;
   if (!pl) return QK_ENOMEM;
   pl->al = in.al;
   pl->dtype = dtype;
   pl->nseg = (int)segs.size();
-  pl->nitems = items;
+  for (int x = 0; x < kNumXcd; ++x) pl->xitems[x] = xitems[x];
   pl->body_smem = (smem + 15) & ~(size_t)15;
   pl->smem = pl->body_smem + (segs.size() <= (size_t)kSegLds ? sizeof(int) * segs.size() : 0);
   auto kern = dtype == QK_C128 ? k_persist<double> : k_persist<float>;
   int occ = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, kMaxBlock, pl->smem) != hipSuccess || occ < 1) occ = 1;
-  pl->grid = qk_num_cus() * occ;
+  pl->grid = ((qk_num_cus() * occ + kNumXcd - 1) / kNumXcd) * kNumXcd;   // every sub-queue has work-groups
   hipError_t e = dev_alloc(pl->al, (void**)&pl->d_ws, sizeof(PWork) * ws.size());
   if (e == hipSuccess) e = dev_alloc(pl->al, (void**)&pl->d_seg, sizeof(PSeg) * segs.size());
   if (e == hipSuccess) e = dev_alloc(pl->al, (void**)&pl->d_deps, sizeof(int) * (deps.empty() ? 1 : deps.size()));
+  if (e == hipSuccess) e = dev_alloc(pl->al, (void**)&pl->d_xfirst, sizeof(int) * xfirst.size());
   if (e == hipSuccess) e = dev_alloc(pl->al, (void**)&pl->d_ctr, sizeof(int) * ctr_ints(pl->nseg));
   if (e == hipSuccess) e = hipMemcpy(pl->d_ws, ws.data(), sizeof(PWork) * ws.size(), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(pl->d_seg, segs.data(), sizeof(PSeg) * segs.size(), hipMemcpyHostToDevice);
   if (e == hipSuccess && !deps.empty())
     e = hipMemcpy(pl->d_deps, deps.data(), sizeof(int) * deps.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = hipMemcpy(pl->d_xfirst, xfirst.data(), sizeof(int) * xfirst.size(), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemset(pl->d_ctr, 0, sizeof(int) * ctr_ints(pl->nseg));
   int khz = 0;
   if (e == hipSuccess) e = hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, in.ks[0]->device);
@@ -549,7 +569,8 @@ qk_status persist_launch(const PersistPlan* pl, double dt, double* P, double* C,
   pa.seg = pl->d_seg;
   pa.deps = pl->d_deps;
   pa.nseg = pl->nseg;
-  pa.nitems = pl->nitems;
+  pa.xfirst = pl->d_xfirst;
+  for (int x = 0; x < kNumXcd; ++x) pa.xitems[x] = pl->xitems[x];
   pa.ctr = pl->d_ctr;
   pa.P = P;
   pa.C = C;
