@@ -40,9 +40,9 @@
 // and one thread issues an agent-scope release fence (the L2 writeback that
 // makes the tile's results visible to the other XCDs; one per work-group, not
 // one per wave, which made the passes up to twice as long) and adds 1 to the
-// pass's done counter (acquire-release, so that the tile completing the pass
-// also carries every earlier tile's results); that tile then sets the pass's
-// ready flag.  Waiting work-groups poll only the ready flag (written once per
+// pass's done counter; the tile completing the pass then issues an acquire
+// fence (so that it carries every earlier tile's results) and sets the
+// pass's ready flag with a release store.  Waiting work-groups poll only the ready flag (written once per
 // launch, on a cache line of its own, so the polls never contend with the
 // counter's atomic adds), with a growing sleep between polls; the polling
 // thread then issues an agent-scope acquire fence (which invalidates the
@@ -134,7 +134,7 @@ __host__ __device__ inline int ctr_done(int seg) { return kCtrDone + seg * kLine
 __host__ __device__ inline int ctr_ready(int seg, int nseg) { return kCtrDone + (nseg + seg) * kLine; }
 __host__ __device__ inline size_t ctr_ints(int nseg) { return (size_t)kCtrDone + 2 * (size_t)nseg * kLine; }
 constexpr int kSegLds = 4096;         // passes whose first items a work-group keeps in LDS (its queue's)
-constexpr double kTileWork = 8192;    // (row, column) elements a tile covers at least
+constexpr double kTileWork = 512;     // (row, column) elements a tile covers at least
 constexpr double kWaitSeconds = 5.0;  // bound on a work-group's waiting in one launch
 
 __device__ __forceinline__ int ld_agent(const int* p) {
@@ -350,9 +350,14 @@ __global__ void __launch_bounds__(kMaxBlock, 4) k_persist(PArgs pa) {
     __syncthreads();
     if (threadIdx.x == 0) {
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-      const int done = __hip_atomic_fetch_add(ctr + ctr_done(seg), 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-      if (done == sg.ntiles - 1)   // the pass's last tile: every tile's results are released
+      const int done = __hip_atomic_fetch_add(ctr + ctr_done(seg), 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (done == sg.ntiles - 1) {
+        // the pass's last tile: its acquire fence pairs with every other
+        // tile's release fence through the counter, and the release store of
+        // the flag passes all their results on to the waiting work-groups
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         __hip_atomic_store(ctr + ctr_ready(seg, pa.nseg), 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      }
     }
   }
   // the last work-group to leave resets the counters for the next launch
