@@ -115,20 +115,22 @@ k_grad_coeffs(KState fw, KState bw, const double* __restrict__ Cn, double* __res
 }
 
 // Per row r: s_r = sum_c conj(u'_c[r]) sum_d C~_cd u_d[r] (u_0 = psi_k,
-// u'_0 = lambda_{k+1}, further vectors from the workspace slots).  Four
-// lanes share two rows: lane g accumulates t_c = sum_d C~_cd u_d of both
-// rows for the columns c = g, g+4, ... (at most eight), so each C~ value read
-// from LDS serves two rows and every lane holds sixteen accumulators; the
-// four partial sums of s_r are combined by lane shuffles.  Every tile of 128
-// rows puts its s_r and states in LDS, and thread q < 2(L_max+1) adds
-// component q&1 of s_r over the tile's rows whose state has bit q>>1 set
-// (q>>1 == L_max: all rows), so each block writes 2(L_max+1) partial sums.
+// u'_0 = lambda_{k+1}, further vectors from the workspace slots).  A block
+// takes tiles of kGcRows consecutive positions: it stages u_d of the tile's
+// rows for every d in LDS, from registers loaded while the previous tile was
+// computed (the contraction reads 2m vectors per row once each, so it is
+// bound by how many of those reads are in flight); then thread (g, j) computes t_c = sum_d C~_cd u_d for
+// row j and the columns c = g, g + kGcGroups, ... (C~ read from LDS, the
+// same address for the 32 threads of a row group), loads its u'_c directly
+// and forms its share of s_j; the kGcGroups shares of a row are added in
+// group order.  The tile's s_r and states then go to LDS, and thread
+// q < 2(L_max+1) adds component q&1 of s_r over the tile's rows whose state
+// has bit q>>1 set (q>>1 == L_max: all rows), so each block writes
+// 2(L_max+1) partial sums.
 constexpr int kGradQ = 2 * (QK_MAX_L + 1);
-constexpr int kGradLanesPerRow = 4;
-constexpr int kGradRowsPerLane = 2;
-constexpr int kGradCPer = kGradMaxM / kGradLanesPerRow;
-constexpr int kGradGroups = 256 / kGradLanesPerRow;            // lane groups of a 256-thread block
-constexpr int kGradRows = kGradGroups * kGradRowsPerLane;       // rows per tile
+constexpr int kGcRows = 32;                          // rows per tile
+constexpr int kGcGroups = 256 / kGcRows;             // column groups
+constexpr int kGcCPer = kGradMaxM / kGcGroups;       // columns per thread
 
 template <typename S>
 __global__ void __launch_bounds__(256, 4)
@@ -140,84 +142,98 @@ k_grad_contract(const S* __restrict__ states, uint64_t niter, int L, const doubl
   // the sorted basis, or, with line tables, elements of the padded layout
   // whose row comes from their line's entry (unused padding is skipped)
   __shared__ double2 C[kGradMaxM * kGradMaxM];
-  __shared__ double2 sbuf[kGradRows];
-  __shared__ S sst[kGradRows];
+  __shared__ double2 Us[kGradMaxM * kGcRows];   // [d][row of the tile]
+  __shared__ double2 sp[kGcGroups * kGcRows];   // share of s per column group
+  __shared__ double2 sbuf[kGcRows];
+  __shared__ S sst[kGcRows];
   const int tid = threadIdx.x;
   for (int i = tid; i < kGradMaxM * kGradMaxM; i += blockDim.x) C[i] = make_double2(Ct[2 * i], Ct[2 * i + 1]);
   __syncthreads();
   const int muf = fw.mused[0] < kGradMaxM ? fw.mused[0] : kGradMaxM;
   const int mub = bw.mused[0] < kGradMaxM ? bw.mused[0] : kGradMaxM;
   const int site = tid >> 1, comp = tid & 1;
-  const int grp = tid / kGradLanesPerRow, lg = tid % kGradLanesPerRow;
+  const int g = tid / kGcRows, jr = tid % kGcRows;
+  // row and validity of position p
+  auto locate = [&](uint64_t p, size_t* r) -> bool {
+    *r = (size_t)p;
+    if (p >= niter) return false;
+    if (!line_r0) return true;
+    const uint64_t ln = p / (uint64_t)pe;
+    const uint32_t e = (uint32_t)(p - ln * (uint64_t)pe);
+    *r = (size_t)line_r0[ln] + e;
+    return e < line_n[ln];
+  };
+  // staging: element e = d * kGcRows + jj of a tile is u_d at the tile's
+  // row jj; thread tid holds elements tid + 256 i.  The next tile's elements
+  // are loaded while the current tile is computed.
+  constexpr int kPre = kGradMaxM * kGcRows / 256;
+  auto fetch = [&](uint64_t base, double2 (&v)[kPre]) {
+#pragma unroll
+    for (int i = 0; i < kPre; ++i) {
+      const int e = tid + 256 * i, d = e / kGcRows, jj = e % kGcRows;
+      const uint64_t p = base + (uint64_t)jj;
+      size_t r;
+      const bool ok = d < muf && locate(p, &r);
+      v[i] = !ok ? make_double2(0.0, 0.0) : (d == 0 ? psi_k[r] : Uf[(size_t)(d - 1) * stride + p]);
+    }
+  };
+  double2 pre[kPre];
+  const uint64_t step = (uint64_t)gridDim.x * kGcRows;
+  if ((uint64_t)blockIdx.x * kGcRows < niter) fetch((uint64_t)blockIdx.x * kGcRows, pre);
   double acc = 0.0;
-  for (uint64_t base = (uint64_t)blockIdx.x * kGradRows; base < niter; base += (uint64_t)gridDim.x * kGradRows) {
-    uint64_t p[kGradRowsPerLane];
-    size_t r[kGradRowsPerLane];
-    bool valid[kGradRowsPerLane];
+  for (uint64_t base = (uint64_t)blockIdx.x * kGcRows; base < niter; base += step) {
 #pragma unroll
-    for (int i = 0; i < kGradRowsPerLane; ++i) {
-      p[i] = base + (uint64_t)i * kGradGroups + grp;   // consecutive lane groups take consecutive rows
-      valid[i] = p[i] < niter;
-      r[i] = (size_t)p[i];
-      if (valid[i] && line_r0) {
-        const uint64_t ln = p[i] / (uint64_t)pe;
-        const uint32_t e = (uint32_t)(p[i] - ln * (uint64_t)pe);
-        valid[i] = e < line_n[ln];
-        r[i] = (size_t)line_r0[ln] + e;
-      }
+    for (int i = 0; i < kPre; ++i) Us[tid + 256 * i] = pre[i];
+    // this thread's row and its costate values u'_c, c = g + kGcGroups k
+    const uint64_t p = base + (uint64_t)jr;
+    size_t r;
+    const bool valid = locate(p, &r);
+    double2 w[kGcCPer];
+#pragma unroll
+    for (int k = 0; k < kGcCPer; ++k) {
+      const int c = g + kGcGroups * k;
+      w[k] = (valid && c < mub) ? (c == 0 ? lam[r] : Ub[(size_t)(c - 1) * stride + p]) : make_double2(0.0, 0.0);
     }
-    double tr[kGradRowsPerLane][kGradCPer], ti[kGradRowsPerLane][kGradCPer];
+    __syncthreads();
+    if (base + step < niter) fetch(base + step, pre);   // in flight while this tile is computed
+    double tr[kGcCPer], ti[kGcCPer];
 #pragma unroll
-    for (int i = 0; i < kGradRowsPerLane; ++i)
-#pragma unroll
-      for (int k = 0; k < kGradCPer; ++k) tr[i][k] = ti[i][k] = 0.0;
+    for (int k = 0; k < kGcCPer; ++k) tr[k] = ti[k] = 0.0;
     for (int d = 0; d < muf; ++d) {
-      double2 u[kGradRowsPerLane];
+      const double2 u = Us[d * kGcRows + jr];
 #pragma unroll
-      for (int i = 0; i < kGradRowsPerLane; ++i)
-        u[i] = !valid[i] ? make_double2(0.0, 0.0) : (d == 0 ? psi_k[r[i]] : Uf[(size_t)(d - 1) * stride + p[i]]);
-#pragma unroll
-      for (int k = 0; k < kGradCPer; ++k) {
-        const double2 cc = C[(lg + kGradLanesPerRow * k) * kGradMaxM + d];
-#pragma unroll
-        for (int i = 0; i < kGradRowsPerLane; ++i) {
-          tr[i][k] += cc.x * u[i].x - cc.y * u[i].y;
-          ti[i][k] += cc.x * u[i].y + cc.y * u[i].x;
-        }
+      for (int k = 0; k < kGcCPer; ++k) {
+        const double2 cc = C[(g + kGcGroups * k) * kGradMaxM + d];
+        tr[k] += cc.x * u.x - cc.y * u.y;
+        ti[k] += cc.x * u.y + cc.y * u.x;
       }
     }
-    double sr[kGradRowsPerLane], si[kGradRowsPerLane];
+    double sr = 0.0, si = 0.0;
 #pragma unroll
-    for (int i = 0; i < kGradRowsPerLane; ++i) {
-      sr[i] = si[i] = 0.0;
-#pragma unroll
-      for (int k = 0; k < kGradCPer; ++k) {
-        const int c = lg + kGradLanesPerRow * k;
-        if (valid[i] && c < mub) {
-          const double2 w = c == 0 ? lam[r[i]] : Ub[(size_t)(c - 1) * stride + p[i]];
-          sr[i] += w.x * tr[i][k] + w.y * ti[i][k];   // conj(w) t
-          si[i] += w.x * ti[i][k] - w.y * tr[i][k];
-        }
+    for (int k = 0; k < kGcCPer; ++k) {
+      sr += w[k].x * tr[k] + w[k].y * ti[k];   // conj(w) t
+      si += w[k].x * ti[k] - w[k].y * tr[k];
+    }
+    sp[g * kGcRows + jr] = make_double2(sr, si);
+    __syncthreads();
+    if (tid < kGcRows) {
+      double2 t = sp[tid];
+      for (int q = 1; q < kGcGroups; ++q) {
+        t.x += sp[q * kGcRows + tid].x;
+        t.y += sp[q * kGcRows + tid].y;
       }
-      // the four lanes of a group are adjacent in the wave
-      sr[i] += __shfl_xor(sr[i], 1);
-      si[i] += __shfl_xor(si[i], 1);
-      sr[i] += __shfl_xor(sr[i], 2);
-      si[i] += __shfl_xor(si[i], 2);
-      if (lg == 0) {
-        sbuf[i * kGradGroups + grp] = make_double2(sr[i], si[i]);
-        sst[i * kGradGroups + grp] = valid[i] ? states[r[i]] : (S)0;
-      }
+      sbuf[tid] = t;
+      sst[tid] = valid ? states[r] : (S)0;
     }
     __syncthreads();
     if (tid < kGradQ && (site < L || site == QK_MAX_L)) {
-      for (int q = 0; q < kGradRows; ++q) {
+      for (int q = 0; q < kGcRows; ++q) {
         const bool on = site == QK_MAX_L || ((sst[q] >> site) & (S)1);
         const double v = comp ? sbuf[q].y : sbuf[q].x;
         acc += on ? v : 0.0;
       }
     }
-    __syncthreads();
+    __syncthreads();   // Us, sp and sbuf are written again by the next tile
   }
   if (tid < kGradQ) part[(size_t)blockIdx.x * kGradQ + tid] = acc;
 }
