@@ -114,23 +114,64 @@ k_grad_coeffs(KState fw, KState bw, const double* __restrict__ Cn, double* __res
   Ct[2 * e + 1] = sc * ci;
 }
 
-// Per row r: s_r = sum_c conj(u'_c[r]) sum_d C~_cd u_d[r] (u_0 = psi_k,
-// u'_0 = lambda_{k+1}, further vectors from the workspace slots).  A block
-// takes tiles of kGcRows consecutive positions: it stages u_d of the tile's
-// rows for every d in LDS, from registers loaded while the previous tile was
-// computed (the contraction reads 2m vectors per row once each, so it is
-// bound by how many of those reads are in flight); then thread (g, j) computes t_c = sum_d C~_cd u_d for
-// row j and the columns c = g, g + kGcGroups, ... (C~ read from LDS, the
-// same address for the 32 threads of a row group), loads its u'_c directly
-// and forms its share of s_j; the kGcGroups shares of a row are added in
-// group order.  The tile's s_r and states then go to LDS, and thread
-// q < 2(L_max+1) adds component q&1 of s_r over the tile's rows whose state
-// has bit q>>1 set (q>>1 == L_max: all rows), so each block writes
-// 2(L_max+1) partial sums.
+// Per row r: s_r = sum_c conj(u'_c[r]) t_c[r], t = C~ u[r] (u_0 = psi_k,
+// u'_0 = lambda_{k+1}, further vectors from the workspace slots).  t = C~ U
+// over all rows is a dense product (m x m times m x rows), done on the FP64
+// matrix cores in its real form: the complex C~ becomes the 2m x 2m real
+// matrix R with R[2c][2d] = R[2c+1][2d+1] = Re C~_cd, R[2c][2d+1] = -Im C~_cd,
+// R[2c+1][2d] = Im C~_cd, and the interleaved (re, im) rows of the basis are
+// the other operand.  One wavefront takes tiles of 16 consecutive positions
+// (the N of one 16x16x4 FP64 MFMA):
+//   * lane (q, n), q = lane / 16, n = lane % 16, loads u_d at position n for
+//     d = 4s + q (s = 0..7) as one 16-byte load; its real and imaginary parts
+//     are the B operands of K-steps 2s and 2s + 1, so K-step k of quarter q
+//     is real column 2(4(k/2) + q) + k%2 of R;
+//   * the A operands (R in that K order, per M-block of 16 real rows) are
+//     read from LDS, where the block stored them in fragment order;
+//   * register v of lane (q, n) of the MFMA's output holds output row
+//     4v + q at position n, so R's rows are ordered to make output row 4v + q
+//     of M-block b the component v % 2 of t_c, c = 8b + 2q + v / 2: the lane
+//     holds t_c for c = 8b + 2q and c + 1 (re, im, re, im), loads u'_c for
+//     those c and forms its share of s_n; the four quarters' shares are added
+//     across lanes.
+// Lane i then adds s_n over the tile's positions whose state has bit i set,
+// every lane the total; per block the four waves' sums are added in wave
+// order into 2(L_max + 1) partial sums.
 constexpr int kGradQ = 2 * (QK_MAX_L + 1);
-constexpr int kGcRows = 32;                          // rows per tile
-constexpr int kGcGroups = 256 / kGcRows;             // column groups
-constexpr int kGcCPer = kGradMaxM / kGcGroups;       // columns per thread
+constexpr int kGcWaves = 4;                    // wavefronts per block
+constexpr int kGcN = 16;                       // positions per wavefront tile
+constexpr int kGcMb = 2 * kGradMaxM / 16;      // M-blocks of R (16 real rows each)
+constexpr int kGcKs = 2 * kGradMaxM / 4;       // K-steps of R (4 real columns each)
+constexpr int kGcFrag = kGcMb * kGcKs * 64;    // doubles of R in fragment order
+static_assert(kGradMaxM == 32, "fragment layout assumes 32 basis vectors: 8 K-step pairs, 4 M-blocks");
+
+typedef double gc_dbl4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ double gc_readlane(double v, int j) {
+  const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, j);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), j);
+  return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+__device__ __forceinline__ uint32_t gc_readlane(uint32_t v, int j) {
+  return (uint32_t)__builtin_amdgcn_readlane((int)v, j);
+}
+__device__ __forceinline__ uint64_t gc_readlane(uint64_t v, int j) {
+  const uint32_t lo = gc_readlane((uint32_t)v, j), hi = gc_readlane((uint32_t)(v >> 32), j);
+  return ((uint64_t)hi << 32) | lo;
+}
+
+// loads through a global-address-space pointer (plain loads, no flat ones
+// that would share the LDS wait counter)
+typedef double gc_dbl2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ double2 gc_ld(const double2* p) {
+  const gc_dbl2 v = *(const __attribute__((address_space(1))) gc_dbl2*)p;
+  return make_double2(v.x, v.y);
+}
+template <typename S>
+__device__ __forceinline__ S gc_ld(const S* p) {
+  return *(const __attribute__((address_space(1))) S*)p;
+}
 
 template <typename S>
 __global__ void __launch_bounds__(256, 4)
@@ -141,18 +182,23 @@ k_grad_contract(const S* __restrict__ states, uint64_t niter, int L, const doubl
   // niter positions of the workspace vectors (stride elements each): rows of
   // the sorted basis, or, with line tables, elements of the padded layout
   // whose row comes from their line's entry (unused padding is skipped)
-  __shared__ double2 C[kGradMaxM * kGradMaxM];
-  __shared__ double2 Us[kGradMaxM * kGcRows];   // [d][row of the tile]
-  __shared__ double2 sp[kGcGroups * kGcRows];   // share of s per column group
-  __shared__ double2 sbuf[kGcRows];
-  __shared__ S sst[kGcRows];
-  const int tid = threadIdx.x;
-  for (int i = tid; i < kGradMaxM * kGradMaxM; i += blockDim.x) C[i] = make_double2(Ct[2 * i], Ct[2 * i + 1]);
+  __shared__ double Af[kGcFrag];                // [M-block][K-step][lane]
+  __shared__ double red[kGcWaves][kGradQ];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  // R in fragment order: lane l of (b, k) holds the R entry of output row
+  // i = l % 16 (component (i / 4) % 2 of t_c, c = 8b + 2(i % 4) + i / 8) and
+  // of the column of K-step k for quarter l / 16
+  for (int e = tid; e < kGcFrag; e += blockDim.x) {
+    const int b = e / (kGcKs * 64), k = (e / 64) % kGcKs, l = e % 64, i = l % 16;
+    const int c = 8 * b + 2 * (i & 3) + (i >> 3), pc = (i >> 2) & 1;
+    const int d = 4 * (k >> 1) + l / 16, pd = k & 1;
+    const double cr = Ct[2 * (c * kGradMaxM + d)], ci = Ct[2 * (c * kGradMaxM + d) + 1];
+    Af[e] = pc == pd ? cr : (pc == 0 ? -ci : ci);
+  }
   __syncthreads();
   const int muf = fw.mused[0] < kGradMaxM ? fw.mused[0] : kGradMaxM;
   const int mub = bw.mused[0] < kGradMaxM ? bw.mused[0] : kGradMaxM;
-  const int site = tid >> 1, comp = tid & 1;
-  const int g = tid / kGcRows, jr = tid % kGcRows;
+  const int q = lane >> 4, n = lane & 15;
   // row and validity of position p
   auto locate = [&](uint64_t p, size_t* r) -> bool {
     *r = (size_t)p;
@@ -163,79 +209,87 @@ k_grad_contract(const S* __restrict__ states, uint64_t niter, int L, const doubl
     *r = (size_t)line_r0[ln] + e;
     return e < line_n[ln];
   };
-  // staging: element e = d * kGcRows + jj of a tile is u_d at the tile's
-  // row jj; thread tid holds elements tid + 256 i.  The next tile's elements
-  // are loaded while the current tile is computed.
-  constexpr int kPre = kGradMaxM * kGcRows / 256;
-  auto fetch = [&](uint64_t base, double2 (&v)[kPre]) {
-#pragma unroll
-    for (int i = 0; i < kPre; ++i) {
-      const int e = tid + 256 * i, d = e / kGcRows, jj = e % kGcRows;
-      const uint64_t p = base + (uint64_t)jj;
-      size_t r;
-      const bool ok = d < muf && locate(p, &r);
-      v[i] = !ok ? make_double2(0.0, 0.0) : (d == 0 ? psi_k[r] : Uf[(size_t)(d - 1) * stride + p]);
-    }
-  };
-  double2 pre[kPre];
-  const uint64_t step = (uint64_t)gridDim.x * kGcRows;
-  if ((uint64_t)blockIdx.x * kGcRows < niter) fetch((uint64_t)blockIdx.x * kGcRows, pre);
-  double acc = 0.0;
-  for (uint64_t base = (uint64_t)blockIdx.x * kGcRows; base < niter; base += step) {
-#pragma unroll
-    for (int i = 0; i < kPre; ++i) Us[tid + 256 * i] = pre[i];
-    // this thread's row and its costate values u'_c, c = g + kGcGroups k
-    const uint64_t p = base + (uint64_t)jr;
+  const double2 zero = make_double2(0.0, 0.0);
+  double ar = 0.0, ai = 0.0, tr = 0.0, ti = 0.0;   // site `lane`, and the total
+  const uint64_t ntiles = (niter + kGcN - 1) / kGcN;
+  const uint64_t wstep = (uint64_t)gridDim.x * kGcWaves;
+  for (uint64_t t = (uint64_t)blockIdx.x * kGcWaves + wv; t < ntiles; t += wstep) {
+    // the A fragments are read from LDS per tile: hoisted out of the loop
+    // they would need 128 registers per lane
+    __asm__ volatile("" ::: "memory");
+    const uint64_t p = t * kGcN + (uint64_t)n;
     size_t r;
     const bool valid = locate(p, &r);
-    double2 w[kGcCPer];
+    // every lane loads (unused vectors and positions from element 0 of
+    // psi_k) and zeroes what it does not use: no branches around the loads
+    const size_t rv = valid ? r : 0, pv = valid ? (size_t)p : 0;
+    double2 u[kGcKs / 2];
 #pragma unroll
-    for (int k = 0; k < kGcCPer; ++k) {
-      const int c = g + kGcGroups * k;
-      w[k] = (valid && c < mub) ? (c == 0 ? lam[r] : Ub[(size_t)(c - 1) * stride + p]) : make_double2(0.0, 0.0);
+    for (int s = 0; s < kGcKs / 2; ++s) {
+      const int d = 4 * s + q;
+      const bool on = valid && d < muf;
+      u[s] = gc_ld(d == 0 || !on ? psi_k + rv : Uf + ((size_t)(d - 1) * stride + pv));
+      if (!on) u[s] = zero;
     }
-    __syncthreads();
-    if (base + step < niter) fetch(base + step, pre);   // in flight while this tile is computed
-    double tr[kGcCPer], ti[kGcCPer];
+    double2 w[2 * kGcMb];
 #pragma unroll
-    for (int k = 0; k < kGcCPer; ++k) tr[k] = ti[k] = 0.0;
-    for (int d = 0; d < muf; ++d) {
-      const double2 u = Us[d * kGcRows + jr];
+    for (int h = 0; h < 2 * kGcMb; ++h) {
+      const int c = 8 * (h >> 1) + 2 * q + (h & 1);
+      const bool on = valid && c < mub;
+      w[h] = gc_ld(!on ? psi_k : (c == 0 ? lam + rv : Ub + ((size_t)(c - 1) * stride + pv)));
+      if (!on) w[h] = zero;
+    }
+    S st = gc_ld(states + rv);
+    if (!valid) st = (S)0;
+    gc_dbl4 acc[kGcMb];
 #pragma unroll
-      for (int k = 0; k < kGcCPer; ++k) {
-        const double2 cc = C[(g + kGcGroups * k) * kGradMaxM + d];
-        tr[k] += cc.x * u.x - cc.y * u.y;
-        ti[k] += cc.x * u.y + cc.y * u.x;
+    for (int b = 0; b < kGcMb; ++b) acc[b] = gc_dbl4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int s = 0; s < kGcKs / 2; ++s) {
+#pragma unroll
+      for (int b = 0; b < kGcMb; ++b) {
+        const double a0 = Af[(b * kGcKs + 2 * s) * 64 + lane], a1 = Af[(b * kGcKs + 2 * s + 1) * 64 + lane];
+        acc[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, u[s].x, acc[b], 0, 0, 0);
+        acc[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, u[s].y, acc[b], 0, 0, 0);
       }
     }
     double sr = 0.0, si = 0.0;
 #pragma unroll
-    for (int k = 0; k < kGcCPer; ++k) {
-      sr += w[k].x * tr[k] + w[k].y * ti[k];   // conj(w) t
-      si += w[k].x * ti[k] - w[k].y * tr[k];
+    for (int b = 0; b < kGcMb; ++b) {
+      const double2 w0 = w[2 * b], w1 = w[2 * b + 1];   // conj(u'_c) t_c
+      sr += w0.x * acc[b][0] + w0.y * acc[b][1];
+      si += w0.x * acc[b][1] - w0.y * acc[b][0];
+      sr += w1.x * acc[b][2] + w1.y * acc[b][3];
+      si += w1.x * acc[b][3] - w1.y * acc[b][2];
     }
-    sp[g * kGcRows + jr] = make_double2(sr, si);
-    __syncthreads();
-    if (tid < kGcRows) {
-      double2 t = sp[tid];
-      for (int q = 1; q < kGcGroups; ++q) {
-        t.x += sp[q * kGcRows + tid].x;
-        t.y += sp[q * kGcRows + tid].y;
-      }
-      sbuf[tid] = t;
-      sst[tid] = valid ? states[r] : (S)0;
+    // (q0 + q1) + (q2 + q3): every quarter ends with the same bits
+    sr += __shfl_xor(sr, 16);
+    si += __shfl_xor(si, 16);
+    sr += __shfl_xor(sr, 32);
+    si += __shfl_xor(si, 32);
+#pragma unroll
+    for (int j = 0; j < kGcN; ++j) {
+      const double sj = gc_readlane(sr, j), tj = gc_readlane(si, j);
+      const S stj = gc_readlane(st, j);
+      tr += sj;
+      ti += tj;
+      const bool on = lane < L && ((stj >> (lane & (8 * (int)sizeof(S) - 1))) & (S)1);
+      ar += on ? sj : 0.0;
+      ai += on ? tj : 0.0;
     }
-    __syncthreads();
-    if (tid < kGradQ && (site < L || site == QK_MAX_L)) {
-      for (int q = 0; q < kGcRows; ++q) {
-        const bool on = site == QK_MAX_L || ((sst[q] >> site) & (S)1);
-        const double v = comp ? sbuf[q].y : sbuf[q].x;
-        acc += on ? v : 0.0;
-      }
-    }
-    __syncthreads();   // Us, sp and sbuf are written again by the next tile
   }
-  if (tid < kGradQ) part[(size_t)blockIdx.x * kGradQ + tid] = acc;
+  red[wv][2 * lane] = lane < L ? ar : 0.0;
+  red[wv][2 * lane + 1] = lane < L ? ai : 0.0;
+  if (lane == 0) {
+    red[wv][2 * QK_MAX_L] = tr;
+    red[wv][2 * QK_MAX_L + 1] = ti;
+  }
+  __syncthreads();
+  if (tid < kGradQ) {
+    double v = red[0][tid];
+    for (int k = 1; k < kGcWaves; ++k) v += red[k][tid];
+    part[(size_t)blockIdx.x * kGradQ + tid] = v;
+  }
 }
 
 // dA[i] += -i (S_i - S_total / 2), the partial sums of the G contraction

@@ -166,3 +166,19 @@ def test_persistent_rejects_what_it_does_not_cover():
     assert np.all(np.isfinite(P)) and P.shape == (2, 2)
     with pytest.raises(ValueError):
         qk.qk_batch_run(bt, 0.1, 2, use_graph=3)
+
+
+def test_persistent_full_size_l28_bitwise():
+    # an L = 28 complex64 workspace (321 MB vectors: non-temporal update and
+    # combination, the 11-low-bit blocked H-pass on its full grid) batched
+    # with an L = 16 chain, two steps, persistent against the graph of plain
+    # launches
+    dtype = torch.complex64
+
+    def make():
+        ws = [_ws(28, 1, dtype, h=1.5, seed=91, m=30), _ws(16, 1, dtype, seed=92, m=30)]
+        return ws, [w["psi"] for w in ws], [w["r0"] for w in ws]
+
+    out = _run_modes(make, 2, 0.1, modes=(1, 2))
+    _assert_same(out, modes=(1, 2))
+    torch.cuda.empty_cache()
