@@ -115,7 +115,10 @@ k_grad_coeffs(KState fw, KState bw, const double* __restrict__ Cn, double* __res
 }
 
 // Per row r: s_r = sum_c conj(u'_c[r]) t_c[r], t = C~ u[r] (u_0 = psi_k,
-// u'_0 = lambda_{k+1}, further vectors from the workspace slots).  t = C~ U
+// u'_0 = lambda_{k+1}, further vectors from the workspace slots), and the
+// costate's step: lambda_k[r] = sum_c g_c u'_c[r] with the weights g of its
+// small exponential, written over lambda_{k+1} (each position is read and
+// written by the same lane group, so the costate basis is read once).  t = C~ U
 // over all rows is a dense product (m x m times m x rows), done on the FP64
 // matrix cores in its real form: the complex C~ becomes the 2m x 2m real
 // matrix R with R[2c][2d] = R[2c+1][2d+1] = Re C~_cd, R[2c][2d+1] = -Im C~_cd,
@@ -132,8 +135,8 @@ k_grad_coeffs(KState fw, KState bw, const double* __restrict__ Cn, double* __res
 //     4v + q at position n, so R's rows are ordered to make output row 4v + q
 //     of M-block b the component v % 2 of t_c, c = 8b + 2q + v / 2: the lane
 //     holds t_c for c = 8b + 2q and c + 1 (re, im, re, im), loads u'_c for
-//     those c and forms its share of s_n; the four quarters' shares are added
-//     across lanes.
+//     those c and forms its shares of s_n and of lambda_k[n]; the four
+//     quarters' shares are added across lanes.
 // Lane i then adds s_n over the tile's positions whose state has bit i set,
 // every lane the total; per block the four waves' sums are added in wave
 // order into 2(L_max + 1) partial sums.
@@ -176,7 +179,7 @@ __device__ __forceinline__ S gc_ld(const S* p) {
 template <typename S>
 __global__ void __launch_bounds__(256, 4)
 k_grad_contract(const S* __restrict__ states, uint64_t niter, int L, const double2* __restrict__ psi_k,
-                const double2* __restrict__ Uf, const double2* __restrict__ lam, const double2* __restrict__ Ub,
+                const double2* __restrict__ Uf, double2* __restrict__ lam, const double2* __restrict__ Ub,
                 size_t stride, const uint32_t* __restrict__ line_r0, const uint8_t* __restrict__ line_n, int pe,
                 KState fw, KState bw, const double* __restrict__ Ct, double* __restrict__ part) {
   // niter positions of the workspace vectors (stride elements each): rows of
@@ -184,6 +187,7 @@ k_grad_contract(const S* __restrict__ states, uint64_t niter, int L, const doubl
   // whose row comes from their line's entry (unused padding is skipped)
   __shared__ double Af[kGcFrag];                // [M-block][K-step][lane]
   __shared__ double red[kGcWaves][kGradQ];
+  __shared__ double2 gw[kGradMaxM];             // the costate's combination weights
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   // R in fragment order: lane l of (b, k) holds the R entry of output row
   // i = l % 16 (component (i / 4) % 2 of t_c, c = 8b + 2(i % 4) + i / 8) and
@@ -195,9 +199,12 @@ k_grad_contract(const S* __restrict__ states, uint64_t niter, int L, const doubl
     const double cr = Ct[2 * (c * kGradMaxM + d)], ci = Ct[2 * (c * kGradMaxM + d) + 1];
     Af[e] = pc == pd ? cr : (pc == 0 ? -ci : ci);
   }
-  __syncthreads();
   const int muf = fw.mused[0] < kGradMaxM ? fw.mused[0] : kGradMaxM;
   const int mub = bw.mused[0] < kGradMaxM ? bw.mused[0] : kGradMaxM;
+  // as the plain combination: a failed or empty costate step leaves lambda as it is
+  const bool comb = bw.status[0] == QK_OK && bw.mused[0] > 0;
+  if (tid < kGradMaxM) gw[tid] = tid < mub ? make_double2(bw.gre[tid], bw.gim[tid]) : make_double2(0.0, 0.0);
+  __syncthreads();
   const int q = lane >> 4, n = lane & 15;
   // row and validity of position p
   auto locate = [&](uint64_t p, size_t* r) -> bool {
@@ -223,12 +230,16 @@ k_grad_contract(const S* __restrict__ states, uint64_t niter, int L, const doubl
     // every lane loads (unused vectors and positions from element 0 of
     // psi_k) and zeroes what it does not use: no branches around the loads
     const size_t rv = valid ? r : 0, pv = valid ? (size_t)p : 0;
+    // slot offsets as one per-lane part and one uniform part per load (the
+    // uniform part of slot 4s + q - 1 wraps below zero only for d = 0,
+    // which reads psi_k instead)
+    const size_t lu = (size_t)q * stride + pv, lw = (size_t)(2 * q) * stride + pv;
     double2 u[kGcKs / 2];
 #pragma unroll
     for (int s = 0; s < kGcKs / 2; ++s) {
       const int d = 4 * s + q;
       const bool on = valid && d < muf;
-      u[s] = gc_ld(d == 0 || !on ? psi_k + rv : Uf + ((size_t)(d - 1) * stride + pv));
+      u[s] = gc_ld(d == 0 || !on ? psi_k + rv : Uf + (lu + (size_t)(4 * s - 1) * stride));
       if (!on) u[s] = zero;
     }
     double2 w[2 * kGcMb];
@@ -236,7 +247,7 @@ k_grad_contract(const S* __restrict__ states, uint64_t niter, int L, const doubl
     for (int h = 0; h < 2 * kGcMb; ++h) {
       const int c = 8 * (h >> 1) + 2 * q + (h & 1);
       const bool on = valid && c < mub;
-      w[h] = gc_ld(!on ? psi_k : (c == 0 ? lam + rv : Ub + ((size_t)(c - 1) * stride + pv)));
+      w[h] = gc_ld(!on ? psi_k : (c == 0 ? lam + rv : Ub + (lw + (size_t)(8 * (h >> 1) + (h & 1) - 1) * stride)));
       if (!on) w[h] = zero;
     }
     S st = gc_ld(states + rv);
@@ -253,7 +264,7 @@ k_grad_contract(const S* __restrict__ states, uint64_t niter, int L, const doubl
         acc[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, u[s].y, acc[b], 0, 0, 0);
       }
     }
-    double sr = 0.0, si = 0.0;
+    double sr = 0.0, si = 0.0, lr = 0.0, li = 0.0;
 #pragma unroll
     for (int b = 0; b < kGcMb; ++b) {
       const double2 w0 = w[2 * b], w1 = w[2 * b + 1];   // conj(u'_c) t_c
@@ -261,12 +272,23 @@ k_grad_contract(const S* __restrict__ states, uint64_t niter, int L, const doubl
       si += w0.x * acc[b][1] - w0.y * acc[b][0];
       sr += w1.x * acc[b][2] + w1.y * acc[b][3];
       si += w1.x * acc[b][3] - w1.y * acc[b][2];
+      const double2 g0 = gw[8 * b + 2 * q], g1 = gw[8 * b + 2 * q + 1];   // g_c u'_c
+      lr += g0.x * w0.x - g0.y * w0.y;
+      li += g0.x * w0.y + g0.y * w0.x;
+      lr += g1.x * w1.x - g1.y * w1.y;
+      li += g1.x * w1.y + g1.y * w1.x;
     }
     // (q0 + q1) + (q2 + q3): every quarter ends with the same bits
     sr += __shfl_xor(sr, 16);
     si += __shfl_xor(si, 16);
+    lr += __shfl_xor(lr, 16);
+    li += __shfl_xor(li, 16);
     sr += __shfl_xor(sr, 32);
     si += __shfl_xor(si, 32);
+    lr += __shfl_xor(lr, 32);
+    li += __shfl_xor(li, 32);
+    // lambda_{k+1}[r] was loaded by quarter 0 (c = 0), which now writes lambda_k[r]
+    if (comb && valid && q == 0) lam[r] = make_double2(lr, li);
 #pragma unroll
     for (int j = 0; j < kGcN; ++j) {
       const double sj = gc_readlane(sr, j), tj = gc_readlane(si, j);
@@ -372,7 +394,6 @@ qk_status grad_return_prob(qk_krylov* k, int64_t r0, double T, int n_steps, int 
   double2* seg = nullptr;    // recomputed states of one segment after its checkpoint (c - 1)
   double2* cur = nullptr;    // running forward state
   double2* lam = nullptr;    // lambda_k
-  double2* lamp = nullptr;   // lambda_{k+1}
   double *Ct = nullptr, *Cn = nullptr, *part = nullptr, *dA = nullptr;
   qk_status st = krylov_create(H, k->m, QK_C128, k->reorth, k->al, &kb);
   if (st != QK_OK) {
@@ -389,7 +410,6 @@ qk_status grad_return_prob(qk_krylov* k, int64_t r0, double T, int n_steps, int 
   if (e == hipSuccess && c > 1) e = dev_alloc(k->al, (void**)&seg, vbytes * (size_t)(c - 1));
   if (e == hipSuccess) e = dev_alloc(k->al, (void**)&cur, vbytes);
   if (e == hipSuccess) e = dev_alloc(k->al, (void**)&lam, vbytes);
-  if (e == hipSuccess) e = dev_alloc(k->al, (void**)&lamp, vbytes);
   if (e == hipSuccess) e = dev_alloc(k->al, (void**)&Ct, sizeof(double) * 2 * kGradMaxM * kGradMaxM);
   if (e == hipSuccess) e = dev_alloc(k->al, (void**)&Cn, sizeof(double) * 2 * kGradMaxM * kGradMaxM * kGaussNodes);
   if (e == hipSuccess) e = dev_alloc(k->al, (void**)&part, sizeof(double) * (size_t)G * kGradQ);
@@ -426,7 +446,7 @@ qk_status grad_return_prob(qk_krylov* k, int64_t r0, double T, int n_steps, int 
   for (int t = 0; t < n_steps && st == QK_OK; ++t) {
     // with kept bases the step builds its basis directly in the bank
     if (keep) k->d_U = (char*)ubank + (size_t)t * ubytes;
-    st = launch_krylov_step(k, cur, dt, s, true);
+    st = launch_krylov_step(k, cur, dt, s);
     k->d_U = u_home;
     if (st == QK_OK && keep) {
       e = hipMemcpyAsync(cbank + (size_t)t * cdoubles, k->d_coef, sizeof(double) * cdoubles, hipMemcpyDeviceToDevice,
@@ -462,7 +482,7 @@ qk_status grad_return_prob(qk_krylov* k, int64_t r0, double T, int n_steps, int 
       for (int u = t0 + 1; u <= t && st == QK_OK; ++u) {
         e = hipMemcpyAsync(state_at(u), state_at(u - 1), vbytes, hipMemcpyDeviceToDevice, s);
         chk("segment copy");
-        if (st == QK_OK) st = launch_krylov_step(k, state_at(u), dt, s, true);
+        if (st == QK_OK) st = launch_krylov_step(k, state_at(u), dt, s);
       }
       if (st != QK_OK) break;
     }
@@ -470,12 +490,12 @@ qk_status grad_return_prob(qk_krylov* k, int64_t r0, double T, int n_steps, int 
     // stored state (which is left unchanged)
     const double2* Uf = keep ? (const double2*)((char*)ubank + (size_t)t * ubytes) : (const double2*)k->d_U;
     const KState fwt = keep ? kstate_at(k, cbank + (size_t)t * cdoubles, ibank + 2 * (size_t)t) : fw;
-    if (!keep) st = launch_krylov_step(k, state_at(t), dt, s, false);
+    if (!keep) st = launch_krylov_step(k, state_at(t), dt, s, StepUpTo::basis);
     if (st != QK_OK) break;
-    // lambda_t = exp(+iH dt) lambda_{t+1}; lamp keeps lambda_{t+1}
-    e = hipMemcpyAsync(lamp, lam, vbytes, hipMemcpyDeviceToDevice, s);
-    chk("costate copy");
-    if (st == QK_OK) st = launch_krylov_step(kb, lam, -dt, s, true);
+    // lambda_t = exp(+iH dt) lambda_{t+1}: the costate's basis and
+    // combination weights; the contraction reads lambda_{t+1} and the basis
+    // and replaces lambda_{t+1} by the combination
+    st = launch_krylov_step(kb, lam, -dt, s, StepUpTo::weights);
     if (st != QK_OK) break;
     hipLaunchKernelGGL(k_grad_nodes, dim3(kGaussNodes), dim3(64), 0, s, fwt, bw, dt, gr, Cn);
     chk("k_grad_nodes");
@@ -485,12 +505,12 @@ qk_status grad_return_prob(qk_krylov* k, int64_t r0, double T, int n_steps, int 
     if (st != QK_OK) break;
     if (H->basis->wide)
       hipLaunchKernelGGL(k_grad_contract<uint64_t>, dim3(G), dim3(256), 0, s, (const uint64_t*)H->basis->d_states,
-                         niter, L, (const double2*)state_at(t), Uf, (const double2*)lamp,
-                         (const double2*)kb->d_U, (size_t)k->ustride, lr0, lnn, pe, fwt, bw, Ct, part);
+                         niter, L, (const double2*)state_at(t), Uf, lam, (const double2*)kb->d_U,
+                         (size_t)k->ustride, lr0, lnn, pe, fwt, bw, Ct, part);
     else
       hipLaunchKernelGGL(k_grad_contract<uint32_t>, dim3(G), dim3(256), 0, s, (const uint32_t*)H->basis->d_states,
-                         niter, L, (const double2*)state_at(t), Uf, (const double2*)lamp,
-                         (const double2*)kb->d_U, (size_t)k->ustride, lr0, lnn, pe, fwt, bw, Ct, part);
+                         niter, L, (const double2*)state_at(t), Uf, lam, (const double2*)kb->d_U,
+                         (size_t)k->ustride, lr0, lnn, pe, fwt, bw, Ct, part);
     chk("k_grad_contract");
     if (st != QK_OK) break;
     hipLaunchKernelGGL(k_grad_accum, dim3(1), dim3(kAccThreads), 0, s, part, G, L, dA);
@@ -511,7 +531,6 @@ qk_status grad_return_prob(qk_krylov* k, int64_t r0, double T, int n_steps, int 
   dev_free(k->al, seg);
   dev_free(k->al, cur);
   dev_free(k->al, lam);
-  dev_free(k->al, lamp);
   dev_free(k->al, Ct);
   dev_free(k->al, Cn);
   dev_free(k->al, part);

@@ -563,7 +563,7 @@ static void launch_combine(typename Cx<T>::V* psi, const typename Cx<T>::V* U, u
 }
 
 template <typename T>
-static qk_status krylov_step_t(qk_krylov* k, void* psi_v, double dt, hipStream_t s, bool combine,
+static qk_status krylov_step_t(qk_krylov* k, void* psi_v, double dt, hipStream_t s, StepUpTo upto,
                                const AdaptiveStep* ad = nullptr) {
   using V = typename Cx<T>::V;
   const qk_ham* H = k->H;
@@ -682,7 +682,7 @@ static qk_status krylov_step_t(qk_krylov* k, void* psi_v, double dt, hipStream_t
     }
     QK_MARK(QK_KERNEL_LANCZOS_UPDATE, false);
   }
-  if (!combine) return QK_OK;   // only the Krylov basis and coefficients were asked for
+  if (upto == StepUpTo::basis) return QK_OK;   // only the Krylov basis and coefficients were asked for
   QK_MARK(QK_KERNEL_SMALL_EXPM, true);
   if (ad) {
     hipLaunchKernelGGL(k_step_size, dim3(B), dim3(64), 0, s, st, m, B, ad->tau_max, ad->tol, pB, GB);
@@ -692,6 +692,7 @@ static qk_status krylov_step_t(qk_krylov* k, void* psi_v, double dt, hipStream_t
                      pB, GB);
   QK_HIP(hipGetLastError());
   QK_MARK(QK_KERNEL_SMALL_EXPM, false);
+  if (upto == StepUpTo::weights) return QK_OK;
   QK_MARK(QK_KERNEL_COMBINE, true);
   if (k->d_Z) {
     qk_status cs = launch_split_combine(H, k->dtype, psi, U, st, s);
@@ -748,15 +749,15 @@ qk_status profile_collect(qk_krylov* k) {
   return QK_OK;
 }
 
-qk_status launch_krylov_step(qk_krylov* k, void* psi, double dt, hipStream_t s, bool combine) {
-  if (k->dtype == QK_C128) return krylov_step_t<double>(k, psi, dt, s, combine);
-  return krylov_step_t<float>(k, psi, dt, s, combine);
+qk_status launch_krylov_step(qk_krylov* k, void* psi, double dt, hipStream_t s, StepUpTo upto) {
+  if (k->dtype == QK_C128) return krylov_step_t<double>(k, psi, dt, s, upto);
+  return krylov_step_t<float>(k, psi, dt, s, upto);
 }
 
 qk_status launch_krylov_adaptive_step(qk_krylov* k, void* psi, double tau_max, double tol, hipStream_t s) {
   const AdaptiveStep ad{tau_max, tol};
-  if (k->dtype == QK_C128) return krylov_step_t<double>(k, psi, tau_max, s, true, &ad);
-  return krylov_step_t<float>(k, psi, tau_max, s, true, &ad);
+  if (k->dtype == QK_C128) return krylov_step_t<double>(k, psi, tau_max, s, StepUpTo::combination, &ad);
+  return krylov_step_t<float>(k, psi, tau_max, s, StepUpTo::combination, &ad);
 }
 
 qk_status launch_return_prob(const qk_basis* b, int64_t r0, const void* psi0, const void* psi, int dtype, int B,
