@@ -411,7 +411,20 @@ def aux_timings(qk, torch, L, fields1, b, csr_L, h):
         t0 = time.perf_counter()
         F, dF = qk.qk_grad_return_prob(kg, rg, T, n)
         sec = time.perf_counter() - t0
+        # the forward step of the same workspace (launch shape as created)
+        psi = torch.zeros(qk.qk_basis_dim(bg), dtype=torch.complex128, device="cuda")
+        psi[rg] = 1.0
+        qk.qk_krylov_expm_step(kg, psi, T / n)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(3):
+            qk.qk_krylov_expm_step(kg, psi, T / n)
+        torch.cuda.synchronize()
+        fwd = (time.perf_counter() - t1) / 3
+        del psi
         out[f"gradient_L{Lg}"] = dict(T=T, steps=n, m=30, seconds=round(sec, 4), ms_per_step=round(1e3 * sec / n, 3),
+                                       forward_ms_per_step=round(1e3 * fwd, 3),
+                                       forward_steps_per_gradient_step=round(sec / n / fwd, 3),
                                        F=round(F, 12), max_abs_dFdh=round(float(max(abs(dF))), 9))
         kg.close()
         Hg.close()

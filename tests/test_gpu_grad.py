@@ -26,16 +26,23 @@ def _ws(L, pbc, h, phi, jz=1.0, m=24):
     return b, H, qk.qk_krylov_create(H, m), hf
 
 
-@pytest.mark.parametrize("L,pbc,h,jz,T,n_steps", [
-    (8, True, 1.0, 1.0, 2.0, 20),
-    (10, False, 2.0, 1.0, 3.0, 30),
-    (12, True, 3.0, 0.5, 5.0, 50),
-    (12, False, 0.0, 1.0, 1.0, 7),
+@pytest.mark.parametrize("L,pbc,h,jz,T,n_steps,m", [
+    (8, True, 1.0, 1.0, 2.0, 20, 24),
+    (10, False, 2.0, 1.0, 3.0, 30, 24),
+    (12, True, 3.0, 0.5, 5.0, 50, 24),
+    (12, False, 0.0, 1.0, 1.0, 7, 24),
+    # Lanczos breakdown in every step (D = 20 and 6 < m): the unused basis
+    # slots of both workspaces must not enter the contraction
+    (6, True, 1.5, 1.0, 2.0, 10, 24),
+    (4, False, 1.0, 1.0, 1.0, 5, 30),
+    # a Krylov dimension that is no multiple of the four basis vectors per
+    # load group or the eight per M-block
+    (10, True, 2.0, 1.0, 0.5, 25, 11),
 ])
-def test_gradient_vs_daleckii_krein(L, pbc, h, jz, T, n_steps):
-    b, H, k, hf = _ws(L, pbc, h, 0.3, jz=jz)
+def test_gradient_vs_daleckii_krein(L, pbc, h, jz, T, n_steps, m):
+    b, H, k, hf = _ws(L, pbc, h, 0.3, jz=jz, m=m)
     r0 = neel_row(L)
-    say("grad vs DK", L, pbc, h, jz, T, n_steps)
+    say("grad vs DK", L, pbc, h, jz, T, n_steps, m)
     F, g = qk.qk_grad_return_prob(k, r0, T, n_steps)
     F_ref, g_ref = OG.dF_dh(L, L // 2, pbc, 1.0, jz, hf, r0, T)
     assert abs(F - F_ref) < 1e-10
