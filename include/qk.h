@@ -405,20 +405,26 @@ void qk_batch_destroy(qk_batch* b);
  * derivative dF/dh_i with respect to every on-site field h_i of Eq. (1),
  * i = 1..L (dFdh_host[i-1]), by the adjoint method: n_steps Krylov steps of
  * dt = T / n_steps forward with every state kept as a checkpoint, then the
- * costate lambda(s) = exp(+iH(T-s)) e_r0 propagated backward by Krylov steps
- * of -dt; inside each step the time integral of <lambda|Z_i|psi> is taken
- * between the two Krylov bases by Gauss-Legendre quadrature of the projected
- * propagators.  When n_steps Krylov bases of the workspace (n_steps * m
- * vectors) and n_steps + 1 states fit in 80 % of the free device memory, the
- * forward pass keeps every basis with its coefficients and every state for
- * the duration of the call, and the backward pass uses them directly;
+ * costate lambda(s) = exp(+iH(T-s)) e_r0 backward; inside each step the time
+ * integral of <lambda|Z_i|psi> is taken between the two Krylov bases by
+ * Gauss-Legendre quadrature of the projected propagators.  H and e_r0 are
+ * real, so the costate is the conjugated forward state, lambda(s) =
+ * conj(psi(T - s)), and the costate's Krylov step from lambda_{k+1} has the
+ * conjugated basis and the tridiagonal matrix of the forward step from
+ * psi_{n_steps-1-k}: no costate is propagated.  When n_steps Krylov bases of
+ * the workspace (n_steps * m vectors) and n_steps + 1 states fit in 80 % of
+ * the free device memory, the forward pass keeps every basis with its
+ * coefficients and every state for the duration of the call, and the
+ * backward pass uses them directly (one Krylov step per time step in all);
  * ckpt_every is then not used.  Otherwise (or with the environment
  * variable QK_GRAD_KEEP=0) the forward states are kept every ckpt_every
  * (>= 1) steps, the backward sweep recomputes the states of one segment from
- * its checkpoint (one extra forward pass in total) and rebuilds each basis
- * from its state; both ways give identical results.  The call also holds
- * up to n_steps / ckpt_every + ckpt_every + 2 state vectors plus one more
- * workspace, allocated for its duration.  Uses the workspace's Hamiltonian,
+ * its checkpoint (one extra forward pass in total), rebuilds each basis from
+ * its state, and takes the mirrored forward steps again from e_r0 in a
+ * second workspace; both ways give identical results.  The call also holds
+ * up to n_steps / ckpt_every + ckpt_every + 3 state vectors plus, without
+ * kept bases, one more workspace, allocated for its duration.  Uses the
+ * workspace's Hamiltonian,
  * Krylov dimension and launch shape.  Requires dtype QK_C128, batch 1 and
  * m <= 32 (else QK_EUNSUPPORTED).  Synchronous; F_host and dFdh_host are host
  * pointers.

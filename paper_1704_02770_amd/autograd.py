@@ -4,8 +4,8 @@ F(T) (Sec. 4) as a differentiable function of the on-site fields of Eq. (1).
 forward propagates e_r0 to T with the workspace's Krylov steps and returns
 F(T) = |psi(T)[r0]|^2; nothing else is computed unless a gradient is asked
 for.  backward runs the adjoint sweep (qk_grad_return_prob: forward states
-kept as checkpoints, the costate propagated backward, the in-step
-contractions) and scales dF/dh by the incoming gradient.  Both set the
+kept as checkpoints, the costate taken backward as the conjugated forward
+states, the in-step contractions) and scales dF/dh by the incoming gradient.  Both set the
 workspace Hamiltonian's fields to the given ones for their duration and
 restore the previous fields afterwards, so other users of the Hamiltonian
 see no change.  All computation happens in the library's kernels.

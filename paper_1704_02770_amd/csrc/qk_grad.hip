@@ -5,12 +5,12 @@
 // H depends on h_i through h_i Z_i, Z_i = diag(bit_i - 1/2), so
 //     dA/dh_i = -i * integral_0^T <lambda(s)| Z_i |psi(s)> ds,
 //     lambda(s) = exp(+iH(T-s)) psi0,
-// and dF/dh_i = 2 Re(conj(A) dA/dh_i).  With time steps t_k = k dt:
+// and dF/dh_i = 2 Re(conj(A) dA/dh_i).  With K time steps t_k = k dt:
 //   * the forward pass stores psi_k (checkpoints);
 //   * the costate runs backward, lambda_K = psi0 and lambda_k =
 //     exp(+iH dt) lambda_{k+1}, i.e. a Krylov step with time step -dt;
 //   * inside step k, psi(t_k + tau) = V p(tau) with p(tau) = exp(-i tau T) ||psi_k|| e_1
-//     (the Krylov basis V of psi_k, rebuilt from the checkpoint) and
+//     (the Krylov basis V of psi_k) and
 //     lambda(t_k + tau) = W q(tau) with q(tau) = exp(+i (dt - tau) T') ||lambda_{k+1}|| e_1
 //     (the basis W of the backward step), so
 //         integral over the step of <lambda|Z_i|psi>
@@ -20,9 +20,18 @@
 //     the m-dimensional propagators (an entire function of tau, so the rule
 //     converges to rounding error), and the row sum is one pass over the two
 //     Krylov bases.
+// H is real and psi0 = e_r0 is real, so time reversal gives the costate as
+// the conjugated forward state: lambda(s) = conj(psi(T - s)), and with the
+// Krylov scheme lambda_{k+1} = conj(psi_{K-1-k}) step by step (a Lanczos run on
+// conj(u) with a real H produces the conjugated vectors and the same alpha,
+// beta).  The backward step's basis and matrix are therefore those of the
+// forward step from psi_{K-1-k}: W = conj(V'), T' = T_{K-1-k}, and
+// conj(W_rc) = V'_rc.  The backward sweep reads the forward bases of the
+// steps k and K-1-k instead of propagating the costate.
 #include <cmath>
 #include <cstdlib>
 #include <new>
+#include <utility>
 #include <vector>
 
 #include "qk_device.h"
@@ -114,11 +123,10 @@ k_grad_coeffs(KState fw, KState bw, const double* __restrict__ Cn, double* __res
   Ct[2 * e + 1] = sc * ci;
 }
 
-// Per row r: s_r = sum_c conj(u'_c[r]) t_c[r], t = C~ u[r] (u_0 = psi_k,
-// u'_0 = lambda_{k+1}, further vectors from the workspace slots), and the
-// costate's step: lambda_k[r] = sum_c g_c u'_c[r] with the weights g of its
-// small exponential, written over lambda_{k+1} (each position is read and
-// written by the same lane group, so the costate basis is read once).  t = C~ U
+// Per row r: s_r = sum_c v'_c[r] t_c[r], t = C~ u[r], where u is the forward
+// basis of step k (u_0 = psi_k) and v' that of the mirrored step K-1-k
+// (v'_0 = psi_{K-1-k}), i.e. the conjugated costate basis, further vectors
+// from the workspace slots.  t = C~ U
 // over all rows is a dense product (m x m times m x rows), done on the FP64
 // matrix cores in its real form: the complex C~ becomes the 2m x 2m real
 // matrix R with R[2c][2d] = R[2c+1][2d+1] = Re C~_cd, R[2c][2d+1] = -Im C~_cd,
@@ -134,9 +142,9 @@ k_grad_coeffs(KState fw, KState bw, const double* __restrict__ Cn, double* __res
 //   * register v of lane (q, n) of the MFMA's output holds output row
 //     4v + q at position n, so R's rows are ordered to make output row 4v + q
 //     of M-block b the component v % 2 of t_c, c = 8b + 2q + v / 2: the lane
-//     holds t_c for c = 8b + 2q and c + 1 (re, im, re, im), loads u'_c for
-//     those c and forms its shares of s_n and of lambda_k[n]; the four
-//     quarters' shares are added across lanes.
+//     holds t_c for c = 8b + 2q and c + 1 (re, im, re, im), loads v'_c for
+//     those c and forms its share of s_n; the four quarters' shares are added
+//     across lanes.
 // Lane i then adds s_n over the tile's positions whose state has bit i set,
 // every lane the total; per block the four waves' sums are added in wave
 // order into 2(L_max + 1) partial sums.
@@ -179,7 +187,7 @@ __device__ __forceinline__ S gc_ld(const S* p) {
 template <typename S>
 __global__ void __launch_bounds__(256, 4)
 k_grad_contract(const S* __restrict__ states, uint64_t niter, int L, const double2* __restrict__ psi_k,
-                const double2* __restrict__ Uf, double2* __restrict__ lam, const double2* __restrict__ Ub,
+                const double2* __restrict__ Uf, const double2* __restrict__ vm0, const double2* __restrict__ Ub,
                 size_t stride, const uint32_t* __restrict__ line_r0, const uint8_t* __restrict__ line_n, int pe,
                 KState fw, KState bw, const double* __restrict__ Ct, double* __restrict__ part) {
   // niter positions of the workspace vectors (stride elements each): rows of
@@ -187,7 +195,6 @@ k_grad_contract(const S* __restrict__ states, uint64_t niter, int L, const doubl
   // whose row comes from their line's entry (unused padding is skipped)
   __shared__ double Af[kGcFrag];                // [M-block][K-step][lane]
   __shared__ double red[kGcWaves][kGradQ];
-  __shared__ double2 gw[kGradMaxM];             // the costate's combination weights
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   // R in fragment order: lane l of (b, k) holds the R entry of output row
   // i = l % 16 (component (i / 4) % 2 of t_c, c = 8b + 2(i % 4) + i / 8) and
@@ -201,9 +208,6 @@ k_grad_contract(const S* __restrict__ states, uint64_t niter, int L, const doubl
   }
   const int muf = fw.mused[0] < kGradMaxM ? fw.mused[0] : kGradMaxM;
   const int mub = bw.mused[0] < kGradMaxM ? bw.mused[0] : kGradMaxM;
-  // as the plain combination: a failed or empty costate step leaves lambda as it is
-  const bool comb = bw.status[0] == QK_OK && bw.mused[0] > 0;
-  if (tid < kGradMaxM) gw[tid] = tid < mub ? make_double2(bw.gre[tid], bw.gim[tid]) : make_double2(0.0, 0.0);
   __syncthreads();
   const int q = lane >> 4, n = lane & 15;
   // row and validity of position p
@@ -247,7 +251,7 @@ k_grad_contract(const S* __restrict__ states, uint64_t niter, int L, const doubl
     for (int h = 0; h < 2 * kGcMb; ++h) {
       const int c = 8 * (h >> 1) + 2 * q + (h & 1);
       const bool on = valid && c < mub;
-      w[h] = gc_ld(!on ? psi_k : (c == 0 ? lam + rv : Ub + (lw + (size_t)(8 * (h >> 1) + (h & 1) - 1) * stride)));
+      w[h] = gc_ld(!on ? psi_k : (c == 0 ? vm0 + rv : Ub + (lw + (size_t)(8 * (h >> 1) + (h & 1) - 1) * stride)));
       if (!on) w[h] = zero;
     }
     S st = gc_ld(states + rv);
@@ -264,31 +268,20 @@ k_grad_contract(const S* __restrict__ states, uint64_t niter, int L, const doubl
         acc[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, u[s].y, acc[b], 0, 0, 0);
       }
     }
-    double sr = 0.0, si = 0.0, lr = 0.0, li = 0.0;
+    double sr = 0.0, si = 0.0;
 #pragma unroll
     for (int b = 0; b < kGcMb; ++b) {
-      const double2 w0 = w[2 * b], w1 = w[2 * b + 1];   // conj(u'_c) t_c
-      sr += w0.x * acc[b][0] + w0.y * acc[b][1];
-      si += w0.x * acc[b][1] - w0.y * acc[b][0];
-      sr += w1.x * acc[b][2] + w1.y * acc[b][3];
-      si += w1.x * acc[b][3] - w1.y * acc[b][2];
-      const double2 g0 = gw[8 * b + 2 * q], g1 = gw[8 * b + 2 * q + 1];   // g_c u'_c
-      lr += g0.x * w0.x - g0.y * w0.y;
-      li += g0.x * w0.y + g0.y * w0.x;
-      lr += g1.x * w1.x - g1.y * w1.y;
-      li += g1.x * w1.y + g1.y * w1.x;
+      const double2 w0 = w[2 * b], w1 = w[2 * b + 1];   // v'_c t_c
+      sr += w0.x * acc[b][0] - w0.y * acc[b][1];
+      si += w0.x * acc[b][1] + w0.y * acc[b][0];
+      sr += w1.x * acc[b][2] - w1.y * acc[b][3];
+      si += w1.x * acc[b][3] + w1.y * acc[b][2];
     }
     // (q0 + q1) + (q2 + q3): every quarter ends with the same bits
     sr += __shfl_xor(sr, 16);
     si += __shfl_xor(si, 16);
-    lr += __shfl_xor(lr, 16);
-    li += __shfl_xor(li, 16);
     sr += __shfl_xor(sr, 32);
     si += __shfl_xor(si, 32);
-    lr += __shfl_xor(lr, 32);
-    li += __shfl_xor(li, 32);
-    // lambda_{k+1}[r] was loaded by quarter 0 (c = 0), which now writes lambda_k[r]
-    if (comb && valid && q == 0) lam[r] = make_double2(lr, li);
 #pragma unroll
     for (int j = 0; j < kGcN; ++j) {
       const double sj = gc_readlane(sr, j), tj = gc_readlane(si, j);
@@ -389,40 +382,49 @@ qk_status grad_return_prob(qk_krylov* k, int64_t r0, double T, int n_steps, int 
   // kept bases need every state psi_t as a checkpoint
   const int c = keep ? 1 : (ckpt_every < 1 ? 1 : (ckpt_every > n_steps ? n_steps : ckpt_every));
   const int nck = n_steps / c + 1;   // checkpoints psi_0, psi_c, psi_2c, ...
-  qk_krylov* kb = nullptr;   // workspace of the backward steps
+  // Without kept bases a second workspace takes the mirrored forward steps
+  // (psi_0, psi_1, ... while the backward sweep goes down from K-1), with the
+  // launch shape of the first, so that its states and bases have the bits of
+  // the forward pass.
+  qk_krylov* kb = nullptr;   // workspace of the mirrored steps
   double2* ck = nullptr;     // checkpoints
   double2* seg = nullptr;    // recomputed states of one segment after its checkpoint (c - 1)
   double2* cur = nullptr;    // running forward state
-  double2* lam = nullptr;    // lambda_k
+  double2* mir = nullptr;    // psi_{K-1-t} of the mirrored steps
+  double2* mnext = nullptr;  // the state after it
   double *Ct = nullptr, *Cn = nullptr, *part = nullptr, *dA = nullptr;
-  qk_status st = krylov_create(H, k->m, QK_C128, k->reorth, k->al, &kb);
+  qk_status st = keep ? QK_OK : krylov_create(H, k->m, QK_C128, k->reorth, k->al, &kb);
   if (st != QK_OK) {
     dev_free(k->al, ubank);
     dev_free(k->al, cbank);
     dev_free(k->al, ibank);
     return st;
   }
-  kb->threads = k->threads;
-  kb->blocks_per_cu = k->blocks_per_cu;
-  kb->blocked_wgs = k->blocked_wgs;
-  kb->grid = k->grid;
+  if (kb) {
+    kb->threads = k->threads;
+    kb->blocks_per_cu = k->blocks_per_cu;
+    kb->blocked_wgs = k->blocked_wgs;
+    kb->grid = k->grid;
+  }
   hipError_t e = dev_alloc(k->al, (void**)&ck, vbytes * (size_t)nck);
   if (e == hipSuccess && c > 1) e = dev_alloc(k->al, (void**)&seg, vbytes * (size_t)(c - 1));
   if (e == hipSuccess) e = dev_alloc(k->al, (void**)&cur, vbytes);
-  if (e == hipSuccess) e = dev_alloc(k->al, (void**)&lam, vbytes);
+  if (e == hipSuccess && !keep) e = dev_alloc(k->al, (void**)&mir, vbytes);
+  if (e == hipSuccess && !keep) e = dev_alloc(k->al, (void**)&mnext, vbytes);
   if (e == hipSuccess) e = dev_alloc(k->al, (void**)&Ct, sizeof(double) * 2 * kGradMaxM * kGradMaxM);
   if (e == hipSuccess) e = dev_alloc(k->al, (void**)&Cn, sizeof(double) * 2 * kGradMaxM * kGradMaxM * kGaussNodes);
   if (e == hipSuccess) e = dev_alloc(k->al, (void**)&part, sizeof(double) * (size_t)G * kGradQ);
   if (e == hipSuccess) e = dev_alloc(k->al, (void**)&dA, sizeof(double) * 2 * L);
   if (e == hipSuccess) e = hipMemsetAsync(dA, 0, sizeof(double) * 2 * L, s);
-  const KState fw = make_kstate(k), bw = make_kstate(kb);
+  const KState fw = make_kstate(k);
+  const KState bw = kb ? make_kstate(kb) : fw;
   // the workspaces' vectors in the padded layout of the two-pass split: the
   // contraction walks that layout and finds each element's row in its line
   const uint32_t* lr0 = nullptr;
   const uint8_t* lnn = nullptr;
   int pe = 1;
   uint64_t niter = D;
-  if (st == QK_OK && (k->d_Z != nullptr) != (kb->d_Z != nullptr)) {
+  if (st == QK_OK && kb && (k->d_Z != nullptr) != (kb->d_Z != nullptr)) {
     set_error("forward and backward workspaces differ in layout");
     st = QK_EUNSUPPORTED;
   }
@@ -470,9 +472,9 @@ qk_status grad_return_prob(qk_krylov* k, int64_t r0, double T, int n_steps, int 
     const int j = t / c, o = t - j * c;
     return o == 0 ? ck + (size_t)j * D : seg + (size_t)(o - 1) * D;
   };
-  // backward pass of the costate
-  if (st == QK_OK) {
-    hipLaunchKernelGGL(k_basis_vector, dim3((D + 255) / 256), dim3(256), 0, s, lam, D, (uint32_t)r0);
+  // backward sweep; the mirrored steps start again from psi_0
+  if (st == QK_OK && !keep) {
+    hipLaunchKernelGGL(k_basis_vector, dim3((D + 255) / 256), dim3(256), 0, s, mir, D, (uint32_t)r0);
     chk("k_basis_vector");
   }
   for (int t = n_steps - 1; t >= 0 && st == QK_OK; --t) {
@@ -492,29 +494,38 @@ qk_status grad_return_prob(qk_krylov* k, int64_t r0, double T, int n_steps, int 
     const KState fwt = keep ? kstate_at(k, cbank + (size_t)t * cdoubles, ibank + 2 * (size_t)t) : fw;
     if (!keep) st = launch_krylov_step(k, state_at(t), dt, s, StepUpTo::basis);
     if (st != QK_OK) break;
-    // lambda_t = exp(+iH dt) lambda_{t+1}: the costate's basis and
-    // combination weights; the contraction reads lambda_{t+1} and the basis
-    // and replaces lambda_{t+1} by the combination
-    st = launch_krylov_step(kb, lam, -dt, s, StepUpTo::weights);
-    if (st != QK_OK) break;
-    hipLaunchKernelGGL(k_grad_nodes, dim3(kGaussNodes), dim3(64), 0, s, fwt, bw, dt, gr, Cn);
+    // the costate's step from lambda_{t+1} = conj(psi_{K-1-t}): the forward
+    // step of the mirrored index, kept from the forward pass or taken now by
+    // the second workspace from the mirrored state (which advances to the next)
+    const int tm = n_steps - 1 - t;
+    const double2* vm0 = keep ? ck + (size_t)tm * D : mir;
+    const double2* Ub = keep ? (const double2*)((char*)ubank + (size_t)tm * ubytes) : (const double2*)kb->d_U;
+    const KState bwt = keep ? kstate_at(k, cbank + (size_t)tm * cdoubles, ibank + 2 * (size_t)tm) : bw;
+    if (!keep) {
+      e = hipMemcpyAsync(mnext, mir, vbytes, hipMemcpyDeviceToDevice, s);
+      chk("mirrored state copy");
+      if (st == QK_OK) st = launch_krylov_step(kb, mnext, dt, s);
+      if (st != QK_OK) break;
+    }
+    hipLaunchKernelGGL(k_grad_nodes, dim3(kGaussNodes), dim3(64), 0, s, fwt, bwt, dt, gr, Cn);
     chk("k_grad_nodes");
     if (st != QK_OK) break;
-    hipLaunchKernelGGL(k_grad_coeffs, dim3(1), dim3(kGradMaxM * kGradMaxM), 0, s, fwt, bw, (const double*)Cn, Ct);
+    hipLaunchKernelGGL(k_grad_coeffs, dim3(1), dim3(kGradMaxM * kGradMaxM), 0, s, fwt, bwt, (const double*)Cn, Ct);
     chk("k_grad_coeffs");
     if (st != QK_OK) break;
     if (H->basis->wide)
       hipLaunchKernelGGL(k_grad_contract<uint64_t>, dim3(G), dim3(256), 0, s, (const uint64_t*)H->basis->d_states,
-                         niter, L, (const double2*)state_at(t), Uf, lam, (const double2*)kb->d_U,
-                         (size_t)k->ustride, lr0, lnn, pe, fwt, bw, Ct, part);
+                         niter, L, (const double2*)state_at(t), Uf, vm0, Ub, (size_t)k->ustride, lr0, lnn, pe, fwt,
+                         bwt, Ct, part);
     else
       hipLaunchKernelGGL(k_grad_contract<uint32_t>, dim3(G), dim3(256), 0, s, (const uint32_t*)H->basis->d_states,
-                         niter, L, (const double2*)state_at(t), Uf, lam, (const double2*)kb->d_U,
-                         (size_t)k->ustride, lr0, lnn, pe, fwt, bw, Ct, part);
+                         niter, L, (const double2*)state_at(t), Uf, vm0, Ub, (size_t)k->ustride, lr0, lnn, pe, fwt,
+                         bwt, Ct, part);
     chk("k_grad_contract");
     if (st != QK_OK) break;
     hipLaunchKernelGGL(k_grad_accum, dim3(1), dim3(kAccThreads), 0, s, part, G, L, dA);
     chk("k_grad_accum");
+    if (!keep) std::swap(mir, mnext);
   }
   std::vector<double> dAh(2 * L);
   if (st == QK_OK) {
@@ -530,7 +541,8 @@ qk_status grad_return_prob(qk_krylov* k, int64_t r0, double T, int n_steps, int 
   dev_free(k->al, ck);
   dev_free(k->al, seg);
   dev_free(k->al, cur);
-  dev_free(k->al, lam);
+  dev_free(k->al, mir);
+  dev_free(k->al, mnext);
   dev_free(k->al, Ct);
   dev_free(k->al, Cn);
   dev_free(k->al, part);

@@ -204,10 +204,9 @@ qk_status launch_split_apply(const qk_ham* H, const void* x, void* y, int dtype,
 // qk_krylov_create with the device memory of the workspace from `al`
 qk_status krylov_create(const qk_ham* H, int32_t m, int32_t dtype, int32_t reorth, const qk_allocator& al,
                         qk_krylov** out);
-// How far one Krylov step goes: the basis and Lanczos coefficients only, also
-// the small exponential's combination weights (the caller combines), or the
-// whole step with psi replaced by the combination.
-enum class StepUpTo { basis, weights, combination };
+// How far one Krylov step goes: the basis and Lanczos coefficients only, or
+// the whole step with psi replaced by the combination.
+enum class StepUpTo { basis, combination };
 qk_status launch_krylov_step(qk_krylov* k, void* psi, double dt, hipStream_t s,
                              StepUpTo upto = StepUpTo::combination);
 // One step of at most tau_max whose length the device chooses from the error

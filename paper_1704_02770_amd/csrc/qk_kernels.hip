@@ -692,7 +692,6 @@ static qk_status krylov_step_t(qk_krylov* k, void* psi_v, double dt, hipStream_t
                      pB, GB);
   QK_HIP(hipGetLastError());
   QK_MARK(QK_KERNEL_SMALL_EXPM, false);
-  if (upto == StepUpTo::weights) return QK_OK;
   QK_MARK(QK_KERNEL_COMBINE, true);
   if (k->d_Z) {
     qk_status cs = launch_split_combine(H, k->dtype, psi, U, st, s);
