@@ -38,6 +38,10 @@ def _ws(L, pbc, h, phi, jz=1.0, m=24):
     # a Krylov dimension that is no multiple of the four basis vectors per
     # load group or the eight per M-block
     (10, True, 2.0, 1.0, 0.5, 25, 11),
+    # one step (the mirrored step of the backward sweep is the step itself)
+    # and two (each step mirrors the other)
+    (8, True, 1.0, 1.0, 0.1, 1, 24),
+    (10, False, 1.5, 1.0, 0.2, 2, 24),
 ])
 def test_gradient_vs_daleckii_krein(L, pbc, h, jz, T, n_steps, m):
     b, H, k, hf = _ws(L, pbc, h, 0.3, jz=jz, m=m)
