@@ -4,7 +4,8 @@ propagation and against the free-fermion closed form at all 200 output times
 to t = 100; the L=28 and L=30 chains against the free-fermion closed
 form (zz coupling 0, same kernels); and, where no exact reference exists
 (L=28/30 with zz coupling), short-time amplitudes against the Taylor series
-of the oracle's H, the invariants and the FP64/FP32 agreement; the 8-phase
+of the oracle's H, the invariants (with the time-reversal amplitude
+identity) and the FP64/FP32 agreement; the 8-phase
 complex64 form at L=28 against the oracle's rows and single-phase runs."""
 import math
 import os
@@ -144,6 +145,37 @@ def test_l28_benchmark_workload_invariants():
     err = np.max(np.abs(P32 - P64))
     say("  complex64 vs complex128 max |dP| =", err)
     assert err < 1e-5
+
+
+@pytest.mark.parametrize("dtype,tol", [(torch.complex128, 1e-12), (torch.complex64, 1e-6)])
+def test_l28_amplitude_doubling(dtype, tol):
+    # H of Eq. (1) and the Neel state are real, so time reversal gives
+    # conj(psi(t)) = exp(+iHt) psi0 and <psi0|psi(2t)> = sum_r psi_r(t)^2: the
+    # amplitude after 20 steps of 0.1 against the one formed from the state
+    # after 10, at full size in the benchmark's configuration (L = 28 ring,
+    # h = 1.5, zz coupling 1, m = 30).  It holds for any real symmetric H, so
+    # it pins the propagation (steps composing to exp(-2iHt)), not H; the sum
+    # is taken on the test side in complex128.
+    L = 28
+    b = qk.qk_basis_build(L, L // 2)
+    hf = OM.fields(L, 1.5, BETA_GOLDEN, PHI)
+    H = qk.qk_ham_create(b, 1.0, 1.0, True, hf)
+    k = qk.qk_krylov_create(H, 30, dtype)
+    r0 = _neel_row(b, L)
+    psi = torch.zeros(qk.qk_basis_dim(b), dtype=dtype, device="cuda")
+    psi[r0] = 1.0
+    say("L28 amplitude doubling", dtype)
+    for _ in range(10):
+        qk.qk_krylov_expm_step(k, psi, 0.1)
+    p64 = psi.to(torch.complex128)
+    A2 = complex((p64 * p64).sum().item())
+    del p64
+    for _ in range(10):
+        qk.qk_krylov_expm_step(k, psi, 0.1)
+    A = complex(psi[r0].item())
+    say("  A(2) =", A, "sum psi(1)^2 =", A2)
+    assert abs(A) > 1e-3   # P(2) is of order 1e-2 here
+    assert abs(A - A2) < tol
 
 
 def _evolve_adaptive(b, H, L, times, m, tol, dtype=torch.complex128):
