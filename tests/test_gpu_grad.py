@@ -120,6 +120,45 @@ def test_kept_bases_equal_rebuilt_blocked_path(monkeypatch):
     assert Fk == Fr and np.array_equal(gk, gr)
 
 
+def test_gradient_at_full_size_l28():
+    # the benchmark's chain (L = 28 ring, h = 1.5, m = 30, dt = 0.1, Neel
+    # state), 5 steps with kept bases, where no exact reference exists: the
+    # uniform-field sum rule (the total magnetisation is conserved, so a
+    # uniform shift of the fields leaves F unchanged), F against plain forward
+    # steps, and dF/dh_i for two sites against central differences of the
+    # forward steps' F (step 1e-4: truncation about 1e-10, rounding 1e-12)
+    L, T, n = 28, 0.5, 5
+    b = qk.qk_basis_build(L, L // 2)
+    hf = OM.fields(L, 1.5, BETA_GOLDEN, 0.7)
+    H = qk.qk_ham_create(b, 1.0, 1.0, True, hf)
+    k = qk.qk_krylov_create(H, 30)
+    r0 = neel_row(L)
+    D = qk.qk_basis_dim(b)
+    say("grad L=28")
+    F, g = qk.qk_grad_return_prob(k, r0, T, n)
+    scale = float(np.max(np.abs(g)))
+    assert scale > 1e-4
+    assert abs(float(np.sum(g))) < 1e-9 * scale
+
+    def forward_F(h):
+        qk.qk_ham_set_fields(H, h)
+        psi = torch.zeros(D, dtype=torch.complex128, device="cuda")
+        psi[r0] = 1.0
+        for _ in range(n):
+            qk.qk_krylov_expm_step(k, psi, T / n)
+        return abs(complex(psi[r0].item())) ** 2
+
+    assert abs(forward_F(hf) - F) < 1e-14
+    eps = 1e-4
+    for i in (0, 13):
+        e = np.zeros(L)
+        e[i] = eps
+        fd = (forward_F(hf + e) - forward_F(hf - e)) / (2 * eps)
+        say("  site", i, "adjoint", g[i], "central difference", fd)
+        assert abs(g[i] - fd) < 1e-6 * scale
+    qk.qk_ham_set_fields(H, hf)
+
+
 def test_autograd_wrapper():
     # forward computes F only, backward the adjoint; the Hamiltonian's own
     # fields are restored after each
